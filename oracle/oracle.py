@@ -1,0 +1,114 @@
+"""ctypes wrapper of the C oracle (``xdrop_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg.  The product library never imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "xdrop_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+NEG = -(1 << 63)
+
+PAIR_FIELDS = ["score", "left_score", "right_score", "seed_score",
+               "a_begin", "a_end", "b_begin", "b_end",
+               "left_cells", "right_cells",
+               "left_bi", "left_bj", "right_bi", "right_bj", "status"]
+PAIR_DTYPE = np.dtype([(f, np.int64) for f in PAIR_FIELDS])
+
+
+class _Ext(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("best", "bi", "bj", "cells", "ndiag", "wmax")]
+
+
+class _Trace(ctypes.Structure):
+    _fields_ = [("cap", ctypes.c_int64), ("n", ctypes.c_int64)] + [
+        (f, ctypes.POINTER(ctypes.c_int64)) for f in ("lo", "hi", "la", "lb", "best", "vmax")]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, -O3, no intrinsics, no threads)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O3", "-march=native", "-std=c11", "-Wall",
+                               "-shared", "-fPIC", "-o", tmp, SRC])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB)
+        i64, p = ctypes.c_int64, ctypes.c_void_p
+        L.ox_extend.argtypes = [p, i64, p, i64, i64, i64, i64, i64,
+                                ctypes.POINTER(_Ext), ctypes.POINTER(_Trace)]
+        L.ox_extend.restype = ctypes.c_int
+        L.ox_pair.argtypes = [p, i64, p, i64, i64, i64, i64, i64, i64, i64, i64, p]
+        L.ox_pair.restype = ctypes.c_int
+        L.ox_batch.argtypes = [p, p, p, p, p, p, p, p, p, i64, i64, i64, i64, i64, p]
+        L.ox_batch.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _ptr(arr: np.ndarray):
+    return arr.ctypes.data_as(ctypes.c_void_p)
+
+
+def extend(a, b, match=1, mismatch=-1, gap=-1, x=10, trace: bool = False):
+    """One extension of a against b (codes 0..3).  Returns a dict."""
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    b = np.ascontiguousarray(b, dtype=np.uint8)
+    out = _Ext()
+    tr = None
+    bufs = None
+    if trace:
+        cap = len(a) + len(b) + 1
+        bufs = {f: np.zeros(cap, np.int64) for f in ("lo", "hi", "la", "lb", "best", "vmax")}
+        tr = _Trace(cap, 0, *[bufs[f].ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+                              for f in ("lo", "hi", "la", "lb", "best", "vmax")])
+    rc = lib().ox_extend(_ptr(a), len(a), _ptr(b), len(b), match, mismatch, gap, x,
+                         ctypes.byref(out), ctypes.byref(tr) if tr is not None else None)
+    if rc:
+        raise ValueError("ox_extend rejected its arguments")
+    res = {f: int(getattr(out, f)) for f in ("best", "bi", "bj", "cells", "ndiag", "wmax")}
+    if trace:
+        res["trace"] = {f: v[: tr.n].copy() for f, v in bufs.items()}
+    return res
+
+
+def pair(a, b, a_seed, b_seed, k=17, match=1, mismatch=-1, gap=-1, x=10) -> dict:
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    b = np.ascontiguousarray(b, dtype=np.uint8)
+    out = np.zeros(1, PAIR_DTYPE)
+    lib().ox_pair(_ptr(a), len(a), _ptr(b), len(b), a_seed, b_seed, k,
+                  match, mismatch, gap, x, _ptr(out))
+    return {f: int(out[f][0]) for f in PAIR_FIELDS}
+
+
+def batch(bt, return_time: bool = False):
+    """Oracle results for a generator batch, as a structured array."""
+    n = bt.n
+    out = np.zeros(n, PAIR_DTYPE)
+    arr = lambda v, dt: np.ascontiguousarray(v, dtype=dt)
+    a = arr(bt.a, np.uint8) if len(bt.a) else np.zeros(1, np.uint8)
+    b = arr(bt.b, np.uint8) if len(bt.b) else np.zeros(1, np.uint8)
+    keep = [arr(bt.a_off, np.int64), arr(bt.a_len, np.int64), arr(bt.b_off, np.int64),
+            arr(bt.b_len, np.int64), arr(bt.a_seed, np.int64), arr(bt.b_seed, np.int64),
+            arr(bt.x, np.int32)]
+    m, mm, g = bt.scores
+    secs = lib().ox_batch(_ptr(a), _ptr(b), *[_ptr(v) for v in keep], n, bt.k, m, mm, g,
+                          _ptr(out))
+    return (out, secs) if return_time else out

@@ -1,0 +1,304 @@
+"""Pins of the C oracle against facts fixed outside it (CPU only).
+
+Each test names what it pins:
+  P1  brute force: with X beyond the whole score range nothing is pruned, so
+      the result is the full-DP best cell (recurrence, tie-break, cell count).
+  P2  an independent full-matrix X-drop (pure Python, -inf as -math.inf,
+      ranges found by scanning the matrix) on exhaustive and random tiny
+      inputs (pruning rule, trimming, range rule, termination).
+  P3  identical reads score len * match at (len, len).
+  P4  closed form for reads with no common base: best 0 at the origin,
+      2X + 1 anti-diagonals and X^2 + 4X + 2 cells (derived by hand).
+  P5  one substitution at p: best max(p, L-2) at the first anti-diagonal.
+  P6  swapping the reads keeps score and cells.
+  P7  scaling all scores and X by c scales the score, keeps ends and cells.
+  P8  per-anti-diagonal invariants on the trace.
+  P9  0 <= best(X) <= full-DP best; large X gives the full DP.
+  P10 X below -gap: anti-diagonal 1 dies, result 0 at the origin.
+  P11 the two runs for X' < X agree up to the first anti-diagonal holding a
+      cell in [best - X, best - X'); a stored counterexample shows that the
+      final score is not monotone in X.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import brute
+from oracle import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+X_INF = 1 << 29
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+def ext(a, b, sc=(1, -1, -1), x=10, trace=False):
+    return O.extend(np.array(a, np.uint8), np.array(b, np.uint8), *sc, x=x, trace=trace)
+
+
+SCORE_SETS = [(1, -1, -1), (2, -3, -2), (1, -2, -1), (3, -1, -2), (1, 0, -1), (5, -4, -3)]
+
+
+# --------------------------------------------------------------------- P1
+@pytest.mark.parametrize("sc", SCORE_SETS)
+def test_p1_xinf_equals_full_dp(sc):
+    r = rng(1)
+    for _ in range(120):
+        m, n = int(r.integers(0, 11)), int(r.integers(0, 11))
+        alpha = int(r.integers(1, 5))
+        a = r.integers(0, alpha, m)
+        b = r.integers(0, alpha, n)
+        got = ext(a, b, sc, X_INF)
+        ref = brute.full_dp(list(a), list(b), *sc)
+        assert (got["best"], got["bi"], got["bj"], got["cells"]) == (
+            ref["best"], ref["bi"], ref["bj"], ref["cells"]), (a, b, sc)
+
+
+# --------------------------------------------------------------------- P2
+def _strings(alpha, max_len):
+    for L in range(max_len + 1):
+        for t in itertools.product(range(alpha), repeat=L):
+            yield list(t)
+
+
+def test_p2_full_matrix_exhaustive_binary():
+    strs = list(_strings(2, 4))
+    for a in strs:
+        for b in strs:
+            for x in range(0, 7):
+                got = ext(a, b, (1, -1, -1), x)
+                ref = brute.xdrop_full(a, b, 1, -1, -1, x)
+                assert (got["best"], got["bi"], got["bj"], got["cells"]) == (
+                    ref["best"], ref["bi"], ref["bj"], ref["cells"]), (a, b, x)
+
+
+@pytest.mark.parametrize("sc", SCORE_SETS)
+def test_p2_full_matrix_random(sc):
+    r = rng(2)
+    for _ in range(60):
+        m, n = int(r.integers(0, 31)), int(r.integers(0, 31))
+        a = list(r.integers(0, 4, m))
+        if r.random() < 0.6 and m:
+            # a noisy copy keeps the band alive for long
+            b = [c if r.random() > 0.2 else int(r.integers(0, 4)) for c in a]
+            b = b[: n] if n < len(b) else b
+        else:
+            b = list(r.integers(0, 4, n))
+        x = int(r.integers(0, 12))
+        got = ext(a, b, sc, x)
+        ref = brute.xdrop_full(a, b, *sc, x)
+        assert (got["best"], got["bi"], got["bj"], got["cells"]) == (
+            ref["best"], ref["bi"], ref["bj"], ref["cells"]), (a, b, sc, x)
+
+
+# --------------------------------------------------------------------- P3
+def test_p3_identical_reads():
+    r = rng(3)
+    for L in list(range(0, 12)) + [100, 1000, 5000]:
+        a = r.integers(0, 4, L)
+        for sc in [(1, -1, -1), (2, -3, -2), (4, -1, -3)]:
+            for x in (-sc[2], 5, 50):
+                got = ext(a, a, sc, x)
+                assert got["best"] == L * sc[0]
+                assert (got["bi"], got["bj"]) == (L, L)
+
+
+# --------------------------------------------------------------------- P4
+def test_p4_no_match_closed_form():
+    with open(os.path.join(GOLDEN, "no_match_cells.json")) as f:
+        golden = json.load(f)
+    r = rng(4)
+    for row in golden["rows"]:
+        x = row["X"]
+        for _ in range(3):
+            m = int(r.integers(x + 1, 3 * x + 3))
+            n = int(r.integers(x + 1, 3 * x + 3))
+            a = r.integers(0, 2, m)       # A, C only
+            b = r.integers(2, 4, n)       # G, T only
+            got = ext(a, b, (1, -1, -1), x)
+            assert got["best"] == 0 and (got["bi"], got["bj"]) == (0, 0)
+            assert got["cells"] == row["cells"] == x * x + 4 * x + 2
+            assert got["ndiag"] == 2 * x + 1
+
+
+# --------------------------------------------------------------------- P5
+def test_p5_single_substitution():
+    r = rng(5)
+    checked = 0
+    for _ in range(400):
+        L = int(r.integers(3, 40))
+        a = r.integers(0, 4, L)
+        p = int(r.integers(0, L))
+        b = a.copy()
+        b[p] = (b[p] + int(r.integers(1, 4))) % 4
+        best = max(p, L - 2)
+        end = (p, p) if p >= L - 2 else (L, L)
+        full = brute.full_dp(list(a), list(b))
+        if (full["best"], full["bi"], full["bj"]) != (best,) + end:
+            continue          # a repeat offers another path; the closed form does not apply
+        checked += 1
+        for x in (2, 3, 5, 10):
+            got = ext(a, b, (1, -1, -1), x)
+            assert (got["best"], got["bi"], got["bj"]) == (best,) + end, (a, b, p, x)
+    assert checked > 200
+
+
+# --------------------------------------------------------------------- P6
+def test_p6_swap_symmetry():
+    r = rng(6)
+    for _ in range(300):
+        m, n = int(r.integers(0, 60)), int(r.integers(0, 60))
+        a = r.integers(0, 4, m)
+        b = a[:n].copy() if r.random() < 0.5 and m >= n else r.integers(0, 4, n)
+        x = int(r.integers(0, 15))
+        sc = SCORE_SETS[int(r.integers(0, len(SCORE_SETS)))]
+        p, q = ext(a, b, sc, x), ext(b, a, sc, x)
+        assert p["best"] == q["best"] and p["cells"] == q["cells"]
+        assert p["bi"] + p["bj"] == q["bi"] + q["bj"]     # same anti-diagonal
+
+
+# --------------------------------------------------------------------- P7
+def test_p7_scale_invariance():
+    r = rng(7)
+    for _ in range(200):
+        m, n = int(r.integers(0, 80)), int(r.integers(0, 80))
+        a = r.integers(0, 4, m)
+        b = np.where(r.random(n) < 0.85, np.resize(a, n) if m else 0, r.integers(0, 4, n)) \
+            if m else r.integers(0, 4, n)
+        x = int(r.integers(0, 20))
+        c = int(r.integers(2, 5))
+        base = ext(a, b, (1, -1, -1), x)
+        sc = ext(a, b, (c, -c, -c), c * x)
+        assert sc["best"] == c * base["best"]
+        assert (sc["bi"], sc["bj"], sc["cells"]) == (base["bi"], base["bj"], base["cells"])
+
+
+# --------------------------------------------------------------------- P8
+def test_p8_trace_invariants():
+    r = rng(8)
+    for _ in range(60):
+        m, n = int(r.integers(1, 40)), int(r.integers(1, 40))
+        a = list(r.integers(0, 4, m))
+        b = [c if r.random() > 0.15 else int(r.integers(0, 4)) for c in a][:n]
+        if len(b) < n:
+            b += list(r.integers(0, 4, n - len(b)))
+        x = int(r.integers(1, 10))
+        got = ext(a, b, (1, -1, -1), x, trace=True)
+        tr = got["trace"]
+        full = brute.full_dp(a, b)["S"]
+        xm = brute.xdrop_full(a, b, 1, -1, -1, x)
+        S = xm["S"]
+        prev_best = 0
+        for e in range(len(tr["lo"])):
+            d = e + 1
+            assert tr["best"][e] >= prev_best                      # best never decreases
+            for i in range(tr["lo"][e], tr["hi"][e] + 1):
+                v = S[i][d - i]
+                if v != brute.NEG_INF:
+                    assert v >= prev_best - x                      # survivors within X
+                    assert v <= full[i][d - i]                     # never above the full DP
+            if e > 0 and tr["la"][e - 1] <= tr["lb"][e - 1]:
+                assert tr["hi"][e] - tr["lo"][e] <= tr["lb"][e - 1] - tr["la"][e - 1] + 1
+            prev_best = tr["best"][e]
+        assert got["cells"] == sum(tr["hi"] - tr["lo"] + 1)
+
+
+# --------------------------------------------------------------------- P9
+def test_p9_sandwich_and_saturation():
+    r = rng(9)
+    for _ in range(150):
+        m, n = int(r.integers(0, 25)), int(r.integers(0, 25))
+        a = r.integers(0, 4, m)
+        b = r.integers(0, 4, n)
+        full = brute.full_dp(list(a), list(b))
+        for x in (0, 1, 3, 8):
+            got = ext(a, b, (1, -1, -1), x)
+            assert 0 <= got["best"] <= full["best"]
+        sat = ext(a, b, (1, -1, -1), m + n + 2)
+        assert (sat["best"], sat["bi"], sat["bj"]) == (full["best"], full["bi"], full["bj"])
+
+
+# --------------------------------------------------------------------- P10
+def test_p10_tiny_x():
+    r = rng(10)
+    for _ in range(100):
+        m, n = int(r.integers(0, 30)), int(r.integers(0, 30))
+        a, b = r.integers(0, 4, m), r.integers(0, 4, n)
+        gap = -int(r.integers(1, 5))
+        for x in range(0, -gap):
+            got = ext(a, b, (1, -1, gap), x)
+            assert (got["best"], got["bi"], got["bj"]) == (0, 0, 0)
+            assert got["cells"] == int(m > 0) + int(n > 0)
+
+
+# --------------------------------------------------------------------- P11
+def test_p11_first_divergence_between_two_x():
+    r = rng(11)
+    diverged = 0
+    for _ in range(150):
+        m, n = int(r.integers(2, 25)), int(r.integers(2, 25))
+        a = list(r.integers(0, 4, m))
+        b = [c if r.random() > 0.3 else int(r.integers(0, 4)) for c in a][:n]
+        if len(b) < n:
+            b += list(r.integers(0, 4, n - len(b)))
+        x_hi = int(r.integers(2, 10))
+        x_lo = int(r.integers(0, x_hi))
+        big = brute.xdrop_full(a, b, 1, -1, -1, x_hi)
+        small = brute.xdrop_full(a, b, 1, -1, -1, x_lo)
+        best = 0
+        for (d, lo, hi), (d2, lo2, hi2) in zip(big["ranges"], small["ranges"]):
+            assert (d, lo, hi) == (d2, lo2, hi2)
+            diff = [i for i in range(lo, hi + 1) if big["S"][i][d - i] != small["S"][i][d - i]]
+            if diff:
+                diverged += 1
+                for i in diff:
+                    v = big["S"][i][d - i]
+                    assert small["S"][i][d - i] == brute.NEG_INF
+                    assert best - x_hi <= v < best - x_lo
+                break
+            row = [big["S"][i][d - i] for i in range(lo, hi + 1)
+                   if big["S"][i][d - i] != brute.NEG_INF]
+            if row:
+                best = max(best, max(row))
+    assert diverged > 10
+
+
+def test_p11_score_not_monotone_in_x_counterexample():
+    with open(os.path.join(GOLDEN, "x_non_monotone.json")) as f:
+        g = json.load(f)
+    a, b = g["a"], g["b"]
+    lo = ext(a, b, tuple(g["scores"]), g["x_small"])
+    hi = ext(a, b, tuple(g["scores"]), g["x_large"])
+    assert g["x_small"] < g["x_large"]
+    assert lo["best"] == g["best_small"] and hi["best"] == g["best_large"]
+    assert lo["best"] > hi["best"]
+    ref_lo = brute.xdrop_full(a, b, *g["scores"], g["x_small"])
+    ref_hi = brute.xdrop_full(a, b, *g["scores"], g["x_large"])
+    assert (ref_lo["best"], ref_hi["best"]) == (lo["best"], hi["best"])
+
+
+# ------------------------------------------------------------ pair level
+def test_pair_matches_bruteforce_seed_split():
+    from paper_2002_05200_amd import synth
+    bt = synth.random_cases(seed=12, n=60, len_lo=17, len_hi=60, x_choices=(0, 1, 2, 4, 7))
+    res = O.batch(bt)
+    for p in range(bt.n):
+        a, b = bt.pair(p)
+        ref = brute.seed_pair(list(a), list(b), int(bt.a_seed[p]), int(bt.b_seed[p]), bt.k,
+                              *bt.scores, int(bt.x[p]))
+        for f, v in ref.items():
+            assert int(res[f][p]) == v, (p, f)
+        assert res["status"][p] == 0
+        assert res["seed_score"][p] == bt.k * bt.scores[0]    # planted seeds are exact
+
+
+def test_pair_rejects_bad_seeds():
+    a = np.zeros(30, np.uint8)
+    for pa, pb, k in [(-1, 0, 17), (14, 0, 17), (0, 14, 17), (0, 0, -1)]:
+        r = O.pair(a, a, pa, pb, k=k)
+        assert r["status"] == 1
