@@ -1,0 +1,166 @@
+/*
+ * xdrop.h -- C ABI of libxdrop: batched X-drop seed extension of read pairs on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (LOGAN, arXiv 2002.05200):
+ *   - Each pair (A, B) carries an exact k-mer seed A[a_seed, a_seed+k) ~
+ *     B[b_seed, b_seed+k) and is split at it into a right extension of the
+ *     suffixes and a left extension of the reversed prefixes (Section IV-B).
+ *   - Each extension is the semi-global X-drop alignment of Section III-A:
+ *     anti-diagonal dynamic programming of the linear-gap recurrence from the
+ *     origin, a running best score, cells scoring below best - X set to -inf,
+ *     the -inf runs at both ends of each anti-diagonal trimmed, and the loop
+ *     ending when an anti-diagonal has no surviving cell (Algorithms 1 and 2).
+ *   - Readings where the paper is silent: best is updated once per
+ *     anti-diagonal and pruning compares strictly (< best - X) against best as
+ *     of the previous anti-diagonal; the next anti-diagonal spans
+ *     [first live, last live + 1] clipped to the matrix; the reported end is
+ *     the first anti-diagonal reaching the final best, smallest A index on it;
+ *     both directions start from best = 0; "cells" counts every computed cell.
+ *   - The pair score is left best + seed score + right best.
+ *
+ * Conventions:
+ *   - All integers little-endian.  All buffers are owned by the caller; the
+ *     library owns only its context's internal scratch.
+ *   - Sequences are 2-bit packed, A=0 C=1 G=2 T=3, 16 bases per uint32, base
+ *     g of an arena in bits [2*(g%16), 2*(g%16)+1] of word g/16 (see xd_pack).
+ *   - No C++ exception crosses this boundary.  Call-level problems return an
+ *     xd_status; problems with one pair set that pair's xd_result.status and
+ *     leave the other pairs unaffected.
+ *   - xd_last_error() returns a thread-local description of the last failure.
+ */
+#ifndef XDROP_H
+#define XDROP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    XD_OK = 0,
+    XD_EINVAL = 1,     /* bad argument (null pointer, bad score set, bad pair)       */
+    XD_ENOMEM = 2,     /* device or host allocation failed                           */
+    XD_EDEVICE = 3,    /* a HIP runtime call failed                                  */
+    XD_EBUSY = 4,      /* serving: no admission capacity right now                   */
+    XD_EOVERFLOW = 5,  /* pair: int32 score range could be exceeded (see xdrop_extend) */
+    XD_ECANCELED = 6,  /* serving: request canceled                                  */
+    XD_ENOTREADY = 7   /* serving: result not complete yet                           */
+} xd_status;
+
+/* Linear-gap scoring (Section III-A), signed and additive: a match adds
+ * `match`, a mismatch adds `mismatch`, a gap adds `gap`.  Supported:
+ * match >= mismatch, gap <= 0, mismatch - 2*gap in [-128, 127] and
+ * match - mismatch <= 255; xdrop_extend returns XD_EINVAL otherwise. */
+typedef struct {
+    int32_t match, mismatch, gap;
+} xd_scores;
+
+/* One seeded pair.  a_off / b_off are base offsets of the reads in the packed
+ * arenas; seeds are read-local.  x is the X-drop threshold, 0 <= x <= 2^29. */
+typedef struct {
+    uint64_t a_off, b_off;
+    uint32_t a_len, b_len;
+    uint32_t a_seed, b_seed;
+    uint32_t k;
+    int32_t x;
+} xd_pair; /* 40 bytes */
+
+/* Result of one pair.  Coordinates are read-local and half-open: the
+ * alignment spans A[a_begin, a_end) and B[b_begin, b_end). */
+typedef struct {
+    int32_t score, left_score, right_score, seed_score;
+    uint32_t a_begin, a_end, b_begin, b_end;
+    uint64_t left_cells, right_cells; /* computed cells of each extension */
+    int32_t status;                   /* xd_status of this pair            */
+    int32_t reserved;
+} xd_result; /* 56 bytes */
+
+/* Batch execution strategy (Section IV-B inter-sequence parallelism). */
+typedef enum {
+    XD_SCHED_AUTO = 0,       /* persistent queue, longest estimated job first */
+    XD_SCHED_PLAIN = 1,      /* one wavefront per job, grid = number of jobs  */
+    XD_SCHED_PERSISTENT = 2  /* persistent waves popping a device job queue   */
+} xd_sched;
+
+typedef struct {
+    int32_t sched;        /* xd_sched                                           */
+    int32_t min_tier;     /* 0 = automatic; else start every job at this lane
+                             width tier (cells per lane 2, 4, 8, 16, 32 for
+                             1..5; 6 = straight to the global-memory tier)      */
+    int32_t waves_per_cu; /* persistent grid: waves per compute unit (0 = auto) */
+    int32_t sort_jobs;    /* persistent: 1 = longest estimated job first        */
+    int32_t short_long_split; /* 0 = off; else jobs with m+n below this go to
+                                 the plain kernel, the rest to the queue        */
+    int32_t profile;      /* 1 = time every stage with HIP events (see
+                             xd_last_stats)                                     */
+    int32_t reserved[2];
+} xd_opts;
+
+/* Statistics of the last xdrop_extend on a context.  Tier t in 0..5 runs C =
+ * 2^t cells per lane (a window of 64*C diagonals); tier 6 keeps the band in
+ * global memory. */
+typedef struct {
+    uint64_t jobs[7];      /* jobs finished at each tier                        */
+    uint64_t cells[7];     /* cells computed by the jobs finished at each tier  */
+    uint64_t escalated[7]; /* jobs whose band outgrew the tier's window          */
+    float stage_ms[9];     /* plan, tiers 0..5, tier 6, combine (profile only)  */
+    int32_t profiled;      /* 1 when stage_ms is valid                          */
+} xd_stats;
+
+typedef struct xd_ctx xd_ctx;
+
+/* Host-side 2-bit packer.  Packs n ASCII bases (ACGT, upper or lower case)
+ * into words[0 .. (n+15)/16); unused high bits of the last word are zero.
+ * Returns XD_EINVAL (and packs nothing) if any character is not ACGT. */
+xd_status xd_pack(const char *ascii, size_t n, uint32_t *words);
+
+/* Same, from base codes 0..3 (one byte each) written at base offset
+ * base_off of an arena already holding whole words (read-modify-write of the
+ * words it touches).  Rejects codes > 3. */
+xd_status xd_pack_codes(const uint8_t *codes, size_t n, uint32_t *words,
+                        uint64_t base_off);
+
+/* Context on HIP device `device`: kernels, internal scratch (job lists, tier
+ * queues) grown on demand.  mem_budget caps the scratch (0 = no cap). */
+xd_status xd_ctx_create(int device, size_t mem_budget, xd_ctx **out);
+void xd_ctx_destroy(xd_ctx *ctx);
+
+/*
+ * Batched X-drop extension of n_pairs pairs, enqueued on `stream` (a
+ * hipStream_t; NULL = the default stream).  Asynchronous: d_out is valid after
+ * the stream is synchronised.
+ *   d_a, d_b      device arenas of a_words / b_words packed words;
+ *   d_pairs       device array of n_pairs xd_pair;
+ *   d_out         device array of n_pairs xd_result;
+ *   opts          NULL = automatic.
+ * Per pair: XD_EINVAL if a seed runs past its read, k > read length, x
+ * outside [0, 2^29] or a read runs past its arena; XD_EOVERFLOW if
+ * (a_len + b_len) * (|match| + |mismatch| + 2|gap|) + x >= 2^29.
+ * Returns XD_EINVAL for null pointers or an unsupported score set, XD_ENOMEM
+ * when scratch cannot be allocated, XD_EDEVICE when a launch fails.
+ */
+xd_status xdrop_extend(xd_ctx *ctx, const uint32_t *d_a, uint64_t a_words,
+                       const uint32_t *d_b, uint64_t b_words,
+                       const xd_pair *d_pairs, size_t n_pairs, xd_scores scores,
+                       xd_result *d_out, void *stream, const xd_opts *opts);
+
+/* Synchronous convenience: host arenas, pairs and results; copies in, runs
+ * xdrop_extend on an internal stream, copies out. */
+xd_status xdrop_extend_host(xd_ctx *ctx, const uint32_t *a, uint64_t a_words,
+                            const uint32_t *b, uint64_t b_words,
+                            const xd_pair *pairs, size_t n_pairs, xd_scores scores,
+                            xd_result *out, const xd_opts *opts);
+
+/* Statistics of the last xdrop_extend on this context (synchronises the
+ * context's device first). */
+xd_status xd_last_stats(xd_ctx *ctx, xd_stats *out);
+
+const char *xd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

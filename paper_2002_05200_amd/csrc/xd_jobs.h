@@ -1,0 +1,45 @@
+// xd_jobs.h -- job descriptors exchanged between the host planner and the
+// gfx950 kernels (library-internal; not part of the C ABI).
+#pragma once
+
+#include <stdint.h>
+
+namespace xd {
+
+constexpr int32_t kNeg = -(1 << 30);       // -inf of the band (never wins a max)
+constexpr int kWaveSlots = 64;             // lanes of a wavefront
+constexpr int kTiers = 6;                  // cells per lane 1, 2, 4, 8, 16, 32
+constexpr int kSpillTier = kTiers;         // unbounded global-memory band
+
+// One one-directional extension (Section IV-B seed split): a_i = A[a_start +
+// dir * (i - 1)], b_j = B[b_start + dir * (j - 1)], 1 <= i <= m, 1 <= j <= n.
+struct Job {
+  int64_t a_start;
+  int64_t b_start;
+  int32_t m, n;
+  int32_t x;
+  int32_t dir;   // +1: right extension (forward), -1: left extension (backward)
+};
+
+// Job status values (internal).
+enum : int32_t { kJobOk = 0, kJobWider = 100 };
+
+struct JobOut {
+  int32_t best, bi, bj, status;
+  uint64_t cells;
+};
+
+// Everything one launch needs besides the job list.  With g = gap,
+// base = mismatch - 2g and delta = match - mismatch, the diagonal term of the
+// gap-free form is W_{d-2} + base + (match ? delta : 0).
+struct Params {
+  const uint32_t *A;
+  const uint32_t *B;
+  int64_t a_words, b_words;
+  int32_t neg_gap;   // -gap: growth of the W-form thresholds per anti-diagonal
+  int32_t base;      // mismatch - 2 gap
+  int32_t delta;     // match - mismatch (>= 0)
+  int32_t pat;       // delta replicated into every 2-bit field (narrow form)
+};
+
+}  // namespace xd

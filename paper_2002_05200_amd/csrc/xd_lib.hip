@@ -1,0 +1,478 @@
+// xd_lib.hip -- libxdrop: batched X-drop seed extension on one MI355X.
+//
+// Launch sequence of one xdrop_extend call (all on the caller's stream):
+//   k_reset    clears the per-tier job counters
+//   k_plan     one thread per pair: validation, seed split into a left and a
+//              right job (Section IV-B), initial lane-width tier from X
+//   k_extend   per tier (cells per lane C = 1, 2, 4, 8, 16, 32): one wavefront
+//              per job; a job whose band outgrows its window is appended to
+//              the next tier's list and recomputed there
+//   k_spill    jobs wider than the widest register tier: band in global memory
+//   k_combine  one thread per pair: left + seed + right
+// Plain mode launches every tier with one wavefront per listed job; the
+// persistent mode launches a fixed grid whose waves pop jobs from a device
+// queue (Section IV-B inter-sequence parallelism, without relaunches).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "xdrop.h"
+#include "xd_extend.h"
+#include "xd_jobs.h"
+#include "xd_pairs.h"
+#include "xd_spill.h"
+
+namespace xd {
+
+constexpr int kBlock = 256;                 // 4 wavefronts, each its own job
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kLists = kTiers + 1;          // register tiers + spill tier
+
+// Device counters: [0, kLists) list lengths, [kLists, 2 kLists) queue heads.
+constexpr int kCounters = 2 * kLists;
+// Device statistics (uint64): jobs finished, cells of those jobs, escalations.
+constexpr int kStats = 3 * kLists;
+
+__global__ void k_reset(int32_t *counters, unsigned long long *stats) {
+  if (threadIdx.x < kCounters) counters[threadIdx.x] = 0;
+  if (threadIdx.x < kStats) stats[threadIdx.x] = 0;
+}
+
+__device__ __forceinline__ void record_done(unsigned long long *stats, int tier, uint64_t cells) {
+  atomicAdd(&stats[tier], 1ull);
+  atomicAdd(&stats[kLists + tier], (unsigned long long)cells);
+}
+
+__global__ void k_plan(const xd_pair *__restrict__ pairs, int64_t n_pairs, int64_t a_words,
+                       int64_t b_words, int32_t match, int32_t mismatch, int32_t gap,
+                       int32_t min_tier, Job *__restrict__ jobs,
+                       int32_t *__restrict__ pair_status, int32_t *__restrict__ lists,
+                       int32_t *__restrict__ counters, int64_t list_stride) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  Job l, r;
+  const int32_t st = plan_pair(pairs[p], a_words, b_words, match, mismatch, gap, &l, &r);
+  pair_status[p] = st;
+  jobs[2 * p] = l;
+  jobs[2 * p + 1] = r;
+  int tl = initial_tier(l), tr = initial_tier(r);
+  if (tl < min_tier) tl = min_tier;
+  if (tr < min_tier) tr = min_tier;
+  int32_t at = atomicAdd(&counters[tl], 1);
+  lists[tl * list_stride + at] = (int32_t)(2 * p);
+  at = atomicAdd(&counters[tr], 1);
+  lists[tr * list_stride + at] = (int32_t)(2 * p + 1);
+}
+
+// One job per wavefront.  Plain: wave w of the grid takes list[w].
+// Persistent (head != nullptr): waves pop list entries until none is left.
+template <int C, bool NARROW>
+__global__ __launch_bounds__(kBlock) void k_extend(const Job *__restrict__ jobs,
+                                                   const int32_t *__restrict__ list,
+                                                   const int32_t *__restrict__ count_ptr,
+                                                   int32_t *head, JobOut *__restrict__ outs,
+                                                   int32_t *__restrict__ next_list,
+                                                   int32_t *__restrict__ next_count,
+                                                   unsigned long long *stats, int tier,
+                                                   Params P) {
+  const int wave = uniform((int32_t)(threadIdx.x >> 6));
+  const int32_t count = *count_ptr;
+  int32_t w;
+  if (head == nullptr) {
+    w = (int32_t)blockIdx.x * kWavesPerBlock + wave;
+    if (w >= count) return;
+  } else {
+    int32_t got = 0;
+    if (lane_id() == 0) got = atomicAdd(head, 1);
+    w = uniform(got);
+  }
+  while (w < count) {
+    const int32_t j = list[w];
+    const Job job = jobs[j];
+    const JobOut o = extend_job<C, NARROW>(job, P);
+    if (lane_id() == 0) {
+      if (o.status == kJobWider) {
+        const int32_t at = atomicAdd(next_count, 1);
+        next_list[at] = j;
+        atomicAdd(&stats[2 * kLists + tier], 1ull);
+      } else {
+        outs[j] = o;
+        record_done(stats, tier, o.cells);
+      }
+    }
+    if (head == nullptr) break;
+    int32_t got = 0;
+    if (lane_id() == 0) got = atomicAdd(head, 1);
+    w = uniform(got);
+  }
+}
+
+__global__ void k_combine(const xd_pair *__restrict__ pairs, int64_t n_pairs,
+                          const int32_t *__restrict__ pair_status, const JobOut *__restrict__ outs,
+                          const uint32_t *__restrict__ A, const uint32_t *__restrict__ B,
+                          int32_t match, int32_t mismatch, xd_result *__restrict__ res) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  const xd_pair pr = pairs[p];
+  const int32_t st = pair_status[p];
+  int32_t seed = 0;
+  if (st == XD_OK) {
+    for (uint32_t t = 0; t < pr.k; ++t) {
+      const uint64_t ga = pr.a_off + pr.a_seed + t, gb = pr.b_off + pr.b_seed + t;
+      const uint32_t ca = (A[ga >> 4] >> (2 * (ga & 15))) & 3u;
+      const uint32_t cb = (B[gb >> 4] >> (2 * (gb & 15))) & 3u;
+      seed += (ca == cb) ? match : mismatch;
+    }
+  }
+  xd_result out;
+  combine_pair(pr, st, outs[2 * p], outs[2 * p + 1], seed, &out);
+  res[p] = out;
+}
+
+}  // namespace xd
+
+// ---------------------------------------------------------------------------
+// host runtime
+// ---------------------------------------------------------------------------
+using namespace xd;
+
+namespace {
+
+thread_local std::string g_err;
+
+xd_status fail(xd_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+#define XD_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return fail(XD_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_));   \
+  } while (0)
+
+struct Scratch {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct xd_ctx {
+  int device = 0;
+  size_t budget = 0;
+  int num_cu = 0;
+  Scratch scratch;
+  int64_t cap_pairs = 0;
+  // carved from scratch
+  Job *jobs = nullptr;
+  JobOut *outs = nullptr;
+  int32_t *pair_status = nullptr;
+  int32_t *lists = nullptr;      // kLists lists of 2 * cap_pairs entries
+  int32_t *counters = nullptr;   // kCounters
+  unsigned long long *stats = nullptr;  // kStats
+  uint32_t *dummy = nullptr;     // one zero word for empty arenas
+  hipEvent_t ev[10] = {};        // stage boundaries when profiling
+  bool have_events = false;
+  bool profiled = false;
+  SpillScratch spill;
+  hipStream_t own_stream = nullptr;
+  std::mutex mu;
+};
+
+namespace {
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+xd_status ensure_capacity(xd_ctx *c, int64_t n_pairs) {
+  if (n_pairs <= c->cap_pairs && c->scratch.ptr) return XD_OK;
+  int64_t cap = std::max<int64_t>(n_pairs, 1024);
+  if (c->cap_pairs > 0) cap = std::max<int64_t>(cap, c->cap_pairs * 3 / 2);
+  const int64_t nj = 2 * cap;
+  size_t off = 0;
+  const size_t o_jobs = off; off = align_up(off + sizeof(Job) * nj);
+  const size_t o_outs = off; off = align_up(off + sizeof(JobOut) * nj);
+  const size_t o_stat = off; off = align_up(off + sizeof(int32_t) * cap);
+  const size_t o_list = off; off = align_up(off + sizeof(int32_t) * nj * kLists);
+  const size_t o_cnt = off; off = align_up(off + sizeof(int32_t) * kCounters);
+  const size_t o_stats = off; off = align_up(off + sizeof(unsigned long long) * kStats);
+  const size_t o_dummy = off; off = align_up(off + 64);
+  if (c->budget && off > c->budget)
+    return fail(XD_ENOMEM, "scratch for " + std::to_string(n_pairs) + " pairs exceeds the budget");
+  if (c->scratch.ptr) {
+    XD_HIP(hipDeviceSynchronize());
+    XD_HIP(hipFree(c->scratch.ptr));
+    c->scratch.ptr = nullptr;
+  }
+  void *p = nullptr;
+  if (hipMalloc(&p, off) != hipSuccess) return fail(XD_ENOMEM, "hipMalloc of job scratch failed");
+  c->scratch.ptr = p;
+  c->scratch.bytes = off;
+  char *b = (char *)p;
+  c->jobs = (Job *)(b + o_jobs);
+  c->outs = (JobOut *)(b + o_outs);
+  c->pair_status = (int32_t *)(b + o_stat);
+  c->lists = (int32_t *)(b + o_list);
+  c->counters = (int32_t *)(b + o_cnt);
+  c->stats = (unsigned long long *)(b + o_stats);
+  c->dummy = (uint32_t *)(b + o_dummy);
+  XD_HIP(hipMemset(c->dummy, 0, 64));
+  c->cap_pairs = cap;
+  return XD_OK;
+}
+
+template <int C, bool NARROW>
+hipError_t launch_tier(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_cu,
+                       int64_t max_jobs, int tier, const Params &P) {
+  const int64_t stride = 2 * c->cap_pairs;
+  const int32_t *list = c->lists + tier * stride;
+  const int32_t *count = c->counters + tier;
+  int32_t *head = persistent ? c->counters + kLists + tier : nullptr;
+  int32_t *next_list = c->lists + (tier + 1) * stride;
+  int32_t *next_count = c->counters + tier + 1;
+  int64_t blocks;
+  if (persistent) {
+    blocks = ((int64_t)c->num_cu * waves_per_cu + kWavesPerBlock - 1) / kWavesPerBlock;
+  } else {
+    blocks = (max_jobs + kWavesPerBlock - 1) / kWavesPerBlock;
+  }
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL((k_extend<C, NARROW>), dim3((unsigned)blocks), dim3(kBlock), 0, s, c->jobs,
+                     list, count, head, c->outs, next_list, next_count, c->stats, tier, P);
+  return hipGetLastError();
+}
+
+template <bool NARROW>
+hipError_t launch_tiers(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_cu,
+                        int64_t nj, const Params &P, bool prof) {
+  // waves per CU suited to each tier's register footprint
+  const int wpc[kTiers] = {32, 32, 24, 16, 8, 4};
+  auto w = [&](int t) { return waves_per_cu > 0 ? waves_per_cu : wpc[t]; };
+  hipError_t e;
+  auto mark = [&](int i) { return prof ? hipEventRecord(c->ev[i], s) : hipSuccess; };
+  if ((e = launch_tier<1, NARROW>(c, s, persistent, w(0), nj, 0, P)) != hipSuccess) return e;
+  if ((e = mark(2)) != hipSuccess) return e;
+  if ((e = launch_tier<2, NARROW>(c, s, persistent, w(1), nj, 1, P)) != hipSuccess) return e;
+  if ((e = mark(3)) != hipSuccess) return e;
+  if ((e = launch_tier<4, NARROW>(c, s, persistent, w(2), nj, 2, P)) != hipSuccess) return e;
+  if ((e = mark(4)) != hipSuccess) return e;
+  if ((e = launch_tier<8, NARROW>(c, s, persistent, w(3), nj, 3, P)) != hipSuccess) return e;
+  if ((e = mark(5)) != hipSuccess) return e;
+  if ((e = launch_tier<16, NARROW>(c, s, persistent, w(4), nj, 4, P)) != hipSuccess) return e;
+  if ((e = mark(6)) != hipSuccess) return e;
+  if ((e = launch_tier<32, NARROW>(c, s, persistent, w(5), nj, 5, P)) != hipSuccess) return e;
+  return mark(7);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *xd_last_error(void) { return g_err.c_str(); }
+
+xd_status xd_pack(const char *ascii, size_t n, uint32_t *words) {
+  if ((!ascii && n) || (!words && n)) return fail(XD_EINVAL, "xd_pack: null pointer");
+  for (size_t g = 0; g < n; ++g) {
+    const char ch = ascii[g];
+    if (!(ch == 'A' || ch == 'C' || ch == 'G' || ch == 'T' || ch == 'a' || ch == 'c' ||
+          ch == 'g' || ch == 't'))
+      return fail(XD_EINVAL, "xd_pack: character " + std::to_string(g) + " is not ACGT");
+  }
+  const size_t nw = (n + 15) / 16;
+  for (size_t w = 0; w < nw; ++w) words[w] = 0;
+  for (size_t g = 0; g < n; ++g) {
+    uint32_t code;
+    switch (ascii[g]) {
+      case 'A': case 'a': code = 0; break;
+      case 'C': case 'c': code = 1; break;
+      case 'G': case 'g': code = 2; break;
+      default: code = 3; break;
+    }
+    words[g >> 4] |= code << (2 * (g & 15));
+  }
+  return XD_OK;
+}
+
+xd_status xd_pack_codes(const uint8_t *codes, size_t n, uint32_t *words, uint64_t base_off) {
+  if ((!codes && n) || (!words && n)) return fail(XD_EINVAL, "xd_pack_codes: null pointer");
+  for (size_t g = 0; g < n; ++g)
+    if (codes[g] > 3) return fail(XD_EINVAL, "xd_pack_codes: code " + std::to_string(g) + " > 3");
+  for (size_t g = 0; g < n; ++g) {
+    const uint64_t pos = base_off + g;
+    const uint32_t sh = 2 * (uint32_t)(pos & 15);
+    uint32_t &w = words[pos >> 4];
+    w = (w & ~(3u << sh)) | ((uint32_t)codes[g] << sh);
+  }
+  return XD_OK;
+}
+
+xd_status xd_ctx_create(int device, size_t mem_budget, xd_ctx **out) {
+  if (!out) return fail(XD_EINVAL, "xd_ctx_create: null out");
+  *out = nullptr;
+  int ndev = 0;
+  XD_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(XD_EINVAL, "xd_ctx_create: no such device");
+  XD_HIP(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  XD_HIP(hipGetDeviceProperties(&prop, device));
+  xd_ctx *c = new xd_ctx();
+  c->device = device;
+  c->budget = mem_budget;
+  c->num_cu = prop.multiProcessorCount;
+  *out = c;
+  return XD_OK;
+}
+
+void xd_ctx_destroy(xd_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  if (c->scratch.ptr) (void)hipFree(c->scratch.ptr);
+  spill_free(&c->spill);
+  if (c->have_events)
+    for (int i = 0; i < 10; ++i) (void)hipEventDestroy(c->ev[i]);
+  if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+  delete c;
+}
+
+xd_status xdrop_extend(xd_ctx *c, const uint32_t *d_a, uint64_t a_words, const uint32_t *d_b,
+                       uint64_t b_words, const xd_pair *d_pairs, size_t n_pairs,
+                       xd_scores sc, xd_result *d_out, void *stream, const xd_opts *opts) {
+  if (!c) return fail(XD_EINVAL, "xdrop_extend: null context");
+  if (n_pairs == 0) return XD_OK;
+  if (!d_pairs || !d_out) return fail(XD_EINVAL, "xdrop_extend: null pairs or results");
+  if ((!d_a && a_words) || (!d_b && b_words)) return fail(XD_EINVAL, "xdrop_extend: null arena");
+  if (n_pairs > (size_t(1) << 29)) return fail(XD_EINVAL, "xdrop_extend: too many pairs");
+  if (sc.match < sc.mismatch)
+    return fail(XD_EINVAL, "xdrop_extend: mismatch score above match score");
+  const int64_t base = (int64_t)sc.mismatch - 2 * (int64_t)sc.gap;
+  const int64_t delta = (int64_t)sc.match - (int64_t)sc.mismatch;
+  if (base < -128 || base > 127 || delta > 255 || sc.gap > 0 || sc.gap < -(1 << 20))
+    return fail(XD_EINVAL, "xdrop_extend: unsupported score set");
+  xd_opts o;
+  std::memset(&o, 0, sizeof(o));
+  if (opts) o = *opts;
+  if (o.min_tier < 0 || o.min_tier > kTiers)
+    return fail(XD_EINVAL, "xdrop_extend: min_tier out of range");
+
+  std::lock_guard<std::mutex> lock(c->mu);
+  XD_HIP(hipSetDevice(c->device));
+  xd_status st = ensure_capacity(c, (int64_t)n_pairs);
+  if (st != XD_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const bool persistent = (o.sched != XD_SCHED_PLAIN);
+  const int64_t nj = 2 * (int64_t)n_pairs;
+
+  Params P;
+  P.A = a_words ? d_a : c->dummy;
+  P.B = b_words ? d_b : c->dummy;
+  P.a_words = a_words ? (int64_t)a_words : 1;
+  P.b_words = b_words ? (int64_t)b_words : 1;
+  P.neg_gap = -sc.gap;
+  P.base = (int32_t)base;
+  P.delta = (int32_t)delta;
+  P.pat = (int32_t)(delta * 0x55555555u);
+  const bool narrow = delta <= 3;
+
+  const bool prof = o.profile != 0;
+  if (prof && !c->have_events) {
+    for (int i = 0; i < 10; ++i) XD_HIP(hipEventCreate(&c->ev[i]));
+    c->have_events = true;
+  }
+  c->profiled = prof;
+  if (prof) XD_HIP(hipEventRecord(c->ev[0], s));
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, c->counters, c->stats);
+  XD_HIP(hipGetLastError());
+  const int64_t stride = 2 * c->cap_pairs;
+  hipLaunchKernelGGL(k_plan, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s, d_pairs,
+                     (int64_t)n_pairs, (int64_t)P.a_words, (int64_t)P.b_words, sc.match,
+                     sc.mismatch, sc.gap, o.min_tier, c->jobs, c->pair_status, c->lists,
+                     c->counters, stride);
+  XD_HIP(hipGetLastError());
+  if (prof) XD_HIP(hipEventRecord(c->ev[1], s));
+  hipError_t e = narrow ? launch_tiers<true>(c, s, persistent, o.waves_per_cu, nj, P, prof)
+                        : launch_tiers<false>(c, s, persistent, o.waves_per_cu, nj, P, prof);
+  if (e != hipSuccess) return fail(XD_EDEVICE, std::string("k_extend: ") + hipGetErrorString(e));
+  st = spill_launch(&c->spill, s, c->jobs, c->lists + kTiers * stride, c->counters + kTiers,
+                    c->counters + kLists + kTiers, c->outs, c->stats, P);
+  if (st != XD_OK) return fail(st, "k_spill launch failed");
+  if (prof) XD_HIP(hipEventRecord(c->ev[8], s));
+  hipLaunchKernelGGL(k_combine, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s,
+                     d_pairs, (int64_t)n_pairs, c->pair_status, c->outs, P.A, P.B, sc.match,
+                     sc.mismatch, d_out);
+  XD_HIP(hipGetLastError());
+  if (prof) XD_HIP(hipEventRecord(c->ev[9], s));
+  return XD_OK;
+}
+
+xd_status xdrop_extend_host(xd_ctx *c, const uint32_t *a, uint64_t a_words, const uint32_t *b,
+                            uint64_t b_words, const xd_pair *pairs, size_t n_pairs,
+                            xd_scores sc, xd_result *out, const xd_opts *opts) {
+  if (!c) return fail(XD_EINVAL, "xdrop_extend_host: null context");
+  if (n_pairs == 0) return XD_OK;
+  if (!pairs || !out || (!a && a_words) || (!b && b_words))
+    return fail(XD_EINVAL, "xdrop_extend_host: null pointer");
+  XD_HIP(hipSetDevice(c->device));
+  if (!c->own_stream) XD_HIP(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+  hipStream_t s = c->own_stream;
+  void *da = nullptr, *db = nullptr, *dp = nullptr, *dr = nullptr;
+  auto cleanup = [&]() {
+    if (da) (void)hipFree(da);
+    if (db) (void)hipFree(db);
+    if (dp) (void)hipFree(dp);
+    if (dr) (void)hipFree(dr);
+  };
+  if (hipMalloc(&da, std::max<size_t>(a_words, 1) * 4) != hipSuccess ||
+      hipMalloc(&db, std::max<size_t>(b_words, 1) * 4) != hipSuccess ||
+      hipMalloc(&dp, n_pairs * sizeof(xd_pair)) != hipSuccess ||
+      hipMalloc(&dr, n_pairs * sizeof(xd_result)) != hipSuccess) {
+    cleanup();
+    return fail(XD_ENOMEM, "xdrop_extend_host: device allocation failed");
+  }
+  hipError_t e = hipSuccess;
+  if (a_words) e = hipMemcpyAsync(da, a, a_words * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && b_words) e = hipMemcpyAsync(db, b, b_words * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dp, pairs, n_pairs * sizeof(xd_pair), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(XD_EDEVICE, std::string("xdrop_extend_host copy-in: ") + hipGetErrorString(e));
+  }
+  xd_status st = xdrop_extend(c, (const uint32_t *)da, a_words, (const uint32_t *)db, b_words,
+                              (const xd_pair *)dp, n_pairs, sc, (xd_result *)dr, s, opts);
+  if (st == XD_OK) {
+    e = hipMemcpyAsync(out, dr, n_pairs * sizeof(xd_result), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = fail(XD_EDEVICE, std::string("xdrop_extend_host: ") + hipGetErrorString(e));
+  }
+  cleanup();
+  return st;
+}
+
+xd_status xd_last_stats(xd_ctx *c, xd_stats *out) {
+  if (!c || !out) return fail(XD_EINVAL, "xd_last_stats: null pointer");
+  std::memset(out, 0, sizeof(*out));
+  if (!c->stats) return XD_OK;
+  unsigned long long h[kStats];
+  XD_HIP(hipSetDevice(c->device));
+  XD_HIP(hipDeviceSynchronize());
+  XD_HIP(hipMemcpy(h, c->stats, sizeof(h), hipMemcpyDeviceToHost));
+  for (int t = 0; t < kLists; ++t) {
+    out->jobs[t] = h[t];
+    out->cells[t] = h[kLists + t];
+    out->escalated[t] = h[2 * kLists + t];
+  }
+  if (c->profiled) {
+    for (int i = 0; i < 9; ++i) XD_HIP(hipEventElapsedTime(&out->stage_ms[i], c->ev[i], c->ev[i + 1]));
+    out->profiled = 1;
+  }
+  return XD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,219 @@
+"""Thin ctypes binding of libxdrop (``include/xdrop.h``).
+
+Argument marshalling only: every step of the extension runs in the library's
+HIP kernels.  PyTorch provides device memory and streams.  The library must be
+built (``python -m paper_2002_05200_amd.build``); importing the binding never
+falls back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime libxdrop binds to)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libxdrop.so")
+
+XD_OK, XD_EINVAL, XD_ENOMEM, XD_EDEVICE, XD_EBUSY, XD_EOVERFLOW, XD_ECANCELED, XD_ENOTREADY = range(8)
+SCHED_AUTO, SCHED_PLAIN, SCHED_PERSISTENT = 0, 1, 2
+TIER_CELLS = (1, 2, 4, 8, 16, 32)
+
+PAIR_DTYPE = np.dtype([("a_off", "<u8"), ("b_off", "<u8"), ("a_len", "<u4"), ("b_len", "<u4"),
+                       ("a_seed", "<u4"), ("b_seed", "<u4"), ("k", "<u4"), ("x", "<i4")])
+RESULT_DTYPE = np.dtype([("score", "<i4"), ("left_score", "<i4"), ("right_score", "<i4"),
+                         ("seed_score", "<i4"), ("a_begin", "<u4"), ("a_end", "<u4"),
+                         ("b_begin", "<u4"), ("b_end", "<u4"), ("left_cells", "<u8"),
+                         ("right_cells", "<u8"), ("status", "<i4"), ("reserved", "<i4")])
+assert PAIR_DTYPE.itemsize == 40 and RESULT_DTYPE.itemsize == 56
+
+RESULT_FIELDS = ["score", "left_score", "right_score", "seed_score", "a_begin", "a_end",
+                 "b_begin", "b_end", "left_cells", "right_cells", "status"]
+
+
+class Scores(ctypes.Structure):
+    _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32), ("gap", ctypes.c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("sched", ctypes.c_int32), ("min_tier", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32), ("sort_jobs", ctypes.c_int32),
+                ("short_long_split", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("jobs", ctypes.c_uint64 * 7), ("cells", ctypes.c_uint64 * 7),
+                ("escalated", ctypes.c_uint64 * 7), ("stage_ms", ctypes.c_float * 9),
+                ("profiled", ctypes.c_int32)]
+
+
+class XdropError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libxdrop status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libxdrop.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2002_05200_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        p, u64, sz, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_int
+        L.xd_pack.argtypes = [ctypes.c_char_p, sz, p]
+        L.xd_pack.restype = i32
+        L.xd_pack_codes.argtypes = [p, sz, p, u64]
+        L.xd_pack_codes.restype = i32
+        L.xd_ctx_create.argtypes = [i32, sz, ctypes.POINTER(p)]
+        L.xd_ctx_create.restype = i32
+        L.xd_ctx_destroy.argtypes = [p]
+        L.xd_ctx_destroy.restype = None
+        L.xdrop_extend.argtypes = [p, p, u64, p, u64, p, sz, Scores, p, p, p]
+        L.xdrop_extend.restype = i32
+        L.xdrop_extend_host.argtypes = [p, p, u64, p, u64, p, sz, Scores, p, p]
+        L.xdrop_extend_host.restype = i32
+        L.xd_last_stats.argtypes = [p, ctypes.POINTER(Stats)]
+        L.xd_last_stats.restype = i32
+        L.xd_last_error.argtypes = []
+        L.xd_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().xd_last_error().decode(errors="replace")
+
+
+def _check(status: int):
+    if status != XD_OK:
+        raise XdropError(status, last_error())
+
+
+def pack_codes(codes: np.ndarray, pad_words: int = 0) -> np.ndarray:
+    """2-bit packs base codes 0..3 with the library's host packer."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    nw = (len(codes) + 15) // 16 + pad_words
+    words = np.zeros(max(nw, 1), dtype=np.uint32)
+    _check(lib().xd_pack_codes(codes.ctypes.data_as(ctypes.c_void_p), len(codes),
+                               words.ctypes.data_as(ctypes.c_void_p), 0))
+    return words
+
+
+def pack_ascii(text: bytes) -> np.ndarray:
+    words = np.zeros(max((len(text) + 15) // 16, 1), dtype=np.uint32)
+    _check(lib().xd_pack(text, len(text), words.ctypes.data_as(ctypes.c_void_p)))
+    return words
+
+
+def make_pairs(bt) -> np.ndarray:
+    """xd_pair records of a generator batch."""
+    pr = np.zeros(bt.n, PAIR_DTYPE)
+    pr["a_off"] = bt.a_off
+    pr["b_off"] = bt.b_off
+    pr["a_len"] = bt.a_len
+    pr["b_len"] = bt.b_len
+    pr["a_seed"] = bt.a_seed
+    pr["b_seed"] = bt.b_seed
+    pr["k"] = bt.k
+    pr["x"] = bt.x
+    return pr
+
+
+def _dev_bytes(arr: np.ndarray, device) -> torch.Tensor:
+    t = torch.from_numpy(np.ascontiguousarray(arr).view(np.uint8).reshape(-1))
+    return t.to(device, non_blocking=False)
+
+
+class DeviceBatch:
+    """A batch resident in device memory: packed arenas, pair records, results."""
+
+    def __init__(self, bt, device="cuda:0"):
+        self.n = bt.n
+        self.scores = tuple(bt.scores)
+        self.a_words = pack_codes(bt.a)
+        self.b_words = pack_codes(bt.b)
+        self.pairs = make_pairs(bt)
+        self.d_a = _dev_bytes(self.a_words, device)
+        self.d_b = _dev_bytes(self.b_words, device)
+        self.d_pairs = _dev_bytes(self.pairs, device)
+        self.d_out = torch.empty(max(self.n, 1) * RESULT_DTYPE.itemsize, dtype=torch.uint8,
+                                 device=device)
+
+    def results(self) -> np.ndarray:
+        raw = self.d_out[: self.n * RESULT_DTYPE.itemsize].cpu().numpy()
+        return raw.view(RESULT_DTYPE).copy()
+
+
+def make_opts(sched: int = SCHED_AUTO, min_tier: int = 0, waves_per_cu: int = 0,
+              sort_jobs: int = 1, short_long_split: int = 0, profile: int = 0) -> Opts:
+    o = Opts()
+    o.sched, o.min_tier, o.waves_per_cu = sched, min_tier, waves_per_cu
+    o.sort_jobs, o.short_long_split, o.profile = sort_jobs, short_long_split, profile
+    return o
+
+
+class Context:
+    """An xd_ctx on one device."""
+
+    def __init__(self, device: int = 0, mem_budget: int = 0):
+        torch.cuda.init()
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(lib().xd_ctx_create(device, mem_budget, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().xd_ctx_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def extend_device(self, db: DeviceBatch, stream: Optional[torch.cuda.Stream] = None,
+                      opts: Optional[Opts] = None, scores: Optional[Sequence[int]] = None):
+        """Enqueues xdrop_extend on ``stream`` (default: torch's current stream)."""
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        sc = Scores(*(scores if scores is not None else db.scores))
+        _check(lib().xdrop_extend(self.h, db.d_a.data_ptr(), len(db.a_words), db.d_b.data_ptr(),
+                                  len(db.b_words), db.d_pairs.data_ptr(), db.n, sc,
+                                  db.d_out.data_ptr(), ctypes.c_void_p(s.cuda_stream),
+                                  ctypes.byref(opts) if opts is not None else None))
+
+    def extend(self, bt, opts: Optional[Opts] = None, device: Optional[str] = None) -> np.ndarray:
+        """Synchronous convenience: upload, extend, download."""
+        db = DeviceBatch(bt, device or f"cuda:{self.device}")
+        self.extend_device(db, opts=opts)
+        torch.cuda.synchronize(self.device)
+        return db.results()
+
+    def extend_host(self, bt, opts: Optional[Opts] = None) -> np.ndarray:
+        """xdrop_extend_host: host arrays in, host results out."""
+        a, b, pr = pack_codes(bt.a), pack_codes(bt.b), make_pairs(bt)
+        out = np.zeros(bt.n, RESULT_DTYPE)
+        _check(lib().xdrop_extend_host(
+            self.h, a.ctypes.data_as(ctypes.c_void_p), len(a), b.ctypes.data_as(ctypes.c_void_p),
+            len(b), pr.ctypes.data_as(ctypes.c_void_p), bt.n, Scores(*bt.scores),
+            out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts) if opts is not None else None))
+        return out
+
+    def stats(self) -> dict:
+        """xd_last_stats: per-tier jobs / cells / escalations, stage times."""
+        st = Stats()
+        _check(lib().xd_last_stats(self.h, ctypes.byref(st)))
+        out = {"jobs": np.array(list(st.jobs), np.int64),
+               "cells": np.array(list(st.cells), np.int64),
+               "escalated": np.array(list(st.escalated), np.int64)}
+        if st.profiled:
+            out["stage_ms"] = np.array(list(st.stage_ms), np.float64)
+        return out

@@ -1,0 +1,101 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function the header declares, and its host-only entry points behave."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "xdrop.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2002_05200_amd import build
+    if not os.path.exists(build.LIB):
+        build.build(verbose=False)
+    from paper_2002_05200_amd import xdrop
+    return xdrop.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(xd[a-z_]*)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["xdrop_extend", "xdrop_extend_host", "xd_pack", "xd_pack_codes", "xd_ctx_create",
+              "xd_ctx_destroy", "xd_last_error", "xd_last_stats"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_single_hip_runtime_in_process(L):
+    maps = open("/proc/self/maps").read()
+    libs = {l.split()[-1] for l in maps.splitlines() if "libamdhip64" in l}
+    assert len(libs) == 1, libs
+
+
+def test_pack_ascii_matches_layout():
+    from paper_2002_05200_amd import synth, xdrop
+    r = np.random.default_rng(3)
+    for n in [0, 1, 15, 16, 17, 100, 1000]:
+        codes = r.integers(0, 4, n).astype(np.uint8)
+        text = synth.decode(codes)
+        w = xdrop.pack_ascii(text)
+        w2 = xdrop.pack_codes(codes)
+        assert np.array_equal(w, w2)
+        # base g in bits [2(g%16), 2(g%16)+1] of word g/16
+        for g in range(n):
+            assert (int(w[g // 16]) >> (2 * (g % 16))) & 3 == codes[g]
+        assert xdrop.pack_ascii(text.lower()).tolist() == w.tolist()
+
+
+def test_pack_rejects_non_acgt():
+    from paper_2002_05200_amd import xdrop
+    with pytest.raises(xdrop.XdropError) as e:
+        xdrop.pack_ascii(b"ACGTN")
+    assert e.value.status == xdrop.XD_EINVAL
+    assert "not ACGT" in xdrop.last_error()
+    with pytest.raises(xdrop.XdropError):
+        xdrop.pack_codes(np.array([0, 1, 4], np.uint8))
+
+
+def test_pack_codes_at_offset_preserves_neighbours(L):
+    words = np.full(4, 0xFFFFFFFF, dtype=np.uint32)
+    codes = np.array([0, 1, 2, 3, 0], np.uint8)
+    rc = L.xd_pack_codes(codes.ctypes.data_as(ctypes.c_void_p), len(codes),
+                         words.ctypes.data_as(ctypes.c_void_p), 14)
+    assert rc == 0
+    got = [(int(words[(14 + t) // 16]) >> (2 * ((14 + t) % 16))) & 3 for t in range(5)]
+    assert got == codes.tolist()
+    assert (int(words[0]) & 0x0FFFFFFF) == 0x0FFFFFFF      # bases 0..13 untouched
+    assert (int(words[1]) >> 6) == (0xFFFFFFFF >> 6)       # bases 19.. untouched
+
+
+def test_null_context_is_rejected_without_touching_a_device(L):
+    from paper_2002_05200_amd import xdrop
+    sc = xdrop.Scores(1, -1, -1)
+    rc = L.xdrop_extend(None, None, 0, None, 0, None, 1, sc, None, None, None)
+    assert rc == xdrop.XD_EINVAL
+    assert "null context" in xdrop.last_error()
+    assert L.xd_last_stats(None, None) == xdrop.XD_EINVAL
+    L.xd_ctx_destroy(None)
+
+
+def test_struct_layouts_match_header():
+    from paper_2002_05200_amd import xdrop
+    text = open(HEADER).read()
+    assert "/* 40 bytes */" in text and xdrop.PAIR_DTYPE.itemsize == 40
+    assert "/* 56 bytes */" in text and xdrop.RESULT_DTYPE.itemsize == 56
+    assert ctypes.sizeof(xdrop.Opts) == 32
+    assert ctypes.sizeof(xdrop.Stats) == 3 * 7 * 8 + 9 * 4 + 4

