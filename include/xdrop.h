@@ -96,7 +96,9 @@ typedef struct {
                                  the plain kernel, the rest to the queue        */
     int32_t profile;      /* 1 = time every stage with HIP events (see
                              xd_last_stats)                                     */
-    int32_t reserved[2];
+    int32_t impl;         /* 0 = hand-scheduled loops where available, 1 = the
+                             portable C loops only (same results; for testing)  */
+    int32_t reserved;
 } xd_opts;
 
 /* Statistics of the last xdrop_extend on a context.  Tier t in 0..5 runs C =

@@ -187,7 +187,7 @@ XD_FN bool step(Band<C> &bd, Scalars &st, int q, const JobView &jv, const Params
     const uint32_t width = (uint32_t)(st.hi - st.lo);
 #pragma unroll
     for (int r = 0; r < C; ++r) {
-      vbool lv = (v[r] >= st.thr) & le_u(s0 + (r - st.lo), width);
+      vbool lv = both(v[r] >= st.thr, le_u(s0 + (r - st.lo), width));
       cur[r] = select(lv, v[r], kNeg);
       lbits = lbits | bit_if(lv, r);
     }
@@ -334,6 +334,187 @@ XD_FN JobOut extend_job(const Job &job, const Params &P) {
   out.bi = st.bi;
   out.bj = st.bj;
   out.cells = st.cells + st.cells_blk;
+  return out;
+}
+
+
+// ---------------------------------------------------------------------------
+// One register per lane (64 diagonals).  The computed range, the survivors
+// and the window edges of an anti-diagonal are all 64-bit lane masks, so the
+// per-anti-diagonal bookkeeping is a handful of scalar instructions:
+//   survivors = ballot(v >= threshold) & range            (v_cmp, s_and)
+//   first/last survivor a = ff1, 63 - f with f = flbit      (s_ff1, s_flbit)
+//   next range = bits [a, 64-f] or [a-1, 63-f]            (s_bfm)
+// Matrix clipping is only compiled into the blocks that can reach the end of
+// either read; everywhere else the window lies inside the matrix.
+enum : int { kStepOn = 0, kStepDone = 1, kStepRecenter = 2 };
+
+struct W1 {
+  int32_t e, par;       // next anti-diagonal d = 2e + par
+  int32_t h;            // window base: lane s holds i = s + ceil(d/2) + h
+  uint64_t range;       // computed range of anti-diagonal d (lanes)
+  int32_t width;        // its size
+  int32_t lo, hi;       // range ends, valid when a recenter is pending
+  int32_t best, bi, bj;
+  int32_t bw, thr;      // W-form improvement and prune thresholds of d
+  uint32_t cells_blk;
+  uint64_t cells;
+};
+
+XD_FN uint64_t lane_bits(int lo, int width) {   // bits lo .. lo + width - 1, width < 64
+  return ((1ull << width) - 1ull) << lo;
+}
+XD_FN int clz64(uint64_t m) { return __builtin_clzll(m); }
+
+template <int PAR>
+XD_FN void improve_w1(vint cur, W1 &st) {
+  int inc = 1;
+  while (ballot(cur > st.bw + inc) != 0) ++inc;
+  st.bw += inc;
+  st.thr += inc;
+  st.best += inc;
+  const int s = ctz64(ballot(cur == st.bw));
+  st.bi = s + st.e + PAR + st.h;         // i = s + ceil(d/2) + h with d = 2e + PAR
+  st.bj = 2 * st.e + PAR - st.bi;
+}
+
+// Anti-diagonal d = 2 st.e + PAR; cur holds d-2 on entry and d on exit.
+template <bool NARROW, bool CLIP, int PAR>
+XD_FN int step_w1(vint &cur, vint prv, vint sw, int pos, W1 &st, const JobView &jv,
+                  const Params &P) {
+  const vint nbr = PAR ? from_next_lane(prv, kNeg) : from_prev_lane(prv, kNeg);
+  const vint v = vmax3(diag_term<NARROW>(cur, sw, pos, P), prv, nbr);
+  const uint64_t live = ballot(v >= st.thr) & st.range;
+  cur = select(lanes(live), v, kNeg);
+  st.cells_blk += (uint32_t)st.width;
+  if (live == 0) return kStepDone;
+  if (ballot(cur > st.bw) != 0) improve_w1<PAR>(cur, st);
+  st.bw += P.neg_gap;
+  st.thr += P.neg_gap;
+  const int a = ctz64(live);
+  const int f = clz64(live);             // last survivor is lane 63 - f
+  if (PAR) { st.e += 1; st.par = 0; } else { st.par = 1; }
+  // next range: [first, last + 1] in i; in lanes [a, 64 - f] after an odd
+  // anti-diagonal, [a - 1, 63 - f] after an even one
+  if (!CLIP) {
+    constexpr uint64_t edge = PAR ? 0xC000000000000001ull : 0x8000000000000003ull;
+    if ((live & edge) != 0) {
+      st.lo = PAR ? a : a - 1;
+      st.hi = PAR ? 64 - f : 63 - f;
+      return kStepRecenter;
+    }
+    st.width = 65 - (a + f);
+    st.range = lane_bits(PAR ? a : a - 1, st.width);
+    return kStepOn;
+  }
+  int lo = PAR ? a : a - 1;
+  int hi = PAR ? 64 - f : 63 - f;
+  const int d1 = 2 * st.e + st.par;        // matrix: d1 - n <= i <= m
+  const int smin = (d1 >> 1) - jv.n - st.h;
+  const int smax = jv.m - ((d1 + 1) >> 1) - st.h;
+  lo = lo > smin ? lo : smin;
+  hi = hi < smax ? hi : smax;
+  if (lo > hi) return kStepDone;
+  if (lo < 1 || hi > kWave - 2) {
+    st.lo = lo;
+    st.hi = hi;
+    return kStepRecenter;
+  }
+  st.width = hi - lo + 1;
+  st.range = lane_bits(lo, st.width);
+  return kStepOn;
+}
+
+// Steps until anti-diagonal 2 e_end, the end of the extension, or a pending
+// recenter.
+template <bool NARROW, bool CLIP>
+XD_FN int run_w1(Band<1> &bd, W1 &st, int32_t e0, int32_t e_end, const JobView &jv,
+                 const Params &P) {
+  int rc;
+  if (st.par) {
+    rc = step_w1<NARROW, CLIP, 1>(bd.O[0], bd.E[0], bd.SO[0], 2 * (st.e - e0), st, jv, P);
+    if (rc != kStepOn) return rc;
+  }
+  while (st.e < e_end) {
+    const int pos = 2 * (st.e - e0);
+    rc = step_w1<NARROW, CLIP, 0>(bd.E[0], bd.O[0], bd.SE[0], pos, st, jv, P);
+    if (rc != kStepOn) return rc;
+    rc = step_w1<NARROW, CLIP, 1>(bd.O[0], bd.E[0], bd.SO[0], pos, st, jv, P);
+    if (rc != kStepOn) return rc;
+  }
+  return kStepOn;
+}
+
+// Runner of extend_job_w1 built from the C steps above.
+struct RunC {
+  template <bool NARROW, bool CLIP>
+  XD_MEMBER static int run(Band<1> &bd, W1 &st, int32_t e0, int32_t e_end, const JobView &jv,
+                           const Params &P) {
+    return run_w1<NARROW, CLIP>(bd, st, e0, e_end, jv, P);
+  }
+};
+
+template <bool NARROW, class Runner = RunC>
+XD_FN JobOut extend_job_w1(const Job &job, const Params &P) {
+  JobOut out;
+  out.best = 0; out.bi = 0; out.bj = 0; out.status = kJobOk; out.cells = 0;
+  if (job.m + job.n == 0) return out;
+  JobView jv;
+  jv.A = make_view(P.A, P.a_words, job.a_start);
+  jv.B = make_view(P.B, P.b_words, job.b_start);
+  jv.m = job.m; jv.n = job.n; jv.x = job.x; jv.dir = job.dir;
+
+  Band<1> bd;
+  bd.O[0] = splat(kNeg);
+  bd.E[0] = select(lane_index() == 32, splat(0), kNeg);   // origin, anti-diagonal 0
+  W1 st;
+  st.h = -32;
+  st.e = 0;
+  st.par = 1;
+  {   // anti-diagonal 1: i in [0, 1], lanes 31 and 32, clipped to the matrix
+    int lo = (jv.n >= 1) ? 31 : 32;
+    int hi = (jv.m >= 1) ? 32 : 31;
+    st.width = hi - lo + 1;
+    st.range = lane_bits(lo, st.width);
+  }
+  st.best = 0; st.bi = 0; st.bj = 0;
+  st.bw = P.neg_gap;
+  st.thr = P.neg_gap - jv.x;
+  st.cells_blk = 0;
+  st.cells = 0;
+
+  int32_t words_e0 = -1, words_h = 0;
+  for (;;) {
+    const int32_t e0 = st.e & ~15;
+    const int32_t e_end = e0 + 16;
+    if (e0 != words_e0 || st.h != words_h) {
+      build_words<1, NARROW>(bd, e0, st.h, jv, P);
+      words_e0 = e0;
+      words_h = st.h;
+    }
+    // the window stays inside the matrix up to anti-diagonal 2 e_end
+    const bool inside = (kWave - 1 + e_end + st.h <= jv.m) && (st.h >= e_end - jv.n);
+    const int rc = inside ? Runner::template run<NARROW, false>(bd, st, e0, e_end, jv, P)
+                          : Runner::template run<NARROW, true>(bd, st, e0, e_end, jv, P);
+    st.cells += st.cells_blk;
+    st.cells_blk = 0;
+    if (rc == kStepDone) break;
+    if (rc == kStepRecenter) {
+      // place the pending range [lo, hi] in the middle of the 64 lanes
+      const int width = st.hi - st.lo + 1;
+      if (width > kWave - 2) { out.status = kJobWider; return out; }
+      const int dl = st.lo - (kWave - width) / 2;
+      bd.E[0] = from_lane_offset(bd.E[0], dl, kNeg);
+      bd.O[0] = from_lane_offset(bd.O[0], dl, kNeg);
+      st.h += dl;
+      st.width = width;
+      st.range = lane_bits(st.lo - dl, width);
+    }
+  }
+  out.best = st.best;
+  out.bi = st.bi;
+  out.bj = st.bj;
+  out.cells = st.cells;
   return out;
 }
 

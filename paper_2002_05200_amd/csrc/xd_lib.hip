@@ -26,6 +26,7 @@
 #include "xd_jobs.h"
 #include "xd_pairs.h"
 #include "xd_spill.h"
+#include "xd_w1_asm.h"
 
 namespace xd {
 
@@ -94,7 +95,16 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job *__restrict__ jobs,
   while (w < count) {
     const int32_t j = list[w];
     const Job job = jobs[j];
-    const JobOut o = extend_job<C, NARROW>(job, P);
+    JobOut o;
+    if constexpr (C == 1) {
+      if (P.impl == 0) {
+        o = extend_job_w1<NARROW, RunAsm>(job, P);
+      } else {
+        o = extend_job_w1<NARROW, RunC>(job, P);
+      }
+    } else {
+      o = extend_job<C, NARROW>(job, P);
+    }
     if (lane_id() == 0) {
       if (o.status == kJobWider) {
         const int32_t at = atomicAdd(next_count, 1);
@@ -360,6 +370,7 @@ xd_status xdrop_extend(xd_ctx *c, const uint32_t *d_a, uint64_t a_words, const u
   if (opts) o = *opts;
   if (o.min_tier < 0 || o.min_tier > kTiers)
     return fail(XD_EINVAL, "xdrop_extend: min_tier out of range");
+  if (o.impl < 0 || o.impl > 1) return fail(XD_EINVAL, "xdrop_extend: impl out of range");
 
   std::lock_guard<std::mutex> lock(c->mu);
   XD_HIP(hipSetDevice(c->device));
@@ -378,6 +389,7 @@ xd_status xdrop_extend(xd_ctx *c, const uint32_t *d_a, uint64_t a_words, const u
   P.base = (int32_t)base;
   P.delta = (int32_t)delta;
   P.pat = (int32_t)(delta * 0x55555555u);
+  P.impl = o.impl;
   const bool narrow = delta <= 3;
 
   const bool prof = o.profile != 0;

@@ -16,13 +16,16 @@
 
 #define XD_FN __device__ __forceinline__
 #define XD_HD __host__ __device__
+#define XD_MEMBER __device__ __forceinline__
 
 namespace xd {
 
 constexpr int kWave = 64;
 
 struct vint { int32_t x; };
-struct vbool { bool x; };
+// A lane predicate is a plain bool: as a one-member struct it would be
+// passed through memory (i1 stored, i8 loaded) and end up in LDS.
+using vbool = bool;
 
 XD_FN vint splat(int32_t s) { return {s}; }
 XD_FN vint lane_index() { return {(int32_t)__lane_id()}; }
@@ -41,12 +44,12 @@ XD_FN vint shr_u(vint a, int s) { return {(int32_t)((uint32_t)a.x >> s)}; }
 XD_FN vint shr_s(vint a, int s) { return {a.x >> s}; }
 XD_FN vint not_(vint a) { return {~a.x}; }
 
-XD_FN vbool operator>=(vint a, int32_t s) { return {a.x >= s}; }
-XD_FN vbool operator>(vint a, int32_t s) { return {a.x > s}; }
-XD_FN vbool operator==(vint a, int32_t s) { return {a.x == s}; }
-XD_FN vbool operator!=(vint a, int32_t s) { return {a.x != s}; }
-XD_FN vbool operator&(vbool a, vbool b) { return {(bool)(a.x & b.x)}; }
-XD_FN vbool le_u(vint a, uint32_t s) { return {(uint32_t)a.x <= s}; }
+XD_FN vbool operator>=(vint a, int32_t s) { return a.x >= s; }
+XD_FN vbool operator>(vint a, int32_t s) { return a.x > s; }
+XD_FN vbool operator==(vint a, int32_t s) { return a.x == s; }
+XD_FN vbool operator!=(vint a, int32_t s) { return a.x != s; }
+XD_FN vbool both(vbool a, vbool b) { return a & b; }
+XD_FN vbool le_u(vint a, uint32_t s) { return (uint32_t)a.x <= s; }
 
 // a[23:0] * b + c (v_mad_u32_u24)
 XD_FN vint mad24(vint a, int32_t b, vint c) {
@@ -56,9 +59,9 @@ XD_FN vint vmax(vint a, vint b) { return {a.x > b.x ? a.x : b.x}; }
 XD_FN vint vmax3(vint a, vint b, vint c) { return vmax(vmax(a, b), c); }
 XD_FN vint vmin(vint a, vint b) { return {a.x < b.x ? a.x : b.x}; }
 XD_FN vint clamp(vint a, int32_t lo, int32_t hi) { return {a.x < lo ? lo : (a.x > hi ? hi : a.x)}; }
-XD_FN vint select(vbool p, vint a, vint b) { return {p.x ? a.x : b.x}; }
-XD_FN vint select(vbool p, vint a, int32_t b) { return {p.x ? a.x : b}; }
-XD_FN vint bit_if(vbool p, int bit) { return {p.x ? (1 << bit) : 0}; }
+XD_FN vint select(vbool p, vint a, vint b) { return {p ? a.x : b.x}; }
+XD_FN vint select(vbool p, vint a, int32_t b) { return {p ? a.x : b}; }
+XD_FN vint bit_if(vbool p, int bit) { return {p ? (1 << bit) : 0}; }
 
 // unsigned bit-field extract of `width` bits at `pos` (v_bfe_u32)
 XD_FN vint bfe_u(vint w, int pos, int width) {
@@ -78,8 +81,8 @@ XD_FN vint bit_insert(vint m, int32_t a, int32_t b) {
   return {(int32_t)(((uint32_t)m.x & (uint32_t)a) | (~(uint32_t)m.x & (uint32_t)b))};
 }
 
-XD_FN uint64_t ballot(vbool p) { return __builtin_amdgcn_ballot_w64(p.x); }
-XD_FN vbool lanes(uint64_t mask) { return {__builtin_amdgcn_inverse_ballot_w64(mask)}; }
+XD_FN uint64_t ballot(vbool p) { return __builtin_amdgcn_ballot_w64(p); }
+XD_FN vbool lanes(uint64_t mask) { return __builtin_amdgcn_inverse_ballot_w64(mask); }
 XD_FN int32_t readlane(vint a, int lane) { return __builtin_amdgcn_readlane(a.x, lane); }
 XD_FN int32_t uniform(int32_t s) { return __builtin_amdgcn_readfirstlane(s); }
 

@@ -41,7 +41,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("sched", ctypes.c_int32), ("min_tier", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("sort_jobs", ctypes.c_int32),
                 ("short_long_split", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("impl", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -152,10 +152,12 @@ class DeviceBatch:
 
 
 def make_opts(sched: int = SCHED_AUTO, min_tier: int = 0, waves_per_cu: int = 0,
-              sort_jobs: int = 1, short_long_split: int = 0, profile: int = 0) -> Opts:
+              sort_jobs: int = 1, short_long_split: int = 0, profile: int = 0,
+              impl: int = 0) -> Opts:
     o = Opts()
     o.sched, o.min_tier, o.waves_per_cu = sched, min_tier, waves_per_cu
     o.sort_jobs, o.short_long_split, o.profile = sort_jobs, short_long_split, profile
+    o.impl = impl
     return o
 
 

@@ -58,6 +58,18 @@ def test_random_pairs(ctx, xd, seed, sched):
     assert_same(run(ctx, xd, bt, sched=sched), oracle_of(bt), f"random seed {seed} sched {sched}")
 
 
+@pytest.mark.parametrize("impl", [0, 1])
+def test_hand_scheduled_and_c_loops_agree(ctx, xd, impl):
+    """The hand-scheduled one-register loop and the portable C loop give the
+    same results, and both equal the oracle."""
+    from paper_2002_05200_amd import synth
+    bt = synth.concat([synth.random_cases(seed=150, n=200, len_lo=17, len_hi=3000,
+                                          x_choices=(0, 1, 2, 5, 10, 20, 30, 50)),
+                       synth.make_batch("batch10k", n=40, start=7, stride=2003)], name="impl")
+    assert_same(run(ctx, xd, bt, impl=impl), oracle_of(bt), f"impl {impl}")
+    assert_same(run(ctx, xd, bt, impl=impl, sched=1), oracle_of(bt), f"impl {impl} plain")
+
+
 @pytest.mark.parametrize("tier", [1, 2, 3, 4, 5])
 def test_every_register_tier(ctx, xd, tier):
     """Forcing every job to start at a wider tier must not change any result."""
