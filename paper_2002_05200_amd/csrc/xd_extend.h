@@ -448,11 +448,18 @@ XD_FN int run_w1(Band<1> &bd, W1 &st, int32_t e0, int32_t e_end, const JobView &
 // Runner of extend_job_w1 built from the C steps above.
 struct RunC {
   template <bool NARROW, bool CLIP>
-  XD_MEMBER static int run(Band<1> &bd, W1 &st, int32_t e0, int32_t e_end, const JobView &jv,
-                           const Params &P) {
+  XD_MEMBER static int run(Band<1> &bd, W1 &st, vint & /*cnt*/, int32_t e0, int32_t e_end,
+                           const JobView &jv, const Params &P) {
     return run_w1<NARROW, CLIP>(bd, st, e0, e_end, jv, P);
   }
 };
+
+// Sum over the 64 lanes (log-step exchange through ds_bpermute).
+XD_FN uint32_t lane_sum(vint v) {
+#pragma unroll
+  for (int sh = 1; sh < kWave; sh <<= 1) v = v + from_lane_offset(v, sh, 0);
+  return (uint32_t)readlane(v, 0);
+}
 
 template <bool NARROW, class Runner = RunC>
 XD_FN JobOut extend_job_w1(const Job &job, const Params &P) {
@@ -483,6 +490,7 @@ XD_FN JobOut extend_job_w1(const Job &job, const Params &P) {
   st.cells_blk = 0;
   st.cells = 0;
 
+  vint cnt = splat(0);            // cells counted per lane by the assembly loop
   int32_t words_e0 = -1, words_h = 0;
   for (;;) {
     const int32_t e0 = st.e & ~15;
@@ -494,8 +502,8 @@ XD_FN JobOut extend_job_w1(const Job &job, const Params &P) {
     }
     // the window stays inside the matrix up to anti-diagonal 2 e_end
     const bool inside = (kWave - 1 + e_end + st.h <= jv.m) && (st.h >= e_end - jv.n);
-    const int rc = inside ? Runner::template run<NARROW, false>(bd, st, e0, e_end, jv, P)
-                          : Runner::template run<NARROW, true>(bd, st, e0, e_end, jv, P);
+    const int rc = inside ? Runner::template run<NARROW, false>(bd, st, cnt, e0, e_end, jv, P)
+                          : Runner::template run<NARROW, true>(bd, st, cnt, e0, e_end, jv, P);
     st.cells += st.cells_blk;
     st.cells_blk = 0;
     if (rc == kStepDone) break;
@@ -514,7 +522,7 @@ XD_FN JobOut extend_job_w1(const Job &job, const Params &P) {
   out.best = st.best;
   out.bi = st.bi;
   out.bj = st.bj;
-  out.cells = st.cells;
+  out.cells = st.cells + lane_sum(cnt);
   return out;
 }
 

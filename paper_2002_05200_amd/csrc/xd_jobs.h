@@ -41,6 +41,7 @@ struct Params {
   int32_t delta;     // match - mismatch (>= 0)
   int32_t pat;       // delta replicated into every 2-bit field (narrow form)
   int32_t impl;      // 0: hand-scheduled loops where available, 1: C loops only
+  int32_t unit_match;  // match == 1: best grows by exactly 1 when it grows
 };
 
 }  // namespace xd

@@ -1,18 +1,24 @@
 // xd_lib.hip -- libxdrop: batched X-drop seed extension on one MI355X.
 //
 // Launch sequence of one xdrop_extend call (all on the caller's stream):
-//   k_reset    clears the per-tier job counters
+//   k_reset    clears the per-tier counters and statistics
 //   k_plan     one thread per pair: validation, seed split into a left and a
-//              right job (Section IV-B), initial lane-width tier from X
+//              right job (Section IV-B), initial lane-width tier from X, and a
+//              sort key (tier, then estimated anti-diagonals, longest first)
+//   radix sort all jobs by that key (hipCUB); k_offsets finds each tier's
+//              segment of the sorted order
 //   k_extend   per tier (cells per lane C = 1, 2, 4, 8, 16, 32): one wavefront
-//              per job; a job whose band outgrows its window is appended to
-//              the next tier's list and recomputed there
+//              per job, taking the tier's segment of the sorted order and then
+//              the jobs escalated into it; a job whose band outgrows its
+//              window is appended to the next tier's escalation list
 //   k_spill    jobs wider than the widest register tier: band in global memory
 //   k_combine  one thread per pair: left + seed + right
-// Plain mode launches every tier with one wavefront per listed job; the
-// persistent mode launches a fixed grid whose waves pop jobs from a device
-// queue (Section IV-B inter-sequence parallelism, without relaunches).
+// Plain mode launches every tier with one wavefront per job; the persistent
+// mode launches a fixed grid whose waves pop jobs from a device queue
+// (Section IV-B inter-sequence parallelism without relaunches), longest
+// estimated job first so no long job starts last.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstdio>
@@ -25,6 +31,7 @@
 #include "xd_extend.h"
 #include "xd_jobs.h"
 #include "xd_pairs.h"
+#include "xd_queue.h"
 #include "xd_spill.h"
 #include "xd_w1_asm.h"
 
@@ -32,12 +39,6 @@ namespace xd {
 
 constexpr int kBlock = 256;                 // 4 wavefronts, each its own job
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kLists = kTiers + 1;          // register tiers + spill tier
-
-// Device counters: [0, kLists) list lengths, [kLists, 2 kLists) queue heads.
-constexpr int kCounters = 2 * kLists;
-// Device statistics (uint64): jobs finished, cells of those jobs, escalations.
-constexpr int kStats = 3 * kLists;
 
 __global__ void k_reset(int32_t *counters, unsigned long long *stats) {
   if (threadIdx.x < kCounters) counters[threadIdx.x] = 0;
@@ -49,11 +50,16 @@ __device__ __forceinline__ void record_done(unsigned long long *stats, int tier,
   atomicAdd(&stats[kLists + tier], (unsigned long long)cells);
 }
 
+__device__ __forceinline__ uint64_t sort_key(const Job &j, int tier, bool by_cost) {
+  const uint64_t cost = by_cost ? (uint64_t)(j.m + j.n) : 0;   // anti-diagonals
+  return ((uint64_t)tier << 40) | ((1ull << 40) - 1 - cost);
+}
+
 __global__ void k_plan(const xd_pair *__restrict__ pairs, int64_t n_pairs, int64_t a_words,
                        int64_t b_words, int32_t match, int32_t mismatch, int32_t gap,
-                       int32_t min_tier, Job *__restrict__ jobs,
-                       int32_t *__restrict__ pair_status, int32_t *__restrict__ lists,
-                       int32_t *__restrict__ counters, int64_t list_stride) {
+                       int32_t min_tier, int32_t by_cost, Job *__restrict__ jobs,
+                       int32_t *__restrict__ pair_status, uint64_t *__restrict__ keys,
+                       int32_t *__restrict__ ids) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_pairs) return;
   Job l, r;
@@ -64,36 +70,52 @@ __global__ void k_plan(const xd_pair *__restrict__ pairs, int64_t n_pairs, int64
   int tl = initial_tier(l), tr = initial_tier(r);
   if (tl < min_tier) tl = min_tier;
   if (tr < min_tier) tr = min_tier;
-  int32_t at = atomicAdd(&counters[tl], 1);
-  lists[tl * list_stride + at] = (int32_t)(2 * p);
-  at = atomicAdd(&counters[tr], 1);
-  lists[tr * list_stride + at] = (int32_t)(2 * p + 1);
+  keys[2 * p] = sort_key(l, tl, by_cost != 0);
+  keys[2 * p + 1] = sort_key(r, tr, by_cost != 0);
+  ids[2 * p] = (int32_t)(2 * p);
+  ids[2 * p + 1] = (int32_t)(2 * p + 1);
 }
 
-// One job per wavefront.  Plain: wave w of the grid takes list[w].
-// Persistent (head != nullptr): waves pop list entries until none is left.
+// Segment of each tier in the sorted keys (binary search; no atomics).
+__global__ void k_offsets(const uint64_t *__restrict__ keys, int64_t nj, int32_t *counters) {
+  const int t = threadIdx.x;
+  if (t > kLists) return;
+  const uint64_t target = (uint64_t)t << 40;
+  int64_t lo = 0, hi = nj;   // first key >= target
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < target) lo = mid + 1; else hi = mid;
+  }
+  __shared__ int32_t bound[kLists + 1];
+  bound[t] = (int32_t)lo;
+  __syncthreads();
+  if (t < kLists) {
+    counters[kOff + t] = bound[t];
+    counters[kInit + t] = bound[t + 1] - bound[t];
+  }
+}
+
+// One job per wavefront.  Plain: wave w of the grid takes work item w.
+// Persistent (head != nullptr): waves pop work items until none is left.
 template <int C, bool NARROW>
-__global__ __launch_bounds__(kBlock) void k_extend(const Job *__restrict__ jobs,
-                                                   const int32_t *__restrict__ list,
-                                                   const int32_t *__restrict__ count_ptr,
+__global__ __launch_bounds__(kBlock) void k_extend(const Job *__restrict__ jobs, TierQueue q,
                                                    int32_t *head, JobOut *__restrict__ outs,
-                                                   int32_t *__restrict__ next_list,
-                                                   int32_t *__restrict__ next_count,
-                                                   unsigned long long *stats, int tier,
-                                                   Params P) {
+                                                   unsigned long long *stats, Params P) {
   const int wave = uniform((int32_t)(threadIdx.x >> 6));
-  const int32_t count = *count_ptr;
+  const int32_t n_init = q.counters[kInit + q.tier];
+  const int32_t n_esc = q.counters[kEsc + q.tier];
+  const int32_t total = n_init + n_esc;
   int32_t w;
   if (head == nullptr) {
     w = (int32_t)blockIdx.x * kWavesPerBlock + wave;
-    if (w >= count) return;
+    if (w >= total) return;
   } else {
     int32_t got = 0;
     if (lane_id() == 0) got = atomicAdd(head, 1);
     w = uniform(got);
   }
-  while (w < count) {
-    const int32_t j = list[w];
+  while (w < total) {
+    const int32_t j = tier_job(q, w, n_init, n_esc);
     const Job job = jobs[j];
     JobOut o;
     if constexpr (C == 1) {
@@ -107,12 +129,12 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job *__restrict__ jobs,
     }
     if (lane_id() == 0) {
       if (o.status == kJobWider) {
-        const int32_t at = atomicAdd(next_count, 1);
-        next_list[at] = j;
-        atomicAdd(&stats[2 * kLists + tier], 1ull);
+        const int32_t at = atomicAdd((int32_t *)&q.counters[kEsc + q.tier + 1], 1);
+        q.next_esc[at] = j;
+        atomicAdd(&stats[2 * kLists + q.tier], 1ull);
       } else {
         outs[j] = o;
-        record_done(stats, tier, o.cells);
+        record_done(stats, q.tier, o.cells);
       }
     }
     if (head == nullptr) break;
@@ -184,7 +206,13 @@ struct xd_ctx {
   Job *jobs = nullptr;
   JobOut *outs = nullptr;
   int32_t *pair_status = nullptr;
-  int32_t *lists = nullptr;      // kLists lists of 2 * cap_pairs entries
+  uint64_t *keys = nullptr;      // sort keys of all jobs (in, out)
+  uint64_t *keys_sorted = nullptr;
+  int32_t *ids = nullptr;        // job ids before and after sorting
+  int32_t *order = nullptr;
+  int32_t *esc = nullptr;        // kLists escalation lists of 2 * cap_pairs entries
+  void *sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
   int32_t *counters = nullptr;   // kCounters
   unsigned long long *stats = nullptr;  // kStats
   uint32_t *dummy = nullptr;     // one zero word for empty arenas
@@ -205,11 +233,21 @@ xd_status ensure_capacity(xd_ctx *c, int64_t n_pairs) {
   int64_t cap = std::max<int64_t>(n_pairs, 1024);
   if (c->cap_pairs > 0) cap = std::max<int64_t>(cap, c->cap_pairs * 3 / 2);
   const int64_t nj = 2 * cap;
+  size_t sort_bytes = 0;
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint64_t *)nullptr,
+                                         (uint64_t *)nullptr, (const int32_t *)nullptr,
+                                         (int32_t *)nullptr, (int)nj, 0, kKeyBits) != hipSuccess)
+    return fail(XD_EDEVICE, "radix sort sizing failed");
   size_t off = 0;
   const size_t o_jobs = off; off = align_up(off + sizeof(Job) * nj);
   const size_t o_outs = off; off = align_up(off + sizeof(JobOut) * nj);
   const size_t o_stat = off; off = align_up(off + sizeof(int32_t) * cap);
-  const size_t o_list = off; off = align_up(off + sizeof(int32_t) * nj * kLists);
+  const size_t o_keys = off; off = align_up(off + sizeof(uint64_t) * nj);
+  const size_t o_keys2 = off; off = align_up(off + sizeof(uint64_t) * nj);
+  const size_t o_ids = off; off = align_up(off + sizeof(int32_t) * nj);
+  const size_t o_order = off; off = align_up(off + sizeof(int32_t) * nj);
+  const size_t o_esc = off; off = align_up(off + sizeof(int32_t) * nj * kLists);
+  const size_t o_sort = off; off = align_up(off + sort_bytes);
   const size_t o_cnt = off; off = align_up(off + sizeof(int32_t) * kCounters);
   const size_t o_stats = off; off = align_up(off + sizeof(unsigned long long) * kStats);
   const size_t o_dummy = off; off = align_up(off + 64);
@@ -228,7 +266,13 @@ xd_status ensure_capacity(xd_ctx *c, int64_t n_pairs) {
   c->jobs = (Job *)(b + o_jobs);
   c->outs = (JobOut *)(b + o_outs);
   c->pair_status = (int32_t *)(b + o_stat);
-  c->lists = (int32_t *)(b + o_list);
+  c->keys = (uint64_t *)(b + o_keys);
+  c->keys_sorted = (uint64_t *)(b + o_keys2);
+  c->ids = (int32_t *)(b + o_ids);
+  c->order = (int32_t *)(b + o_order);
+  c->esc = (int32_t *)(b + o_esc);
+  c->sort_tmp = (void *)(b + o_sort);
+  c->sort_tmp_bytes = sort_bytes;
   c->counters = (int32_t *)(b + o_cnt);
   c->stats = (unsigned long long *)(b + o_stats);
   c->dummy = (uint32_t *)(b + o_dummy);
@@ -241,11 +285,13 @@ template <int C, bool NARROW>
 hipError_t launch_tier(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_cu,
                        int64_t max_jobs, int tier, const Params &P) {
   const int64_t stride = 2 * c->cap_pairs;
-  const int32_t *list = c->lists + tier * stride;
-  const int32_t *count = c->counters + tier;
-  int32_t *head = persistent ? c->counters + kLists + tier : nullptr;
-  int32_t *next_list = c->lists + (tier + 1) * stride;
-  int32_t *next_count = c->counters + tier + 1;
+  TierQueue q;
+  q.order = c->order;
+  q.esc = c->esc + tier * stride;
+  q.counters = c->counters;
+  q.next_esc = c->esc + (tier + 1) * stride;
+  q.tier = tier;
+  int32_t *head = persistent ? c->counters + kHead + tier : nullptr;
   int64_t blocks;
   if (persistent) {
     blocks = ((int64_t)c->num_cu * waves_per_cu + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -254,7 +300,7 @@ hipError_t launch_tier(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_
   }
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL((k_extend<C, NARROW>), dim3((unsigned)blocks), dim3(kBlock), 0, s, c->jobs,
-                     list, count, head, c->outs, next_list, next_count, c->stats, tier, P);
+                     q, head, c->outs, c->stats, P);
   return hipGetLastError();
 }
 
@@ -390,6 +436,7 @@ xd_status xdrop_extend(xd_ctx *c, const uint32_t *d_a, uint64_t a_words, const u
   P.delta = (int32_t)delta;
   P.pat = (int32_t)(delta * 0x55555555u);
   P.impl = o.impl;
+  P.unit_match = sc.match == 1;
   const bool narrow = delta <= 3;
 
   const bool prof = o.profile != 0;
@@ -402,17 +449,32 @@ xd_status xdrop_extend(xd_ctx *c, const uint32_t *d_a, uint64_t a_words, const u
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, c->counters, c->stats);
   XD_HIP(hipGetLastError());
   const int64_t stride = 2 * c->cap_pairs;
+  const bool by_cost = persistent && (opts ? o.sort_jobs != 0 : true);
   hipLaunchKernelGGL(k_plan, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s, d_pairs,
                      (int64_t)n_pairs, (int64_t)P.a_words, (int64_t)P.b_words, sc.match,
-                     sc.mismatch, sc.gap, o.min_tier, c->jobs, c->pair_status, c->lists,
-                     c->counters, stride);
+                     sc.mismatch, sc.gap, o.min_tier, (int32_t)by_cost, c->jobs,
+                     c->pair_status, c->keys, c->ids);
+  XD_HIP(hipGetLastError());
+  {
+    size_t tb = c->sort_tmp_bytes;
+    XD_HIP(hipcub::DeviceRadixSort::SortPairs(c->sort_tmp, tb, c->keys, c->keys_sorted, c->ids,
+                                              c->order, (int)nj, 0, kKeyBits, s));
+  }
+  hipLaunchKernelGGL(k_offsets, dim3(1), dim3(64), 0, s, c->keys_sorted, nj, c->counters);
   XD_HIP(hipGetLastError());
   if (prof) XD_HIP(hipEventRecord(c->ev[1], s));
   hipError_t e = narrow ? launch_tiers<true>(c, s, persistent, o.waves_per_cu, nj, P, prof)
                         : launch_tiers<false>(c, s, persistent, o.waves_per_cu, nj, P, prof);
   if (e != hipSuccess) return fail(XD_EDEVICE, std::string("k_extend: ") + hipGetErrorString(e));
-  st = spill_launch(&c->spill, s, c->jobs, c->lists + kTiers * stride, c->counters + kTiers,
-                    c->counters + kLists + kTiers, c->outs, c->stats, P);
+  {
+    TierQueue q;
+    q.order = c->order;
+    q.esc = c->esc + kTiers * stride;
+    q.counters = c->counters;
+    q.next_esc = nullptr;
+    q.tier = kTiers;
+    st = spill_launch(&c->spill, s, c->jobs, q, c->counters + kHead + kTiers, c->outs, c->stats, P);
+  }
   if (st != XD_OK) return fail(st, "k_spill launch failed");
   if (prof) XD_HIP(hipEventRecord(c->ev[8], s));
   hipLaunchKernelGGL(k_combine, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s,

@@ -13,6 +13,7 @@
 
 #include "xdrop.h"
 #include "xd_jobs.h"
+#include "xd_queue.h"
 
 namespace xd {
 
@@ -29,15 +30,16 @@ __device__ __forceinline__ uint32_t base_at(const uint32_t *W, int64_t g) {
 }
 
 __global__ __launch_bounds__(kSpillThreads) void k_spill(const Job *__restrict__ jobs,
-                                                         const int32_t *__restrict__ list,
-                                                         const int32_t *__restrict__ count_ptr,
+                                                         TierQueue q,
                                                          int32_t *head, JobOut *__restrict__ outs,
                                                          unsigned long long *stats, Params P,
                                                          int32_t *__restrict__ scratch) {
   __shared__ int32_t s_job;
   __shared__ int32_t s_first, s_last, s_max, s_imax;
   const int tid = threadIdx.x;
-  const int32_t count = *count_ptr;
+  const int32_t n_init = q.counters[kInit + q.tier];
+  const int32_t n_esc = q.counters[kEsc + q.tier];
+  const int32_t count = n_init + n_esc;
   int32_t *bufs[3];
   for (int t = 0; t < 3; ++t) bufs[t] = scratch + ((int64_t)blockIdx.x * 3 + t) * kSpillCap;
   const int32_t gap = -P.neg_gap;
@@ -50,7 +52,7 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(const Job *__restrict__
     const int32_t w = s_job;
     __syncthreads();
     if (w >= count) break;
-    const int32_t j = list[w];
+    const int32_t j = tier_job(q, w, n_init, n_esc);
     const Job job = jobs[j];
     JobOut out;
     out.best = 0; out.bi = 0; out.bj = 0; out.status = kJobOk; out.cells = 0;
@@ -126,24 +128,24 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(const Job *__restrict__
     out.best = best; out.bi = bi; out.bj = bj; out.cells = cells;
     if (tid == 0) {
       outs[j] = out;
-      atomicAdd(&stats[kTiers], 1ull);
-      atomicAdd(&stats[(kTiers + 1) + kTiers], (unsigned long long)cells);
+      atomicAdd(&stats[q.tier], 1ull);
+      atomicAdd(&stats[kLists + q.tier], (unsigned long long)cells);
     }
     __syncthreads();
   }
 }
 
 inline xd_status spill_launch(SpillScratch *sp, hipStream_t s, const Job *jobs,
-                              const int32_t *list, const int32_t *count, int32_t *head,
-                              JobOut *outs, unsigned long long *stats, const Params &P) {
+                              const TierQueue &q, int32_t *head, JobOut *outs,
+                              unsigned long long *stats, const Params &P) {
   if (!sp->buf) {
     void *p = nullptr;
     if (hipMalloc(&p, sizeof(int32_t) * 3 * kSpillCap * kSpillSlots) != hipSuccess)
       return XD_ENOMEM;
     sp->buf = (int32_t *)p;
   }
-  hipLaunchKernelGGL(k_spill, dim3(kSpillSlots), dim3(kSpillThreads), 0, s, jobs, list, count,
-                     head, outs, stats, P, sp->buf);
+  hipLaunchKernelGGL(k_spill, dim3(kSpillSlots), dim3(kSpillThreads), 0, s, jobs, q, head, outs,
+                     stats, P, sp->buf);
   return hipGetLastError() == hipSuccess ? XD_OK : XD_EDEVICE;
 }
 
