@@ -111,6 +111,7 @@ struct Scalars {
 
 struct JobView {
   SeqView A, B;
+  int64_t a_start, b_start;
   int32_t m, n, x, dir;
 };
 
@@ -278,6 +279,7 @@ XD_FN JobOut extend_job(const Job &job, const Params &P) {
   JobView jv;
   jv.A = make_view(P.A, P.a_words, job.a_start);
   jv.B = make_view(P.B, P.b_words, job.b_start);
+  jv.a_start = job.a_start; jv.b_start = job.b_start;
   jv.m = job.m; jv.n = job.n; jv.x = job.x; jv.dir = job.dir;
 
   Band<C> bd;
@@ -445,11 +447,24 @@ XD_FN int run_w1(Band<1> &bd, W1 &st, int32_t e0, int32_t e_end, const JobView &
   return kStepOn;
 }
 
+// Score words of block e0 for the current window base, unless already there.
+template <bool NARROW>
+XD_FN void ensure_words_w1(Band<1> &bd, const W1 &st, int32_t e0, const JobView &jv,
+                           const Params &P, int32_t &words_e0, int32_t &words_h) {
+  if (e0 != words_e0 || st.h != words_h) {
+    build_words<1, NARROW>(bd, e0, st.h, jv, P);
+    words_e0 = e0;
+    words_h = st.h;
+  }
+}
+
 // Runner of extend_job_w1 built from the C steps above.
 struct RunC {
   template <bool NARROW, bool CLIP>
   XD_MEMBER static int run(Band<1> &bd, W1 &st, vint & /*cnt*/, int32_t e0, int32_t e_end,
-                           const JobView &jv, const Params &P) {
+                           const JobView &jv, const Params &P, int32_t &words_e0,
+                           int32_t &words_h) {
+    ensure_words_w1<NARROW>(bd, st, e0, jv, P, words_e0, words_h);
     return run_w1<NARROW, CLIP>(bd, st, e0, e_end, jv, P);
   }
 };
@@ -469,6 +484,7 @@ XD_FN JobOut extend_job_w1(const Job &job, const Params &P) {
   JobView jv;
   jv.A = make_view(P.A, P.a_words, job.a_start);
   jv.B = make_view(P.B, P.b_words, job.b_start);
+  jv.a_start = job.a_start; jv.b_start = job.b_start;
   jv.m = job.m; jv.n = job.n; jv.x = job.x; jv.dir = job.dir;
 
   Band<1> bd;
@@ -495,15 +511,12 @@ XD_FN JobOut extend_job_w1(const Job &job, const Params &P) {
   for (;;) {
     const int32_t e0 = st.e & ~15;
     const int32_t e_end = e0 + 16;
-    if (e0 != words_e0 || st.h != words_h) {
-      build_words<1, NARROW>(bd, e0, st.h, jv, P);
-      words_e0 = e0;
-      words_h = st.h;
-    }
     // the window stays inside the matrix up to anti-diagonal 2 e_end
     const bool inside = (kWave - 1 + e_end + st.h <= jv.m) && (st.h >= e_end - jv.n);
-    const int rc = inside ? Runner::template run<NARROW, false>(bd, st, cnt, e0, e_end, jv, P)
-                          : Runner::template run<NARROW, true>(bd, st, cnt, e0, e_end, jv, P);
+    const int rc = inside ? Runner::template run<NARROW, false>(bd, st, cnt, e0, e_end, jv, P,
+                                                                words_e0, words_h)
+                          : Runner::template run<NARROW, true>(bd, st, cnt, e0, e_end, jv, P,
+                                                               words_e0, words_h);
     st.cells += st.cells_blk;
     st.cells_blk = 0;
     if (rc == kStepDone) break;

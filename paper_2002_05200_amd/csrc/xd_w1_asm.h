@@ -1,10 +1,13 @@
 // xd_w1_asm.h -- hand-scheduled gfx950 loop for one-register bands.
 //
-// Runs the anti-diagonals of one score-word block while the window stays
-// inside the matrix (the caller guarantees it), computing exactly what
-// step_w1<.., false, ..> in xd_extend.h computes.  Per anti-diagonal the
-// common path is 9 VALU and 7-8 SALU instructions:
+// Runs anti-diagonals while the 64-lane window stays inside the matrix,
+// computing exactly what step_w1<.., false, ..> in xd_extend.h computes, and
+// keeps running across score-word blocks: the next block's words are loaded
+// a whole block ahead and the score words rebuilt in place, so the loop only
+// returns to C code when the extension ends, the band needs recentring, or
+// the window approaches the end of a read.
 //
+// Common path of one anti-diagonal (9 VALU, 7-8 SALU):
 //   v_addc_co_u32  cnt, 0, cnt, carry=range          cells of this range, per lane
 //   v_mov_b32_dpp  t, prev  wave_shr:1 / wave_shl:1  neighbour diagonal (d-1)
 //   v_bfe_u32      u, score_word, pos, 2             match field
@@ -16,6 +19,8 @@
 //   v_cmp_lt_i32   vcc, bw, cur                      did best improve?
 //   s_add / v_add  thr, bw += -gap                   thresholds of d+1
 //   s_ff1 / s_flbit / s_bfm                          trim: next range mask
+// Block transition (every 32 anti-diagonals): 3 window shifts, 3 clamped
+// prefetch loads, 3 v_alignbit, 2 v_xor, 4 VALU per score word.
 //
 // Window edges: an even anti-diagonal may not use lane 0 (wave_shr leaves it
 // without a neighbour) and an odd one may not use lane 63.  Checking after
@@ -23,12 +28,57 @@
 // the next even range inside [1, 62] and the odd range after it inside
 // [0, 62], so even anti-diagonals need no check.  The neighbour-less lane
 // keeps a stale t, which the range mask discards.  Integer -inf is -2^30,
-// whose bit pattern is the inline constant -2.0.  No memory is accessed.
+// whose bit pattern is the inline constant -2.0.  Loads are vector loads of
+// clamped, in-bounds word indices; nothing is stored.
 #pragma once
 
 #include "xd_extend.h"
 
 namespace xd {
+
+// Packed read addressed for the assembly loop: word indices relative to
+// `base` are non-negative and at most hi_rel.
+struct AsmView {
+  const uint32_t *base;
+  int32_t sub;       // start - 16 * (base - words)
+  int32_t hi_rel;
+};
+
+XD_FN AsmView make_asm_view(const uint32_t *words, int64_t nwords, int64_t start,
+                            int64_t reach_words) {
+  int64_t wb = (start >> 4) - reach_words;
+  if (wb > nwords - 1) wb = nwords - 1;
+  if (wb < 0) wb = 0;
+  AsmView v;
+  v.base = words + wb;
+  v.sub = (int32_t)(start - 16 * wb);
+  const int64_t hi = nwords - 1 - wb;
+  v.hi_rel = (int32_t)(hi > (1 << 28) ? (1 << 28) : hi);
+  return v;
+}
+
+// One 16-base window of a read, followed from block to block: the words
+// (lo, hi) holding it now, the word prefetched for the next block, the index
+// of the word to prefetch after that, and the window's bit offset.
+struct Win {
+  vint lo, hi, nx, idx, sh;
+};
+
+XD_FN vint load_clamped(const AsmView &v, vint w) { return load_word(v.base, clamp(w, 0, v.hi_rel)); }
+
+// Window state of block e0 for base offset `off` (relative to the read start).
+template <bool FWD>
+XD_FN Win make_win(const AsmView &v, vint off) {
+  Win w;
+  const vint g = off + v.sub;
+  const vint wi = shr_s(g, 4);
+  w.sh = (g & 15) << 1;
+  w.lo = load_clamped(v, wi);
+  w.hi = load_clamped(v, wi + 1);
+  w.idx = FWD ? wi + 2 : wi - 1;   // next block: one word further along the read
+  w.nx = splat(0);
+  return w;
+}
 
 #define XD_DIAG_NARROW(CUR, SW)                         \
   "v_bfe_u32 %[u], %[" SW "], %[pos], 2\n\t"            \
@@ -37,6 +87,43 @@ namespace xd {
   "v_bfe_u32 %[u], %[" SW "], %[pos], 1\n\t"            \
   "v_mad_u32_u24 %[" CUR "], %[u], %[delta], %[" CUR "]\n\t" \
   "v_add_u32 %[" CUR "], %[base], %[" CUR "]\n\t"
+
+// Score word from an XOR of two windows: match bits z = ~(x | x >> 1) & 0x5555..;
+// narrow form: delta in every matching 2-bit field; wide form: z itself.
+#define XD_SW_NARROW(S, X)                                          \
+  "v_lshrrev_b32 %[u], 1, %[" X "]\n\t"                             \
+  "v_bitop3_b32 %[u], %[u], %[k55], %[" X "] bitop3:4\n\t"          \
+  "v_lshl_add_u32 %[u], %[u], 1, %[u]\n\t"                          \
+  "v_and_b32 %[" S "], %[pat], %[u]\n\t"
+#define XD_SW_WIDE(S, X)                                            \
+  "v_lshrrev_b32 %[u], 1, %[" X "]\n\t"                             \
+  "v_bitop3_b32 %[" S "], %[u], %[k55], %[" X "] bitop3:4\n\t"
+
+// Prefetch of window K's next word.
+#define XD_PREFETCH(K, HI, BASE)                                    \
+  "v_med3_i32 %[p" K "], %[idx" K "], 0, %[" HI "]\n\t"             \
+  "v_lshlrev_b32 %[p" K "], 2, %[p" K "]\n\t"                       \
+  "global_load_dword %[nx" K "], %[p" K "], %[" BASE "]\n\t"
+
+// Window K moves one word along the read.
+#define XD_SHIFT_FWD(K)                                             \
+  "v_mov_b32 %[lo" K "], %[hi" K "]\n\t"                            \
+  "v_mov_b32 %[hi" K "], %[nx" K "]\n\t"                            \
+  "v_add_u32 %[idx" K "], 1, %[idx" K "]\n\t"
+#define XD_SHIFT_BWD(K)                                             \
+  "v_mov_b32 %[hi" K "], %[lo" K "]\n\t"                            \
+  "v_mov_b32 %[lo" K "], %[nx" K "]\n\t"                            \
+  "v_add_u32 %[idx" K "], -1, %[idx" K "]\n\t"
+
+#define XD_WORDS(SW, SHIFT, REV)                                    \
+  "v_alignbit_b32 %[x0], %[hi0], %[lo0], %[sh0]\n\t"                \
+  "v_alignbit_b32 %[x1], %[hi1], %[lo1], %[sh1]\n\t"                \
+  "v_alignbit_b32 %[x2], %[hi2], %[lo2], %[sh2]\n\t"                \
+  "v_xor_b32 %[x0], %[x0], %[x2]\n\t"                               \
+  "v_xor_b32 %[x1], %[x1], %[x2]\n\t"                               \
+  REV                                                               \
+  SW("SE", "x0")                                                    \
+  SW("SO", "x1")
 
 // The cell update and prune of one anti-diagonal, then its thresholds and
 // survivor ends.
@@ -60,8 +147,8 @@ namespace xd {
 // Improvement of best on one parity.  The new best W value is bw + inc with
 // the smallest inc that no lane exceeds (inc = 1 when match = 1: best grows
 // by at most `match` per anti-diagonal).  The best cell is the first lane
-// holding it; its lane and position (pos | PAR) are recorded and turned into
-// (i, j) after the block.
+// holding it; its lane and anti-diagonal 2e + PAR are recorded and turned
+// into (i, j) after the loop.
 #define XD_IMPROVE_HEAD_UNIT(TAG, CUR)                                            \
   ".Limp" TAG "%=:\n\t"                                                           \
   "v_add_u32 %[tv], 1, %[bw]\n\t"                                                 \
@@ -83,25 +170,54 @@ namespace xd {
   "s_add_i32 %[thr], %[thr], %[inc]\n\t"                                          \
   "s_add_i32 %[best], %[best], %[inc]\n\t"                                        \
   "s_ff1_i32_b64 %[bs], vcc\n\t"                                                  \
-  "s_or_b32 %[bpos], %[pos], " PARBIT "\n\t"                                      \
+  "s_add_i32 %[bpos], %[e0x2], %[pos]\n\t"                                        \
+  "s_add_i32 %[bpos], %[bpos], " PARBIT "\n\t"                                    \
   "s_branch .Lret" TAG "%=\n"
 
-template <bool NARROW, bool UNIT>
-XD_FN int run_w1_fast(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, int32_t e_end,
-                      const Params &P) {
+enum : int { kStepLeave = 3 };
+
+template <bool NARROW, bool UNIT, bool FWD>
+XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &jv,
+                     const AsmView &av_a, const AsmView &av_b, const Params &P,
+                     int32_t &words_e0) {
+  // windows of block e0: A for even and odd anti-diagonals, and B
+  const vint s = lane_index();
+  const vint i0 = s + (st.h + e0);
+  const vint j0 = splat(e0 - st.h) - s;
+  Win w0 = make_win<FWD>(av_a, FWD ? i0 - 1 : splat(-14) - i0);
+  Win w1 = make_win<FWD>(av_a, FWD ? i0 + 0 : splat(-15) - i0);
+  Win w2 = make_win<FWD>(av_b, FWD ? j0 - 1 : splat(-14) - j0);
+  int32_t e0x2 = 2 * e0;
+  // the window stays inside the matrix for blocks ending at or before e_lim
+  int32_t e_lim = jv.m - (kWave - 1) - st.h;
+  if (st.h + jv.n < e_lim) e_lim = st.h + jv.n;
+  const int32_t lim2 = 2 * (e_lim - 16);
   int32_t status = 0;
   int32_t pos = 2 * (st.e - e0);
-  const int32_t pos_end = 2 * (e_end - e0);
   int32_t a = 0, f = 0, tmp = 0, inc = 0;
-  int32_t bs = 0, bpos = -1;   // lane and position of the last improvement
+  int32_t bs = 0, bpos = -1;   // lane and anti-diagonal of the last improvement
   uint64_t live = 0;
   const uint64_t edge = 0xC000000000000001ull;   // lanes 0, 62, 63
+  const int32_t k55 = 0x55555555;
+  const int32_t hi_a = av_a.hi_rel, hi_b = av_b.hi_rel;
+  const uint32_t *base_a = av_a.base, *base_b = av_b.base;
   int32_t par = st.par;
   int32_t bw = st.bw;
-  int32_t u, t, tv;
-#define XD_ASM_BODY(DIAG, HEAD)                                                       \
+  int32_t u, t, tv, x0, x1, x2, p0, p1, p2;
+  // score words of block e0 (the loop rebuilds them at each later block)
+  {
+    vint xe = funnel_shr(w0.hi, w0.lo, w0.sh) ^ funnel_shr(w2.hi, w2.lo, w2.sh);
+    vint xo = funnel_shr(w1.hi, w1.lo, w1.sh) ^ funnel_shr(w2.hi, w2.lo, w2.sh);
+    if (!FWD) { xe = bit_reverse(xe); xo = bit_reverse(xo); }
+    bd.SE[0] = score_word<NARROW>(xe, P.pat);
+    bd.SO[0] = score_word<NARROW>(xo, P.pat);
+  }
+#define XD_ASM_BODY(DIAG, HEAD, SW, SHIFTW, REV)                                      \
   asm volatile(                                                                       \
-      "s_nop 2\n\t"                                                                   \
+      "s_nop 4\n\t"                                                                   \
+      XD_PREFETCH("0", "hi_a", "base_a")                                              \
+      XD_PREFETCH("1", "hi_a", "base_a")                                              \
+      XD_PREFETCH("2", "hi_b", "base_b")                                              \
       "s_cmp_eq_u32 %[par], 0\n\t"                                                    \
       "s_cbranch_scc0 .Lodd%=\n"                                                      \
       ".Leven%=:\n\t"                                                                 \
@@ -118,11 +234,19 @@ XD_FN int run_w1_fast(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, int32_t e_end,
       "s_sub_i32 %[tmp], 65, %[tmp]\n\t"                                              \
       "s_bfm_b64 %[range], %[tmp], %[a]\n\t"                                          \
       "s_add_i32 %[pos], %[pos], 2\n\t"                                               \
-      "s_cmp_lt_i32 %[pos], %[pos_end]\n\t"                                           \
+      "s_cmp_lt_i32 %[pos], 32\n\t"                                                   \
       "s_cbranch_scc1 .Leven%=\n\t"                                                   \
-      "s_mov_b32 %[par], 0\n\t"                                                       \
-      "s_mov_b32 %[status], 0\n\t"                                                    \
-      "s_branch .Lexit%=\n"                                                           \
+      "s_add_i32 %[e0x2], %[e0x2], 32\n\t"                                            \
+      "s_mov_b32 %[pos], 0\n\t"                                                       \
+      "s_cmp_gt_i32 %[e0x2], %[lim2]\n\t"                                             \
+      "s_cbranch_scc1 .Lleave%=\n\t"                                                  \
+      "s_waitcnt vmcnt(0)\n\t"                                                        \
+      SHIFTW("0") SHIFTW("1") SHIFTW("2")                                             \
+      XD_PREFETCH("0", "hi_a", "base_a")                                              \
+      XD_PREFETCH("1", "hi_a", "base_a")                                              \
+      XD_PREFETCH("2", "hi_b", "base_b")                                              \
+      XD_WORDS(SW, SHIFTW, REV)                                                       \
+      "s_branch .Leven%=\n"                                                           \
       XD_IMPROVE(HEAD, "e", "E", "0")                                                 \
       XD_IMPROVE(HEAD, "o", "O", "1")                                                 \
       ".Ldone%=:\n\t"                                                                 \
@@ -131,41 +255,70 @@ XD_FN int run_w1_fast(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, int32_t e_end,
       ".Lrec%=:\n\t"                                                                  \
       "s_add_i32 %[pos], %[pos], 2\n\t"                                               \
       "s_mov_b32 %[par], 0\n\t"                                                       \
-      "s_mov_b32 %[status], 2\n"                                                      \
-      ".Lexit%=:\n"                                                                   \
+      "s_mov_b32 %[status], 2\n\t"                                                    \
+      "s_branch .Lexit%=\n"                                                           \
+      ".Lleave%=:\n\t"                                                                \
+      "s_mov_b32 %[par], 0\n\t"                                                       \
+      "s_mov_b32 %[status], 3\n"                                                      \
+      ".Lexit%=:\n\t"                                                                 \
+      "s_waitcnt vmcnt(0)\n"                                                          \
       : [E] "+v"(bd.E[0].x), [O] "+v"(bd.O[0].x), [cnt] "+v"(cnt.x), [bw] "+v"(bw),   \
-        [u] "=&v"(u), [t] "=&v"(t), [tv] "=&v"(tv),                                   \
+        [SE] "+v"(bd.SE[0].x), [SO] "+v"(bd.SO[0].x),                                 \
+        [lo0] "+v"(w0.lo.x), [hi0] "+v"(w0.hi.x), [nx0] "+v"(w0.nx.x), [idx0] "+v"(w0.idx.x), \
+        [lo1] "+v"(w1.lo.x), [hi1] "+v"(w1.hi.x), [nx1] "+v"(w1.nx.x), [idx1] "+v"(w1.idx.x), \
+        [lo2] "+v"(w2.lo.x), [hi2] "+v"(w2.hi.x), [nx2] "+v"(w2.nx.x), [idx2] "+v"(w2.idx.x), \
+        [u] "=&v"(u), [t] "=&v"(t), [tv] "=&v"(tv), [x0] "=&v"(x0), [x1] "=&v"(x1),   \
+        [x2] "=&v"(x2), [p0] "=&v"(p0), [p1] "=&v"(p1), [p2] "=&v"(p2),               \
         [thr] "+s"(st.thr), [best] "+s"(st.best), [bs] "+s"(bs), [bpos] "+s"(bpos),   \
-        [par] "+s"(par), [pos] "+s"(pos), [range] "+s"(st.range), [live] "+s"(live),  \
-        [a] "+s"(a), [f] "+s"(f), [tmp] "+s"(tmp), [inc] "+s"(inc),                   \
+        [par] "+s"(par), [pos] "+s"(pos), [e0x2] "+s"(e0x2), [range] "+s"(st.range),  \
+        [live] "+s"(live), [a] "+s"(a), [f] "+s"(f), [tmp] "+s"(tmp), [inc] "+s"(inc), \
         [status] "+s"(status)                                                         \
-      : [SE] "v"(bd.SE[0].x), [SO] "v"(bd.SO[0].x), [base] "s"(P.base),               \
-        [delta] "s"(P.delta), [ng] "s"(P.neg_gap), [pos_end] "s"(pos_end),            \
-        [edge] "s"(edge)                                                              \
-      : "vcc", "scc")
-  if (NARROW) {
-    if (UNIT) { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMPROVE_HEAD_UNIT); }
-    else { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMPROVE_HEAD_LOOP); }
+      : [sh0] "v"(w0.sh.x), [sh1] "v"(w1.sh.x), [sh2] "v"(w2.sh.x), [base] "s"(P.base), \
+        [delta] "s"(P.delta), [ng] "s"(P.neg_gap), [lim2] "s"(lim2), [edge] "s"(edge), \
+        [k55] "s"(k55), [pat] "s"(P.pat), [hi_a] "s"(hi_a), [hi_b] "s"(hi_b),          \
+        [base_a] "s"(base_a), [base_b] "s"(base_b)                                    \
+      : "vcc", "scc", "memory")
+#define XD_REV_NONE ""
+#define XD_REV_BOTH "v_bfrev_b32 %[x0], %[x0]\n\tv_bfrev_b32 %[x1], %[x1]\n\t"
+  if (FWD) {
+    if (NARROW) {
+      if (UNIT) { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMPROVE_HEAD_UNIT, XD_SW_NARROW, XD_SHIFT_FWD, XD_REV_NONE); }
+      else { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMPROVE_HEAD_LOOP, XD_SW_NARROW, XD_SHIFT_FWD, XD_REV_NONE); }
+    } else {
+      if (UNIT) { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMPROVE_HEAD_UNIT, XD_SW_WIDE, XD_SHIFT_FWD, XD_REV_NONE); }
+      else { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMPROVE_HEAD_LOOP, XD_SW_WIDE, XD_SHIFT_FWD, XD_REV_NONE); }
+    }
   } else {
-    if (UNIT) { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMPROVE_HEAD_UNIT); }
-    else { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMPROVE_HEAD_LOOP); }
+    if (NARROW) {
+      if (UNIT) { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMPROVE_HEAD_UNIT, XD_SW_NARROW, XD_SHIFT_BWD, XD_REV_BOTH); }
+      else { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMPROVE_HEAD_LOOP, XD_SW_NARROW, XD_SHIFT_BWD, XD_REV_BOTH); }
+    } else {
+      if (UNIT) { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMPROVE_HEAD_UNIT, XD_SW_WIDE, XD_SHIFT_BWD, XD_REV_BOTH); }
+      else { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMPROVE_HEAD_LOOP, XD_SW_WIDE, XD_SHIFT_BWD, XD_REV_BOTH); }
+    }
   }
+#undef XD_REV_NONE
+#undef XD_REV_BOTH
 #undef XD_ASM_BODY
-  if (bpos >= 0) {   // best cell: i = s + ceil(d/2) + h, j = d - i, d = 2e + par
-    const int32_t be = e0 + (bpos >> 1), bp = bpos & 1;
-    st.bi = bs + be + bp + st.h;
-    st.bj = 2 * be + bp - st.bi;
+  if (bpos >= 0) {   // best cell: i = s + ceil(d/2) + h, j = d - i, d = bpos
+    st.bi = bs + ((bpos + 1) >> 1) + st.h;
+    st.bj = bpos - st.bi;
   }
-  st.e = e0 + (pos >> 1);
+  const int32_t e0_now = e0x2 >> 1;
+  st.e = e0_now + (pos >> 1);
   st.par = par;
   st.bw = uniform(bw);
   st.width = __builtin_popcountll(st.range);
+  // the score words in SE/SO belong to block e0_now unless the loop left at a
+  // block boundary before rebuilding them
+  words_e0 = (status == kStepLeave) ? -1 : e0_now;
   if (status == 2) {   // pending even range [a, 64 - f] needs the window moved
     st.lo = a;
     st.hi = 64 - f;
     return kStepRecenter;
   }
-  return status == 1 ? kStepDone : kStepOn;
+  if (status == 1) return kStepDone;
+  return kStepOn;
 }
 
 // Runner of extend_job_w1: the assembly loop inside the matrix, the C loop
@@ -173,12 +326,23 @@ XD_FN int run_w1_fast(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, int32_t e_end,
 struct RunAsm {
   template <bool NARROW, bool CLIP>
   XD_MEMBER static int run(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, int32_t e_end,
-                           const JobView &jv, const Params &P) {
+                           const JobView &jv, const Params &P, int32_t &words_e0,
+                           int32_t &words_h) {
     if constexpr (CLIP) {
+      ensure_words_w1<NARROW>(bd, st, e0, jv, P, words_e0, words_h);
       return run_w1<NARROW, true>(bd, st, e0, e_end, jv, P);
     } else {
-      return P.unit_match ? run_w1_fast<NARROW, true>(bd, st, cnt, e0, e_end, P)
-                          : run_w1_fast<NARROW, false>(bd, st, cnt, e0, e_end, P);
+      const int64_t reach = ((int64_t)(jv.m + jv.n) >> 4) + 16;
+      const AsmView av_a = make_asm_view(P.A, P.a_words, jv.a_start, reach);
+      const AsmView av_b = make_asm_view(P.B, P.b_words, jv.b_start, reach);
+      if (jv.dir > 0) {
+        return P.unit_match
+                   ? run_w1_asm<NARROW, true, true>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0)
+                   : run_w1_asm<NARROW, false, true>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0);
+      }
+      return P.unit_match
+                 ? run_w1_asm<NARROW, true, false>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0)
+                 : run_w1_asm<NARROW, false, false>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0);
     }
   }
 };
