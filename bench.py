@@ -32,6 +32,20 @@ N_CU, LANES, CLOCK_HZ = 256, 64, 2.4e9
 INT32_PEAK_TOPS = N_CU * LANES * CLOCK_HZ / 1e12   # 39.32 T int32 lane-ops/s
 
 
+def profiled_traffic(kernel_tag: str, workload: str):
+    """HBM bytes per launch of a kernel from its committed counter summary, or
+    None when there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None, None
+    fields = dict(l.split(None, 1) for l in open(path).read().splitlines()
+                  if l.startswith(("TRAFFIC_BYTES ", "SOURCE_SHA256 ")))
+    from paper_2002_05200_amd import build as lib_build
+    if fields.get("SOURCE_SHA256", "").strip() != lib_build.source_hash():
+        return None, os.path.relpath(path, ROOT) + " (stale: sources changed)"
+    return int(fields["TRAFFIC_BYTES"]), os.path.relpath(path, ROOT)
+
+
 def cpu_baseline(workload: str, budget_s: float, n_total: int) -> dict:
     from oracle import oracle
     from paper_2002_05200_amd import synth
@@ -131,6 +145,10 @@ def main():
     achieved = dom_cells_per_launch * OPS_PER_CELL / (dom_ms_per_launch / 1e3) / 1e12
     kname = (f"k_extend<C={1 << dom}> (cells per lane {1 << dom})" if dom < 6
              else "k_spill (global-memory band)")
+    ktag = f"k_extend_c{1 << dom}" if dom < 6 else "k_spill"
+    traffic, traffic_src = profiled_traffic(ktag, args.workload)
+    if n_pairs != wl.n_pairs:          # the summary covers the whole workload only
+        traffic, traffic_src = None, None
     line = {
         "metric": METRIC,
         "value": round(gcups, 2),
@@ -150,7 +168,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": kname,
                      "achieved": round(achieved, 3), "peak": round(INT32_PEAK_TOPS, 3),
                      "unit": "TOP/s (int32 lane ops)", "frac": round(achieved / INT32_PEAK_TOPS, 4),
-                     "traffic": None,
+                     "traffic": traffic, "traffic_source": traffic_src,
                      "ops_per_cell": OPS_PER_CELL,
                      "kernel_ms_per_launch": round(dom_ms_per_launch, 4),
                      "kernel_cells_per_launch": int(dom_cells_per_launch),

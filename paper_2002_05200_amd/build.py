@@ -43,6 +43,17 @@ def sources():
             if f.endswith((".hip", ".h"))] + [os.path.join(INCLUDE, "xdrop.h")]
 
 
+def source_hash() -> str:
+    """sha256 over the library's sources and header (names and contents)."""
+    import hashlib
+    h = hashlib.sha256()
+    for path in sources():
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     obj = os.path.join(BUILD, "xd_lib.o")

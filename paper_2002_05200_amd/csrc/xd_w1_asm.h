@@ -7,10 +7,11 @@
 // returns to C code when the extension ends, the band needs recentring, or
 // the window approaches the end of a read.
 //
-// Common path of one anti-diagonal (9 VALU, 7-8 SALU):
+// Common path of one anti-diagonal (9 VALU, 8 SALU; the 32 anti-diagonals of
+// a score-word block are unrolled, so field offsets are immediates):
 //   v_addc_co_u32  cnt, 0, cnt, carry=range          cells of this range, per lane
 //   v_mov_b32_dpp  t, prev  wave_shr:1 / wave_shl:1  neighbour diagonal (d-1)
-//   v_bfe_u32      u, score_word, pos, 2             match field
+//   v_bfe_u32      u, score_word, 2q, 2              match field
 //   v_add3_u32     cur, cur, base, u                 diagonal term (d-2)
 //   v_max3_i32     cur, cur, prev, t                 the recurrence, gap-free form
 //   v_cmp_le_i32   vcc, thr, cur                     X-drop test ...
@@ -19,6 +20,8 @@
 //   v_cmp_lt_i32   vcc, bw, cur                      did best improve?
 //   s_add / v_add  thr, bw += -gap                   thresholds of d+1
 //   s_ff1 / s_flbit / s_bfm                          trim: next range mask
+// An improvement of best costs 3 SALU + 1 VALU out of line; best itself is
+// not tracked in the loop but recovered from bw afterwards.
 // Block transition (every 32 anti-diagonals): 3 window shifts, 3 clamped
 // prefetch loads, 3 v_alignbit, 2 v_xor, 4 VALU per score word.
 //
@@ -80,11 +83,11 @@ XD_FN Win make_win(const AsmView &v, vint off) {
   return w;
 }
 
-#define XD_DIAG_NARROW(CUR, SW)                         \
-  "v_bfe_u32 %[u], %[" SW "], %[pos], 2\n\t"            \
+#define XD_DIAG_NARROW(CUR, SW, P)                      \
+  "v_bfe_u32 %[u], %[" SW "], " P ", 2\n\t"             \
   "v_add3_u32 %[" CUR "], %[" CUR "], %[base], %[u]\n\t"
-#define XD_DIAG_WIDE(CUR, SW)                           \
-  "v_bfe_u32 %[u], %[" SW "], %[pos], 1\n\t"            \
+#define XD_DIAG_WIDE(CUR, SW, P)                        \
+  "v_bfe_u32 %[u], %[" SW "], " P ", 1\n\t"             \
   "v_mad_u32_u24 %[" CUR "], %[u], %[delta], %[" CUR "]\n\t" \
   "v_add_u32 %[" CUR "], %[base], %[" CUR "]\n\t"
 
@@ -115,7 +118,7 @@ XD_FN Win make_win(const AsmView &v, vint off) {
   "v_mov_b32 %[lo" K "], %[nx" K "]\n\t"                            \
   "v_add_u32 %[idx" K "], -1, %[idx" K "]\n\t"
 
-#define XD_WORDS(SW, SHIFT, REV)                                    \
+#define XD_WORDS(SW, REV)                                           \
   "v_alignbit_b32 %[x0], %[hi0], %[lo0], %[sh0]\n\t"                \
   "v_alignbit_b32 %[x1], %[hi1], %[lo1], %[sh1]\n\t"                \
   "v_alignbit_b32 %[x2], %[hi2], %[lo2], %[sh2]\n\t"                \
@@ -125,54 +128,116 @@ XD_FN Win make_win(const AsmView &v, vint off) {
   SW("SE", "x0")                                                    \
   SW("SO", "x1")
 
-// The cell update and prune of one anti-diagonal, then its thresholds and
-// survivor ends.
-#define XD_CELLS(TAG, DIAG, CUR, PRV, SW, SHIFT)                                  \
+// Cell update and prune of one anti-diagonal (field P of the score word),
+// then its thresholds and survivor ends.  TAG names the step's exits:
+// .Ld (nothing survived), .Li (best improved, returns to .Lr).
+#define XD_CORE(TAG, DIAG, CUR, PRV, SW, SHIFT, P)                                \
   "v_addc_co_u32_e64 %[cnt], vcc, 0, %[cnt], %[range]\n\t"                        \
   "v_mov_b32_dpp %[t], %[" PRV "] " SHIFT " row_mask:0xf bank_mask:0xf\n\t"        \
-  DIAG(CUR, SW)                                                                   \
+  DIAG(CUR, SW, P)                                                                \
   "v_max3_i32 %[" CUR "], %[" CUR "], %[" PRV "], %[t]\n\t"                        \
   "v_cmp_le_i32 vcc, %[thr], %[" CUR "]\n\t"                                      \
   "s_and_b64 %[live], vcc, %[range]\n\t"                                          \
   "v_cndmask_b32_e64 %[" CUR "], -2.0, %[" CUR "], %[live]\n\t"                   \
-  "s_cbranch_scc0 .Ldone%=\n\t"                                                   \
+  "s_cbranch_scc0 .Ld" TAG "_%=\n\t"                                               \
   "v_cmp_lt_i32 vcc, %[bw], %[" CUR "]\n\t"                                       \
-  "s_cbranch_vccnz .Limp" TAG "%=\n"                                              \
-  ".Lret" TAG "%=:\n\t"                                                           \
+  "s_cbranch_vccnz .Li" TAG "_%=\n"                                                \
+  ".Lr" TAG "_%=:\n\t"                                                             \
   "s_add_i32 %[thr], %[thr], %[ng]\n\t"                                           \
   "v_add_u32 %[bw], %[ng], %[bw]\n\t"                                             \
   "s_ff1_i32_b64 %[a], %[live]\n\t"                                               \
   "s_flbit_i32_b64 %[f], %[live]\n\t"
 
-// Improvement of best on one parity.  The new best W value is bw + inc with
-// the smallest inc that no lane exceeds (inc = 1 when match = 1: best grows
-// by at most `match` per anti-diagonal).  The best cell is the first lane
-// holding it; its lane and anti-diagonal 2e + PAR are recorded and turned
-// into (i, j) after the loop.
-#define XD_IMPROVE_HEAD_UNIT(TAG, CUR)                                            \
-  ".Limp" TAG "%=:\n\t"                                                           \
-  "v_add_u32 %[tv], 1, %[bw]\n\t"                                                 \
-  "s_mov_b32 %[inc], 1\n\t"
-#define XD_IMPROVE_HEAD_LOOP(TAG, CUR)                                            \
-  ".Limp" TAG "%=:\n\t"                                                           \
+// Even anti-diagonal 2(e0 + K): next (odd) range is lanes [a - 1, 63 - f].
+#define XD_EVEN(K, P, DIAG)                                                       \
+  ".Le" K "_%=:\n\t"                                                               \
+  XD_CORE("e" K, DIAG, "E", "O", "SE", "wave_shr:1", P)                           \
+  "s_add_i32 %[tmp], %[a], %[f]\n\t"                                              \
+  "s_sub_i32 %[tmp], 65, %[tmp]\n\t"                                              \
+  "s_add_i32 %[a], %[a], -1\n\t"                                                  \
+  "s_bfm_b64 %[range], %[tmp], %[a]\n"
+// Odd anti-diagonal 2(e0 + K) + 1: leave for a recentre when a survivor sits
+// in lane 0, 62 or 63 (.Lc), else the next (even) range is [a, 64 - f].
+#define XD_ODD(K, P, DIAG)                                                        \
+  ".Lo" K "_%=:\n\t"                                                               \
+  XD_CORE("o" K, DIAG, "O", "E", "SO", "wave_shl:1", P)                           \
+  "s_and_b64 vcc, %[live], %[edge]\n\t"                                           \
+  "s_cbranch_scc1 .Lco" K "_%=\n\t"                                                \
+  "s_add_i32 %[tmp], %[a], %[f]\n\t"                                              \
+  "s_sub_i32 %[tmp], 65, %[tmp]\n\t"                                              \
+  "s_bfm_b64 %[range], %[tmp], %[a]\n"
+#define XD_PAIR(K, P, DIAG) XD_EVEN(K, P, DIAG) XD_ODD(K, P, DIAG)
+
+// Improvement of best on anti-diagonal e0x2 + BP.  The new best W value is
+// bw + inc with the smallest inc that no lane exceeds; with match = 1 it is
+// always bw + 1 (best grows by at most `match` per anti-diagonal), so the
+// lanes above bw are exactly the lanes holding the new best.  The first of
+// them and the anti-diagonal are recorded; (i, j) and best itself are
+// derived after the loop.
+#define XD_IMP_UNIT(TAG, CUR, BP)                                                 \
+  ".Li" TAG "_%=:\n\t"                                                             \
+  "s_ff1_i32_b64 %[bs], vcc\n\t"                                                  \
+  "s_add_i32 %[bpos], %[e0x2], " BP "\n\t"                                        \
+  "s_add_i32 %[thr], %[thr], 1\n\t"                                               \
+  "v_add_u32 %[bw], 1, %[bw]\n\t"                                                 \
+  "s_branch .Lr" TAG "_%=\n"
+#define XD_IMP_LOOP(TAG, CUR, BP)                                                 \
+  ".Li" TAG "_%=:\n\t"                                                             \
   "s_mov_b32 %[inc], 1\n"                                                         \
-  ".Limpl" TAG "%=:\n\t"                                                          \
+  ".Lil" TAG "_%=:\n\t"                                                            \
   "v_add_u32 %[tv], %[inc], %[bw]\n\t"                                            \
   "v_cmp_lt_i32 vcc, %[tv], %[" CUR "]\n\t"                                       \
-  "s_cbranch_vccz .Limpd" TAG "%=\n\t"                                            \
+  "s_cbranch_vccz .Lid" TAG "_%=\n\t"                                              \
   "s_add_i32 %[inc], %[inc], 1\n\t"                                               \
-  "s_branch .Limpl" TAG "%=\n"                                                    \
-  ".Limpd" TAG "%=:\n\t"
-#define XD_IMPROVE(HEAD, TAG, CUR, PARBIT)                                        \
-  HEAD(TAG, CUR)                                                                  \
+  "s_branch .Lil" TAG "_%=\n"                                                      \
+  ".Lid" TAG "_%=:\n\t"                                                            \
   "v_cmp_eq_u32 vcc, %[tv], %[" CUR "]\n\t"                                       \
   "v_mov_b32 %[bw], %[tv]\n\t"                                                    \
   "s_add_i32 %[thr], %[thr], %[inc]\n\t"                                          \
-  "s_add_i32 %[best], %[best], %[inc]\n\t"                                        \
   "s_ff1_i32_b64 %[bs], vcc\n\t"                                                  \
-  "s_add_i32 %[bpos], %[e0x2], %[pos]\n\t"                                        \
-  "s_add_i32 %[bpos], %[bpos], " PARBIT "\n\t"                                    \
-  "s_branch .Lret" TAG "%=\n"
+  "s_add_i32 %[bpos], %[e0x2], " BP "\n\t"                                        \
+  "s_branch .Lr" TAG "_%=\n"
+
+// Out-of-line exits of the pair K: improvements, end of the extension, and
+// the recentre exit of the odd anti-diagonal (which resumes at pair K + 1).
+#define XD_STUBS(K, P, P1, PN, IMP)                                               \
+  IMP("e" K, "E", P)                                                              \
+  IMP("o" K, "O", P1)                                                             \
+  ".Lde" K "_%=:\n\t"                                                              \
+  "s_mov_b32 %[pos], " P "\n\t"                                                   \
+  "s_mov_b32 %[par], 0\n\t"                                                       \
+  "s_branch .Ldone_%=\n"                                                           \
+  ".Ldo" K "_%=:\n\t"                                                              \
+  "s_mov_b32 %[pos], " P "\n\t"                                                   \
+  "s_mov_b32 %[par], 1\n\t"                                                       \
+  "s_branch .Ldone_%=\n"                                                           \
+  ".Lco" K "_%=:\n\t"                                                              \
+  "s_mov_b32 %[pos], " PN "\n\t"                                                  \
+  "s_branch .Lrec_%=\n"
+
+#define XD_TABLE(K) "s_branch .Le" K "_%=\n\ts_branch .Lo" K "_%=\n\t"
+
+#define XD_ALL_PAIRS(DIAG)                                                        \
+  XD_PAIR("0", "0", DIAG) XD_PAIR("1", "2", DIAG) XD_PAIR("2", "4", DIAG)         \
+  XD_PAIR("3", "6", DIAG) XD_PAIR("4", "8", DIAG) XD_PAIR("5", "10", DIAG)        \
+  XD_PAIR("6", "12", DIAG) XD_PAIR("7", "14", DIAG) XD_PAIR("8", "16", DIAG)      \
+  XD_PAIR("9", "18", DIAG) XD_PAIR("10", "20", DIAG) XD_PAIR("11", "22", DIAG)    \
+  XD_PAIR("12", "24", DIAG) XD_PAIR("13", "26", DIAG) XD_PAIR("14", "28", DIAG)   \
+  XD_PAIR("15", "30", DIAG)
+#define XD_ALL_STUBS(IMP)                                                         \
+  XD_STUBS("0", "0", "1", "2", IMP) XD_STUBS("1", "2", "3", "4", IMP)             \
+  XD_STUBS("2", "4", "5", "6", IMP) XD_STUBS("3", "6", "7", "8", IMP)             \
+  XD_STUBS("4", "8", "9", "10", IMP) XD_STUBS("5", "10", "11", "12", IMP)         \
+  XD_STUBS("6", "12", "13", "14", IMP) XD_STUBS("7", "14", "15", "16", IMP)       \
+  XD_STUBS("8", "16", "17", "18", IMP) XD_STUBS("9", "18", "19", "20", IMP)       \
+  XD_STUBS("10", "20", "21", "22", IMP) XD_STUBS("11", "22", "23", "24", IMP)     \
+  XD_STUBS("12", "24", "25", "26", IMP) XD_STUBS("13", "26", "27", "28", IMP)     \
+  XD_STUBS("14", "28", "29", "30", IMP) XD_STUBS("15", "30", "31", "32", IMP)
+#define XD_ALL_TABLE                                                              \
+  XD_TABLE("0") XD_TABLE("1") XD_TABLE("2") XD_TABLE("3") XD_TABLE("4")           \
+  XD_TABLE("5") XD_TABLE("6") XD_TABLE("7") XD_TABLE("8") XD_TABLE("9")           \
+  XD_TABLE("10") XD_TABLE("11") XD_TABLE("12") XD_TABLE("13") XD_TABLE("14")      \
+  XD_TABLE("15")
 
 enum : int { kStepLeave = 3 };
 
@@ -212,55 +277,51 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
     bd.SE[0] = score_word<NARROW>(xe, P.pat);
     bd.SO[0] = score_word<NARROW>(xo, P.pat);
   }
-#define XD_ASM_BODY(DIAG, HEAD, SW, SHIFTW, REV)                                      \
+  // The 32 anti-diagonals of a block are unrolled, so field offsets and
+  // anti-diagonal numbers are immediates; entry jumps through a table of
+  // branches indexed by the step within the block (pos + par).
+#define XD_ASM_BODY(DIAG, IMP, SW, SHIFTW, REV)                                       \
   asm volatile(                                                                       \
       "s_nop 4\n\t"                                                                   \
       XD_PREFETCH("0", "hi_a", "base_a")                                              \
       XD_PREFETCH("1", "hi_a", "base_a")                                              \
       XD_PREFETCH("2", "hi_b", "base_b")                                              \
-      "s_cmp_eq_u32 %[par], 0\n\t"                                                    \
-      "s_cbranch_scc0 .Lodd%=\n"                                                      \
-      ".Leven%=:\n\t"                                                                 \
-      XD_CELLS("e", DIAG, "E", "O", "SE", "wave_shr:1")                               \
-      "s_add_i32 %[tmp], %[a], %[f]\n\t"                                              \
-      "s_sub_i32 %[tmp], 65, %[tmp]\n\t"                                              \
-      "s_add_i32 %[a], %[a], -1\n\t"                                                  \
-      "s_bfm_b64 %[range], %[tmp], %[a]\n"                                            \
-      ".Lodd%=:\n\t"                                                                  \
-      XD_CELLS("o", DIAG, "O", "E", "SO", "wave_shl:1")                               \
-      "s_and_b64 vcc, %[live], %[edge]\n\t"                                           \
-      "s_cbranch_scc1 .Lrec%=\n\t"                                                    \
-      "s_add_i32 %[tmp], %[a], %[f]\n\t"                                              \
-      "s_sub_i32 %[tmp], 65, %[tmp]\n\t"                                              \
-      "s_bfm_b64 %[range], %[tmp], %[a]\n\t"                                          \
-      "s_add_i32 %[pos], %[pos], 2\n\t"                                               \
-      "s_cmp_lt_i32 %[pos], 32\n\t"                                                   \
-      "s_cbranch_scc1 .Leven%=\n\t"                                                   \
+      "s_add_i32 s42, %[pos], %[par]\n\t"                                             \
+      "s_lshl_b32 s42, s42, 2\n\t"                                                    \
+      "s_getpc_b64 s[40:41]\n"                                                        \
+      ".Lbase_%=:\n\t"                                                                 \
+      "s_add_u32 s40, s40, s42\n\t"                                                   \
+      "s_addc_u32 s41, s41, 0\n\t"                                                    \
+      "s_add_u32 s40, s40, .Ltab_%=-.Lbase_%=\n\t"                                      \
+      "s_addc_u32 s41, s41, 0\n\t"                                                    \
+      "s_nop 0\n\t"                                                                   \
+      "s_setpc_b64 s[40:41]\n"                                                        \
+      ".Ltab_%=:\n\t"                                                                  \
+      XD_ALL_TABLE                                                                    \
+      XD_ALL_PAIRS(DIAG)                                                              \
       "s_add_i32 %[e0x2], %[e0x2], 32\n\t"                                            \
-      "s_mov_b32 %[pos], 0\n\t"                                                       \
       "s_cmp_gt_i32 %[e0x2], %[lim2]\n\t"                                             \
-      "s_cbranch_scc1 .Lleave%=\n\t"                                                  \
+      "s_cbranch_scc1 .Lleave_%=\n\t"                                                  \
       "s_waitcnt vmcnt(0)\n\t"                                                        \
       SHIFTW("0") SHIFTW("1") SHIFTW("2")                                             \
       XD_PREFETCH("0", "hi_a", "base_a")                                              \
       XD_PREFETCH("1", "hi_a", "base_a")                                              \
       XD_PREFETCH("2", "hi_b", "base_b")                                              \
-      XD_WORDS(SW, SHIFTW, REV)                                                       \
-      "s_branch .Leven%=\n"                                                           \
-      XD_IMPROVE(HEAD, "e", "E", "0")                                                 \
-      XD_IMPROVE(HEAD, "o", "O", "1")                                                 \
-      ".Ldone%=:\n\t"                                                                 \
+      XD_WORDS(SW, REV)                                                               \
+      "s_branch .Le0_%=\n"                                                             \
+      XD_ALL_STUBS(IMP)                                                               \
+      ".Ldone_%=:\n\t"                                                                 \
       "s_mov_b32 %[status], 1\n\t"                                                    \
-      "s_branch .Lexit%=\n"                                                           \
-      ".Lrec%=:\n\t"                                                                  \
-      "s_add_i32 %[pos], %[pos], 2\n\t"                                               \
+      "s_branch .Lexit_%=\n"                                                           \
+      ".Lrec_%=:\n\t"                                                                  \
       "s_mov_b32 %[par], 0\n\t"                                                       \
       "s_mov_b32 %[status], 2\n\t"                                                    \
-      "s_branch .Lexit%=\n"                                                           \
-      ".Lleave%=:\n\t"                                                                \
+      "s_branch .Lexit_%=\n"                                                           \
+      ".Lleave_%=:\n\t"                                                                \
+      "s_mov_b32 %[pos], 0\n\t"                                                       \
       "s_mov_b32 %[par], 0\n\t"                                                       \
       "s_mov_b32 %[status], 3\n"                                                      \
-      ".Lexit%=:\n\t"                                                                 \
+      ".Lexit_%=:\n\t"                                                                 \
       "s_waitcnt vmcnt(0)\n"                                                          \
       : [E] "+v"(bd.E[0].x), [O] "+v"(bd.O[0].x), [cnt] "+v"(cnt.x), [bw] "+v"(bw),   \
         [SE] "+v"(bd.SE[0].x), [SO] "+v"(bd.SO[0].x),                                 \
@@ -269,7 +330,7 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
         [lo2] "+v"(w2.lo.x), [hi2] "+v"(w2.hi.x), [nx2] "+v"(w2.nx.x), [idx2] "+v"(w2.idx.x), \
         [u] "=&v"(u), [t] "=&v"(t), [tv] "=&v"(tv), [x0] "=&v"(x0), [x1] "=&v"(x1),   \
         [x2] "=&v"(x2), [p0] "=&v"(p0), [p1] "=&v"(p1), [p2] "=&v"(p2),               \
-        [thr] "+s"(st.thr), [best] "+s"(st.best), [bs] "+s"(bs), [bpos] "+s"(bpos),   \
+        [thr] "+s"(st.thr), [bs] "+s"(bs), [bpos] "+s"(bpos),                         \
         [par] "+s"(par), [pos] "+s"(pos), [e0x2] "+s"(e0x2), [range] "+s"(st.range),  \
         [live] "+s"(live), [a] "+s"(a), [f] "+s"(f), [tmp] "+s"(tmp), [inc] "+s"(inc), \
         [status] "+s"(status)                                                         \
@@ -277,29 +338,34 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
         [delta] "s"(P.delta), [ng] "s"(P.neg_gap), [lim2] "s"(lim2), [edge] "s"(edge), \
         [k55] "s"(k55), [pat] "s"(P.pat), [hi_a] "s"(hi_a), [hi_b] "s"(hi_b),          \
         [base_a] "s"(base_a), [base_b] "s"(base_b)                                    \
-      : "vcc", "scc", "memory")
+      : "vcc", "scc", "memory", "s40", "s41", "s42")
 #define XD_REV_NONE ""
 #define XD_REV_BOTH "v_bfrev_b32 %[x0], %[x0]\n\tv_bfrev_b32 %[x1], %[x1]\n\t"
   if (FWD) {
     if (NARROW) {
-      if (UNIT) { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMPROVE_HEAD_UNIT, XD_SW_NARROW, XD_SHIFT_FWD, XD_REV_NONE); }
-      else { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMPROVE_HEAD_LOOP, XD_SW_NARROW, XD_SHIFT_FWD, XD_REV_NONE); }
+      if (UNIT) { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_UNIT, XD_SW_NARROW, XD_SHIFT_FWD, XD_REV_NONE); }
+      else { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_LOOP, XD_SW_NARROW, XD_SHIFT_FWD, XD_REV_NONE); }
     } else {
-      if (UNIT) { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMPROVE_HEAD_UNIT, XD_SW_WIDE, XD_SHIFT_FWD, XD_REV_NONE); }
-      else { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMPROVE_HEAD_LOOP, XD_SW_WIDE, XD_SHIFT_FWD, XD_REV_NONE); }
+      if (UNIT) { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMP_UNIT, XD_SW_WIDE, XD_SHIFT_FWD, XD_REV_NONE); }
+      else { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMP_LOOP, XD_SW_WIDE, XD_SHIFT_FWD, XD_REV_NONE); }
     }
   } else {
     if (NARROW) {
-      if (UNIT) { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMPROVE_HEAD_UNIT, XD_SW_NARROW, XD_SHIFT_BWD, XD_REV_BOTH); }
-      else { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMPROVE_HEAD_LOOP, XD_SW_NARROW, XD_SHIFT_BWD, XD_REV_BOTH); }
+      if (UNIT) { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_UNIT, XD_SW_NARROW, XD_SHIFT_BWD, XD_REV_BOTH); }
+      else { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_LOOP, XD_SW_NARROW, XD_SHIFT_BWD, XD_REV_BOTH); }
     } else {
-      if (UNIT) { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMPROVE_HEAD_UNIT, XD_SW_WIDE, XD_SHIFT_BWD, XD_REV_BOTH); }
-      else { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMPROVE_HEAD_LOOP, XD_SW_WIDE, XD_SHIFT_BWD, XD_REV_BOTH); }
+      if (UNIT) { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMP_UNIT, XD_SW_WIDE, XD_SHIFT_BWD, XD_REV_BOTH); }
+      else { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMP_LOOP, XD_SW_WIDE, XD_SHIFT_BWD, XD_REV_BOTH); }
     }
   }
 #undef XD_REV_NONE
 #undef XD_REV_BOTH
 #undef XD_ASM_BODY
+  // the anti-diagonal the loop stopped at: d = e0x2 + pos + par; W-form
+  // thresholds satisfy bw = best + d |gap| there, which gives best
+  const int32_t d_now = e0x2 + pos + par;
+  st.bw = uniform(bw);
+  st.best = st.bw - d_now * P.neg_gap;
   if (bpos >= 0) {   // best cell: i = s + ceil(d/2) + h, j = d - i, d = bpos
     st.bi = bs + ((bpos + 1) >> 1) + st.h;
     st.bj = bpos - st.bi;
@@ -307,7 +373,6 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
   const int32_t e0_now = e0x2 >> 1;
   st.e = e0_now + (pos >> 1);
   st.par = par;
-  st.bw = uniform(bw);
   st.width = __builtin_popcountll(st.range);
   // the score words in SE/SO belong to block e0_now unless the loop left at a
   // block boundary before rebuilding them
@@ -320,7 +385,6 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
   if (status == 1) return kStepDone;
   return kStepOn;
 }
-
 // Runner of extend_job_w1: the assembly loop inside the matrix, the C loop
 // (with matrix clipping) near the ends of the reads.
 struct RunAsm {
