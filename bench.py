@@ -67,6 +67,80 @@ def cpu_baseline(workload: str, budget_s: float, n_total: int) -> dict:
                       f"({cells} cells, {secs:.1f} s, one thread)"}
 
 
+def serving_leg(n_distinct: int, n_requests: int, load: float, slots: int, max_batch: int,
+                graph: bool, workers: int) -> dict:
+    """Continuous-batching serving run: saturation throughput closed-loop, then
+    Poisson arrivals at load * saturation; latency from the scheduled arrival
+    to the completion the server's scheduler observed (same steady clock)."""
+    import threading
+    from multiprocessing import get_context
+    from paper_2002_05200_amd import synth, xdrop
+    t0 = time.time()
+    if workers > 1:
+        with get_context("fork").Pool(workers) as pool:
+            reqs = pool.map(synth.make_request, range(n_distinct), chunksize=8)
+    else:
+        reqs = [synth.make_request(r) for r in range(n_distinct)]
+    packed = [xdrop.PackedRequest(bt) for bt in reqs]
+    cells_of = None
+    print(f"[bench] serving: {n_distinct} distinct requests generated in {time.time()-t0:.1f} s",
+          file=sys.stderr, flush=True)
+    srv = xdrop.Server(slots=slots, max_batch_pairs=max_batch, graph=int(graph),
+                       mem_budget=2 << 30)
+    try:
+        def closed(n):
+            ts = [srv.submit(packed[i % n_distinct]) for i in range(n)]
+            cells = 0
+            for i, t in enumerate(ts):
+                r, _ = srv.poll(t, packed[i % n_distinct].n, wait_ms=-1)
+                cells += int(r["left_cells"].sum() + r["right_cells"].sum())
+            return cells
+        closed(min(200, n_distinct))                       # warm-up (graphs, scratch)
+        t1 = time.perf_counter()
+        closed(n_distinct)
+        r_sat = n_distinct / (time.perf_counter() - t1)
+        rate = load * r_sat
+        arrivals = synth.poisson_arrivals(n_requests, rate)
+        tickets = [None] * n_requests
+        sched_ns = [0] * n_requests
+        lat = np.zeros(n_requests)
+        cells = np.zeros(n_requests)
+        done_ns = np.zeros(n_requests, np.int64)
+        ready = threading.Semaphore(0)
+
+        def poller():
+            for i in range(n_requests):
+                ready.acquire()
+                r, dn = srv.poll(tickets[i], packed[i % n_distinct].n, wait_ms=-1)
+                lat[i] = (dn - sched_ns[i]) / 1e6
+                done_ns[i] = dn
+                cells[i] = int(r["left_cells"].sum() + r["right_cells"].sum())
+
+        th = threading.Thread(target=poller)
+        th.start()
+        start = time.monotonic_ns() + 2_000_000
+        for i in range(n_requests):
+            sched_ns[i] = start + int(arrivals[i] * 1e9)
+            while time.monotonic_ns() < sched_ns[i]:
+                pass
+            tickets[i] = srv.submit(packed[i % n_distinct])
+            ready.release()
+        th.join()
+        window = (done_ns.max() - start) / 1e9
+        st = srv.stats()
+    finally:
+        srv.close()
+    return {"requests": n_requests, "distinct_requests": n_distinct,
+            "saturation_requests_per_s": round(r_sat, 1), "load": load,
+            "rate_requests_per_s": round(rate, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "gcups": round(float(cells.sum()) / window / 1e9, 2),
+            "slots": slots, "max_batch_pairs": max_batch, "graph": bool(graph),
+            "batches": st["batches"], "max_inflight": st["max_inflight"],
+            "workload": synth.WORKLOADS["serving"].describe}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +151,17 @@ def main():
     ap.add_argument("--sched", default="auto", choices=["auto", "plain", "persistent"])
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=4000,
+                    help="requests of the serving leg (0 = skip it)")
+    ap.add_argument("--serving-distinct", type=int, default=1000,
+                    help="distinct generated requests the serving leg cycles through")
+    ap.add_argument("--serving-load", type=float, default=0.7)
+    ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-batch", type=int, default=2048)
+    ap.add_argument("--serving-graph", type=int, default=1)
+    ap.add_argument("--graph", action="store_true",
+                    help="time hipGraph replays of the step (stage times then come from one "
+                         "extra profiled eager step)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic, to scale HBM byte counters)")
@@ -113,9 +198,12 @@ def main():
              "persistent": xdrop.SCHED_PERSISTENT}[args.sched]
     opts = xdrop.make_opts(sched=sched, profile=1)
     stream = torch.cuda.current_stream()
+    if args.graph:
+        stream = torch.cuda.Stream()
+        gopts = xdrop.make_opts(sched=sched, graph=1)
 
     for _ in range(args.warmup):
-        ctx.extend_device(db, stream=stream, opts=opts)
+        ctx.extend_device(db, stream=stream, opts=gopts if args.graph else opts)
     torch.cuda.synchronize()
     res = db.results() if args.warmup else None
 
@@ -123,13 +211,23 @@ def main():
     tier_cells = np.zeros(7)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.extend_device(db, stream=stream, opts=opts)
-        st = ctx.stats()                      # synchronises; reads the step's HIP events
-        stage_ms += st["stage_ms"]
-        tier_cells += st["cells"]
-    torch.cuda.synchronize()
+    if args.graph:
+        for _ in range(args.steps):
+            ctx.extend_device(db, stream=stream, opts=gopts)
+        torch.cuda.synchronize()
+    else:
+        for _ in range(args.steps):
+            ctx.extend_device(db, stream=stream, opts=opts)
+            st = ctx.stats()                  # synchronises; reads the step's HIP events
+            stage_ms += st["stage_ms"]
+            tier_cells += st["cells"]
+        torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    if args.graph:                            # stage times of one profiled eager step
+        ctx.extend_device(db, stream=stream, opts=opts)
+        st = ctx.stats()
+        stage_ms += st["stage_ms"] * args.steps
+        tier_cells += st["cells"] * args.steps
     res2 = db.results()
     if res is not None:
         assert np.array_equal(res2["score"], res["score"]), "results changed between steps"
@@ -164,7 +262,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl.describe}", "pairs": n_pairs,
                    "jobs": 2 * n_pairs, "x": wl.x, "scores": [1, -1, -1], "seed_k": 17,
-                   "sched": args.sched, "cells_per_step": cells_per_step},
+                   "sched": args.sched, "graph": bool(args.graph),
+                   "cells_per_step": cells_per_step},
         "roofline": {"bound": "alu", "kernel": kname,
                      "achieved": round(achieved, 3), "peak": round(INT32_PEAK_TOPS, 3),
                      "unit": "TOP/s (int32 lane ops)", "frac": round(achieved / INT32_PEAK_TOPS, 4),
@@ -177,6 +276,11 @@ def main():
                           "combine"], stage_ms)}},
     }
     ctx.close()
+    del db
+    if args.serving_requests:
+        line["serving"] = serving_leg(args.serving_distinct, args.serving_requests,
+                                      args.serving_load, args.serving_slots, args.serving_batch,
+                                      bool(args.serving_graph), min(16, os.cpu_count() or 1))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget, n_pairs)
     print(json.dumps(line), flush=True)

@@ -92,14 +92,18 @@ typedef struct {
                              1..5; 6 = straight to the global-memory tier)      */
     int32_t waves_per_cu; /* persistent grid: waves per compute unit (0 = auto) */
     int32_t sort_jobs;    /* persistent: 1 = longest estimated job first        */
-    int32_t short_long_split; /* 0 = off; else jobs with m+n below this go to
-                                 the plain kernel, the rest to the queue        */
+    int32_t long_job;     /* 0 = off; else jobs with m + n >= long_job start
+                             long_tier_bias tiers wider than X suggests         */
+    int32_t long_tier_bias; /* 0..5, see long_job                              */
     int32_t profile;      /* 1 = time every stage with HIP events (see
-                             xd_last_stats)                                     */
+                             xd_last_stats); not combined with graph            */
     int32_t impl;         /* 0 = hand-scheduled loops where available, 1 = the
                              portable C loops only (same results; for testing)  */
+    int32_t graph;        /* 1 = capture the launch sequence in a hipGraph on
+                             the first call and replay it while every argument
+                             stays the same; needs a non-NULL stream            */
     int32_t reserved;
-} xd_opts;
+} xd_opts; /* 40 bytes */
 
 /* Statistics of the last xdrop_extend on a context.  Tier t in 0..5 runs C =
  * 2^t cells per lane (a window of 64*C diagonals); tier 6 keeps the band in
@@ -159,6 +163,77 @@ xd_status xdrop_extend_host(xd_ctx *ctx, const uint32_t *a, uint64_t a_words,
 /* Statistics of the last xdrop_extend on this context (synchronises the
  * context's device first). */
 xd_status xd_last_stats(xd_ctx *ctx, xd_stats *out);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.
+ *
+ * Requests (1 .. max_batch_pairs pairs with their own packed reads) are
+ * submitted from any host thread and queue in arrival order.  A scheduler
+ * thread owned by the server forms a batch from the head of the queue as soon
+ * as one of its `slots` is free: it admits requests while the batch's packed
+ * reads and pair records fit in the slot's device memory (its share of
+ * mem_budget), copies them to the device, where they stay until the batch is
+ * done, and launches xdrop_extend on the slot's own stream.  Requests that
+ * arrive while other batches run are admitted into the next free slot, so
+ * their kernels overlap with the batches already on the device.  Results are
+ * the same whether a request runs alone or in a mix (every pair is an
+ * independent extension).
+ * ------------------------------------------------------------------------- */
+typedef struct xd_server xd_server;
+
+typedef struct {
+    int32_t device;
+    int32_t slots;            /* batches in flight at once, 1..16 (0 = 4)           */
+    int32_t max_batch_pairs;  /* pairs per batch (0 = 2048)                         */
+    int32_t graph;            /* 1 = every slot replays a captured hipGraph of
+                                 xdrop_extend (batches padded to max_batch_pairs)  */
+    uint64_t mem_budget;      /* device bytes for all slots' request memory
+                                 (0 = 1 GiB); each slot holds an equal share       */
+    xd_opts extend_opts;      /* launch options of every batch (graph and
+                                 profile are set by the server)                     */
+} xd_server_opts; /* 64 bytes */
+
+/* One request: host buffers, read by xd_server_submit before it returns. */
+typedef struct {
+    const uint32_t *a;        /* packed reads A of this request (a_words words)    */
+    uint64_t a_words;
+    const uint32_t *b;        /* packed reads B (b_words words)                    */
+    uint64_t b_words;
+    const xd_pair *pairs;     /* n_pairs pairs; offsets into this request's reads  */
+    uint32_t n_pairs;
+    xd_scores scores;         /* batches only mix requests with equal scores        */
+} xd_request; /* 56 bytes */
+
+/* Creates a server and its scheduler thread.  XD_EINVAL for bad options,
+ * XD_ENOMEM if the device memory of the slots cannot be allocated. */
+xd_status xd_server_create(const xd_server_opts *opts, xd_server **out);
+
+/* Queues a request (its data are copied) and returns its ticket.
+ * XD_EINVAL if the request is empty, larger than one slot can hold, or its
+ * scores are unsupported; pair-level problems are reported per pair. */
+xd_status xd_server_submit(xd_server *srv, const xd_request *req, uint64_t *ticket);
+
+/* Waits up to wait_ms (0 = do not wait, -1 = forever) for a ticket.  When it
+ * is done, copies its n_pairs results to out, stores the host steady-clock
+ * time (nanoseconds, CLOCK_MONOTONIC) at which the scheduler saw the batch
+ * complete in done_ns (if not NULL), releases the ticket and returns XD_OK.
+ * XD_ENOTREADY if not done in time; XD_EINVAL for an unknown ticket;
+ * XD_EDEVICE if its batch failed. */
+xd_status xd_server_poll(xd_server *srv, uint64_t ticket, xd_result *out, int32_t wait_ms,
+                         uint64_t *done_ns);
+
+typedef struct {
+    uint64_t requests, pairs, batches; /* completed                               */
+    uint64_t cells;                    /* cells of completed requests             */
+    uint64_t queued;                   /* requests waiting for admission now      */
+    uint64_t max_inflight;             /* most batches on the device at once      */
+} xd_server_stats;
+
+xd_status xd_server_get_stats(xd_server *srv, xd_server_stats *out);
+
+/* Stops the scheduler after the batches on the device finish; tickets not
+ * yet admitted are dropped.  Safe on NULL. */
+void xd_server_destroy(xd_server *srv);
 
 const char *xd_last_error(void);
 

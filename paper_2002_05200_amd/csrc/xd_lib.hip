@@ -4,9 +4,12 @@
 //   k_reset    clears the per-tier counters and statistics
 //   k_plan     one thread per pair: validation, seed split into a left and a
 //              right job (Section IV-B), initial lane-width tier from X, and a
-//              sort key (tier, then estimated anti-diagonals, longest first)
-//   radix sort all jobs by that key (hipCUB); k_offsets finds each tier's
-//              segment of the sorted order
+//              counting-sort bin (tier, then estimated anti-diagonals in
+//              logarithmic buckets, longest first)
+//   k_scan, k_scatter  counting sort of all jobs by bin; each tier's segment
+//              of the order
+// Every step is a kernel (no memset, no host round trip), so the whole
+// sequence can be captured in a graph.
 //   k_extend   per tier (cells per lane C = 1, 2, 4, 8, 16, 32): one wavefront
 //              per job, taking the tier's segment of the sorted order and then
 //              the jobs escalated into it; a job whose band outgrows its
@@ -18,7 +21,6 @@
 // (Section IV-B inter-sequence parallelism without relaunches), longest
 // estimated job first so no long job starts last.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstdio>
@@ -40,7 +42,8 @@ namespace xd {
 constexpr int kBlock = 256;                 // 4 wavefronts, each its own job
 constexpr int kWavesPerBlock = kBlock / kWave;
 
-__global__ void k_reset(int32_t *counters, unsigned long long *stats) {
+__global__ void k_reset(int32_t *counters, unsigned long long *stats, int32_t *bins) {
+  for (int i = threadIdx.x; i < 2 * kBins; i += blockDim.x) bins[i] = 0;   // counts, cursors
   if (threadIdx.x < kCounters) counters[threadIdx.x] = 0;
   if (threadIdx.x < kStats) stats[threadIdx.x] = 0;
 }
@@ -50,49 +53,101 @@ __device__ __forceinline__ void record_done(unsigned long long *stats, int tier,
   atomicAdd(&stats[kLists + tier], (unsigned long long)cells);
 }
 
-__device__ __forceinline__ uint64_t sort_key(const Job &j, int tier, bool by_cost) {
-  const uint64_t cost = by_cost ? (uint64_t)(j.m + j.n) : 0;   // anti-diagonals
-  return ((uint64_t)tier << 40) | ((1ull << 40) - 1 - cost);
+__device__ __forceinline__ int32_t job_bin(const Job &j, int tier, bool by_cost) {
+  const int cb = by_cost ? cost_bucket((uint32_t)(j.m + j.n)) : 0;   // anti-diagonals
+  return tier * kCostBuckets + (kCostBuckets - 1 - cb);
 }
 
-__global__ void k_plan(const xd_pair *__restrict__ pairs, int64_t n_pairs, int64_t a_words,
-                       int64_t b_words, int32_t match, int32_t mismatch, int32_t gap,
-                       int32_t min_tier, int32_t by_cost, Job *__restrict__ jobs,
-                       int32_t *__restrict__ pair_status, uint64_t *__restrict__ keys,
-                       int32_t *__restrict__ ids) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_pairs) return;
-  Job l, r;
-  const int32_t st = plan_pair(pairs[p], a_words, b_words, match, mismatch, gap, &l, &r);
-  pair_status[p] = st;
-  jobs[2 * p] = l;
-  jobs[2 * p + 1] = r;
-  int tl = initial_tier(l), tr = initial_tier(r);
-  if (tl < min_tier) tl = min_tier;
-  if (tr < min_tier) tr = min_tier;
-  keys[2 * p] = sort_key(l, tl, by_cost != 0);
-  keys[2 * p + 1] = sort_key(r, tr, by_cost != 0);
-  ids[2 * p] = (int32_t)(2 * p);
-  ids[2 * p + 1] = (int32_t)(2 * p + 1);
-}
+constexpr int kPlanBlock = 256;   // pairs per block of k_plan / k_scatter
 
-// Segment of each tier in the sorted keys (binary search; no atomics).
-__global__ void k_offsets(const uint64_t *__restrict__ keys, int64_t nj, int32_t *counters) {
-  const int t = threadIdx.x;
-  if (t > kLists) return;
-  const uint64_t target = (uint64_t)t << 40;
-  int64_t lo = 0, hi = nj;   // first key >= target
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (keys[mid] < target) lo = mid + 1; else hi = mid;
-  }
-  __shared__ int32_t bound[kLists + 1];
-  bound[t] = (int32_t)lo;
+// One thread per pair: validation, seed split, initial tier, counting-sort
+// bin of both jobs; bin counts go through a block histogram in LDS.
+__global__ __launch_bounds__(kPlanBlock) void k_plan(
+    const xd_pair *__restrict__ pairs, int64_t n_pairs, int64_t a_words, int64_t b_words,
+    int32_t match, int32_t mismatch, int32_t gap, int32_t min_tier, int32_t by_cost,
+    int32_t long_job, int32_t long_bias, Job *__restrict__ jobs,
+    int32_t *__restrict__ pair_status, int32_t *__restrict__ bin_of,
+    int32_t *__restrict__ bin_count) {
+  __shared__ int32_t hist[kBins];
+  for (int i = threadIdx.x; i < kBins; i += blockDim.x) hist[i] = 0;
   __syncthreads();
-  if (t < kLists) {
-    counters[kOff + t] = bound[t];
-    counters[kInit + t] = bound[t + 1] - bound[t];
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n_pairs) {
+    Job l, r;
+    const int32_t st = plan_pair(pairs[p], a_words, b_words, match, mismatch, gap, &l, &r);
+    pair_status[p] = st;
+    jobs[2 * p] = l;
+    jobs[2 * p + 1] = r;
+    int tl = initial_tier(l), tr = initial_tier(r);
+    if (long_job > 0) {   // long jobs start wider (their bands have longer to grow)
+      if (l.m + l.n >= long_job) tl = min(tl + long_bias, kTiers - 1);
+      if (r.m + r.n >= long_job) tr = min(tr + long_bias, kTiers - 1);
+    }
+    if (tl < min_tier) tl = min_tier;
+    if (tr < min_tier) tr = min_tier;
+    const int32_t bl = job_bin(l, tl, by_cost != 0), br = job_bin(r, tr, by_cost != 0);
+    bin_of[2 * p] = bl;
+    bin_of[2 * p + 1] = br;
+    atomicAdd(&hist[bl], 1);
+    atomicAdd(&hist[br], 1);
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kBins; i += blockDim.x)
+    if (hist[i]) atomicAdd(&bin_count[i], hist[i]);
+}
+
+// Exclusive scan of the bin counts (one block) and each tier's segment.
+constexpr int kScanBlock = 1024;
+static_assert(kBins <= kScanBlock, "one scan thread per bin");
+__global__ __launch_bounds__(kScanBlock) void k_scan(const int32_t *__restrict__ bin_count,
+                                                     int32_t *__restrict__ bin_off,
+                                                     int32_t *counters) {
+  __shared__ int32_t buf[kScanBlock];
+  const int t = threadIdx.x;
+  const int32_t v = t < kBins ? bin_count[t] : 0;
+  buf[t] = v;
+  __syncthreads();
+  for (int sh = 1; sh < kScanBlock; sh <<= 1) {   // inclusive Hillis-Steele scan
+    const int32_t add = t >= sh ? buf[t - sh] : 0;
+    __syncthreads();
+    buf[t] += add;
+    __syncthreads();
+  }
+  if (t < kBins) bin_off[t] = buf[t] - v;
+  if (t < kLists) {
+    const int first = t * kCostBuckets, last = first + kCostBuckets - 1;
+    const int32_t start = buf[first] - bin_count[first];
+    counters[kOff + t] = start;
+    counters[kInit + t] = buf[last] - start;
+  }
+}
+
+// Places every job at its bin's offset: ranks within the block from LDS
+// atomics, one global reservation per bin and block.  The order inside a bin
+// depends on timing; results never depend on the order.
+__global__ __launch_bounds__(kPlanBlock) void k_scatter(const int32_t *__restrict__ bin_of,
+                                                       int64_t nj,
+                                                       const int32_t *__restrict__ bin_off,
+                                                       int32_t *__restrict__ cursor,
+                                                       int32_t *__restrict__ order) {
+  __shared__ int32_t cnt[kBins];
+  __shared__ int32_t base[kBins];
+  for (int i = threadIdx.x; i < kBins; i += blockDim.x) cnt[i] = 0;
+  __syncthreads();
+  const int64_t j0 = (int64_t)blockIdx.x * (2 * kPlanBlock) + 2 * threadIdx.x;
+  int32_t b[2] = {-1, -1}, rank[2] = {0, 0};
+  for (int q = 0; q < 2; ++q) {
+    if (j0 + q < nj) {
+      b[q] = bin_of[j0 + q];
+      rank[q] = atomicAdd(&cnt[b[q]], 1);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kBins; i += blockDim.x)
+    if (cnt[i]) base[i] = bin_off[i] + atomicAdd(&cursor[i], cnt[i]);
+  __syncthreads();
+  for (int q = 0; q < 2; ++q)
+    if (b[q] >= 0) order[base[b[q]] + rank[q]] = (int32_t)(j0 + q);
 }
 
 // One job per wavefront.  Plain: wave w of the grid takes work item w.
@@ -206,13 +261,10 @@ struct xd_ctx {
   Job *jobs = nullptr;
   JobOut *outs = nullptr;
   int32_t *pair_status = nullptr;
-  uint64_t *keys = nullptr;      // sort keys of all jobs (in, out)
-  uint64_t *keys_sorted = nullptr;
-  int32_t *ids = nullptr;        // job ids before and after sorting
+  int32_t *bin_of = nullptr;     // counting-sort bin of every job
+  int32_t *bins = nullptr;       // kBins counts, kBins cursors, kBins offsets
   int32_t *order = nullptr;
   int32_t *esc = nullptr;        // kLists escalation lists of 2 * cap_pairs entries
-  void *sort_tmp = nullptr;
-  size_t sort_tmp_bytes = 0;
   int32_t *counters = nullptr;   // kCounters
   unsigned long long *stats = nullptr;  // kStats
   uint32_t *dummy = nullptr;     // one zero word for empty arenas
@@ -221,6 +273,10 @@ struct xd_ctx {
   bool profiled = false;
   SpillScratch spill;
   hipStream_t own_stream = nullptr;
+  // graph of the last graph-mode call and the arguments it was captured for
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<uint8_t> graph_sig;
   std::mutex mu;
 };
 
@@ -233,21 +289,14 @@ xd_status ensure_capacity(xd_ctx *c, int64_t n_pairs) {
   int64_t cap = std::max<int64_t>(n_pairs, 1024);
   if (c->cap_pairs > 0) cap = std::max<int64_t>(cap, c->cap_pairs * 3 / 2);
   const int64_t nj = 2 * cap;
-  size_t sort_bytes = 0;
-  if (hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint64_t *)nullptr,
-                                         (uint64_t *)nullptr, (const int32_t *)nullptr,
-                                         (int32_t *)nullptr, (int)nj, 0, kKeyBits) != hipSuccess)
-    return fail(XD_EDEVICE, "radix sort sizing failed");
   size_t off = 0;
   const size_t o_jobs = off; off = align_up(off + sizeof(Job) * nj);
   const size_t o_outs = off; off = align_up(off + sizeof(JobOut) * nj);
   const size_t o_stat = off; off = align_up(off + sizeof(int32_t) * cap);
-  const size_t o_keys = off; off = align_up(off + sizeof(uint64_t) * nj);
-  const size_t o_keys2 = off; off = align_up(off + sizeof(uint64_t) * nj);
-  const size_t o_ids = off; off = align_up(off + sizeof(int32_t) * nj);
+  const size_t o_binof = off; off = align_up(off + sizeof(int32_t) * nj);
+  const size_t o_bins = off; off = align_up(off + sizeof(int32_t) * 3 * kBins);
   const size_t o_order = off; off = align_up(off + sizeof(int32_t) * nj);
   const size_t o_esc = off; off = align_up(off + sizeof(int32_t) * nj * kLists);
-  const size_t o_sort = off; off = align_up(off + sort_bytes);
   const size_t o_cnt = off; off = align_up(off + sizeof(int32_t) * kCounters);
   const size_t o_stats = off; off = align_up(off + sizeof(unsigned long long) * kStats);
   const size_t o_dummy = off; off = align_up(off + 64);
@@ -262,17 +311,16 @@ xd_status ensure_capacity(xd_ctx *c, int64_t n_pairs) {
   if (hipMalloc(&p, off) != hipSuccess) return fail(XD_ENOMEM, "hipMalloc of job scratch failed");
   c->scratch.ptr = p;
   c->scratch.bytes = off;
+  if (!c->spill.buf && spill_alloc(&c->spill) != XD_OK)
+    return fail(XD_ENOMEM, "hipMalloc of the global-memory band buffers failed");
   char *b = (char *)p;
   c->jobs = (Job *)(b + o_jobs);
   c->outs = (JobOut *)(b + o_outs);
   c->pair_status = (int32_t *)(b + o_stat);
-  c->keys = (uint64_t *)(b + o_keys);
-  c->keys_sorted = (uint64_t *)(b + o_keys2);
-  c->ids = (int32_t *)(b + o_ids);
+  c->bin_of = (int32_t *)(b + o_binof);
+  c->bins = (int32_t *)(b + o_bins);
   c->order = (int32_t *)(b + o_order);
   c->esc = (int32_t *)(b + o_esc);
-  c->sort_tmp = (void *)(b + o_sort);
-  c->sort_tmp_bytes = sort_bytes;
   c->counters = (int32_t *)(b + o_cnt);
   c->stats = (unsigned long long *)(b + o_stats);
   c->dummy = (uint32_t *)(b + o_dummy);
@@ -324,6 +372,85 @@ hipError_t launch_tiers(xd_ctx *c, hipStream_t s, bool persistent, int waves_per
   if ((e = mark(6)) != hipSuccess) return e;
   if ((e = launch_tier<32, NARROW>(c, s, persistent, w(5), nj, 5, P)) != hipSuccess) return e;
   return mark(7);
+}
+
+}  // namespace
+
+namespace {
+
+// Arguments of one xdrop_extend call.
+struct Launch {
+  const uint32_t *d_a;
+  uint64_t a_words;
+  const uint32_t *d_b;
+  uint64_t b_words;
+  const xd_pair *d_pairs;
+  size_t n_pairs;
+  xd_scores sc;
+  xd_result *d_out;
+  xd_opts o;
+};
+
+// Enqueues the whole launch sequence of one call on s (kernels and, when
+// profiling, event records only).
+xd_status enqueue(xd_ctx *c, hipStream_t s, const Launch &L, bool prof) {
+  const xd_opts &o = L.o;
+  const xd_scores &sc = L.sc;
+  const size_t n_pairs = L.n_pairs;
+  const bool persistent = (o.sched != XD_SCHED_PLAIN);
+  const int64_t nj = 2 * (int64_t)n_pairs;
+  Params P;
+  P.A = L.a_words ? L.d_a : c->dummy;
+  P.B = L.b_words ? L.d_b : c->dummy;
+  P.a_words = L.a_words ? (int64_t)L.a_words : 1;
+  P.b_words = L.b_words ? (int64_t)L.b_words : 1;
+  P.neg_gap = -sc.gap;
+  P.base = sc.mismatch - 2 * sc.gap;
+  P.delta = sc.match - sc.mismatch;
+  P.pat = (int32_t)((uint32_t)P.delta * 0x55555555u);
+  P.impl = o.impl;
+  P.unit_match = sc.match == 1;
+  const bool narrow = P.delta <= 3;
+
+  if (prof) XD_HIP(hipEventRecord(c->ev[0], s));
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, c->counters, c->stats, c->bins);
+  XD_HIP(hipGetLastError());
+  const int64_t stride = 2 * c->cap_pairs;
+  const bool by_cost = persistent && o.sort_jobs != 0;
+  int32_t *bin_count = c->bins, *bin_cursor = c->bins + kBins, *bin_off = c->bins + 2 * kBins;
+  const unsigned plan_blocks = (unsigned)((n_pairs + kPlanBlock - 1) / kPlanBlock);
+  hipLaunchKernelGGL(k_plan, dim3(plan_blocks), dim3(kPlanBlock), 0, s, L.d_pairs,
+                     (int64_t)n_pairs, (int64_t)P.a_words, (int64_t)P.b_words, sc.match,
+                     sc.mismatch, sc.gap, o.min_tier, (int32_t)by_cost, o.long_job,
+                     o.long_tier_bias, c->jobs, c->pair_status, c->bin_of, bin_count);
+  XD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanBlock), 0, s, bin_count, bin_off, c->counters);
+  XD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_scatter, dim3(plan_blocks), dim3(kPlanBlock), 0, s, c->bin_of, nj,
+                     bin_off, bin_cursor, c->order);
+  XD_HIP(hipGetLastError());
+  if (prof) XD_HIP(hipEventRecord(c->ev[1], s));
+  hipError_t e = narrow ? launch_tiers<true>(c, s, persistent, o.waves_per_cu, nj, P, prof)
+                        : launch_tiers<false>(c, s, persistent, o.waves_per_cu, nj, P, prof);
+  if (e != hipSuccess) return fail(XD_EDEVICE, std::string("k_extend: ") + hipGetErrorString(e));
+  {
+    TierQueue q;
+    q.order = c->order;
+    q.esc = c->esc + kTiers * stride;
+    q.counters = c->counters;
+    q.next_esc = nullptr;
+    q.tier = kTiers;
+    if (spill_launch(&c->spill, s, c->jobs, q, c->counters + kHead + kTiers, c->outs, c->stats,
+                     P) != XD_OK)
+      return fail(XD_EDEVICE, "k_spill launch failed");
+  }
+  if (prof) XD_HIP(hipEventRecord(c->ev[8], s));
+  hipLaunchKernelGGL(k_combine, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s,
+                     L.d_pairs, (int64_t)n_pairs, c->pair_status, c->outs, P.A, P.B, sc.match,
+                     sc.mismatch, L.d_out);
+  XD_HIP(hipGetLastError());
+  if (prof) XD_HIP(hipEventRecord(c->ev[9], s));
+  return XD_OK;
 }
 
 }  // namespace
@@ -389,6 +516,8 @@ void xd_ctx_destroy(xd_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->scratch.ptr) (void)hipFree(c->scratch.ptr);
   spill_free(&c->spill);
   if (c->have_events)
@@ -414,74 +543,78 @@ xd_status xdrop_extend(xd_ctx *c, const uint32_t *d_a, uint64_t a_words, const u
   xd_opts o;
   std::memset(&o, 0, sizeof(o));
   if (opts) o = *opts;
+  else o.sort_jobs = 1;
+  if (o.sched < 0 || o.sched > XD_SCHED_PERSISTENT)
+    return fail(XD_EINVAL, "xdrop_extend: sched out of range");
   if (o.min_tier < 0 || o.min_tier > kTiers)
     return fail(XD_EINVAL, "xdrop_extend: min_tier out of range");
   if (o.impl < 0 || o.impl > 1) return fail(XD_EINVAL, "xdrop_extend: impl out of range");
+  if (o.long_job < 0 || o.long_tier_bias < 0 || o.long_tier_bias >= kTiers)
+    return fail(XD_EINVAL, "xdrop_extend: long_job / long_tier_bias out of range");
+  if (o.waves_per_cu < 0 || o.waves_per_cu > 64)
+    return fail(XD_EINVAL, "xdrop_extend: waves_per_cu out of range");
+  const bool graph = o.graph != 0;
+  if (graph && o.profile) return fail(XD_EINVAL, "xdrop_extend: graph and profile together");
+  if (graph && !stream) return fail(XD_EINVAL, "xdrop_extend: graph mode needs a non-NULL stream");
 
   std::lock_guard<std::mutex> lock(c->mu);
   XD_HIP(hipSetDevice(c->device));
   xd_status st = ensure_capacity(c, (int64_t)n_pairs);
   if (st != XD_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  const bool persistent = (o.sched != XD_SCHED_PLAIN);
-  const int64_t nj = 2 * (int64_t)n_pairs;
-
-  Params P;
-  P.A = a_words ? d_a : c->dummy;
-  P.B = b_words ? d_b : c->dummy;
-  P.a_words = a_words ? (int64_t)a_words : 1;
-  P.b_words = b_words ? (int64_t)b_words : 1;
-  P.neg_gap = -sc.gap;
-  P.base = (int32_t)base;
-  P.delta = (int32_t)delta;
-  P.pat = (int32_t)(delta * 0x55555555u);
-  P.impl = o.impl;
-  P.unit_match = sc.match == 1;
-  const bool narrow = delta <= 3;
-
   const bool prof = o.profile != 0;
   if (prof && !c->have_events) {
     for (int i = 0; i < 10; ++i) XD_HIP(hipEventCreate(&c->ev[i]));
     c->have_events = true;
   }
   c->profiled = prof;
-  if (prof) XD_HIP(hipEventRecord(c->ev[0], s));
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, c->counters, c->stats);
-  XD_HIP(hipGetLastError());
-  const int64_t stride = 2 * c->cap_pairs;
-  const bool by_cost = persistent && (opts ? o.sort_jobs != 0 : true);
-  hipLaunchKernelGGL(k_plan, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s, d_pairs,
-                     (int64_t)n_pairs, (int64_t)P.a_words, (int64_t)P.b_words, sc.match,
-                     sc.mismatch, sc.gap, o.min_tier, (int32_t)by_cost, c->jobs,
-                     c->pair_status, c->keys, c->ids);
-  XD_HIP(hipGetLastError());
-  {
-    size_t tb = c->sort_tmp_bytes;
-    XD_HIP(hipcub::DeviceRadixSort::SortPairs(c->sort_tmp, tb, c->keys, c->keys_sorted, c->ids,
-                                              c->order, (int)nj, 0, kKeyBits, s));
+  Launch L;
+  std::memset(&L, 0, sizeof(L));   // padding too: the struct is compared bytewise
+  L.d_a = d_a; L.a_words = a_words; L.d_b = d_b; L.b_words = b_words;
+  L.d_pairs = d_pairs; L.n_pairs = n_pairs; L.sc = sc; L.d_out = d_out; L.o = o;
+  if (!graph) return enqueue(c, s, L, prof);
+
+  // graph mode: replay while every argument (and the scratch) is unchanged
+  std::vector<uint8_t> sig(sizeof(L) + sizeof(void *));
+  std::memcpy(sig.data(), &L, sizeof(L));
+  std::memcpy(sig.data() + sizeof(L), &c->scratch.ptr, sizeof(void *));
+  if (!c->graph_exec || sig != c->graph_sig) {
+    if (c->graph_exec) { XD_HIP(hipGraphExecDestroy(c->graph_exec)); c->graph_exec = nullptr; }
+    if (c->graph) { XD_HIP(hipGraphDestroy(c->graph)); c->graph = nullptr; }
+    c->graph_sig.clear();
+    XD_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    st = enqueue(c, s, L, false);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != XD_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      if (st != XD_OK) return st;
+      return fail(XD_EDEVICE, std::string("xdrop_extend capture: ") + hipGetErrorString(e));
+    }
+    // every node must be a kernel: memset nodes have misbehaved on replay
+    size_t nn = 0;
+    XD_HIP(hipGraphGetNodes(g, nullptr, &nn));
+    std::vector<hipGraphNode_t> nodes(nn);
+    XD_HIP(hipGraphGetNodes(g, nodes.data(), &nn));
+    for (size_t i = 0; i < nn; ++i) {
+      hipGraphNodeType ty;
+      XD_HIP(hipGraphNodeGetType(nodes[i], &ty));
+      if (ty != hipGraphNodeTypeKernel) {
+        (void)hipGraphDestroy(g);
+        return fail(XD_EDEVICE, "xdrop_extend capture: non-kernel node in the graph");
+      }
+    }
+    hipGraphExec_t ge = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return fail(XD_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    c->graph = g;
+    c->graph_exec = ge;
+    c->graph_sig = sig;
   }
-  hipLaunchKernelGGL(k_offsets, dim3(1), dim3(64), 0, s, c->keys_sorted, nj, c->counters);
-  XD_HIP(hipGetLastError());
-  if (prof) XD_HIP(hipEventRecord(c->ev[1], s));
-  hipError_t e = narrow ? launch_tiers<true>(c, s, persistent, o.waves_per_cu, nj, P, prof)
-                        : launch_tiers<false>(c, s, persistent, o.waves_per_cu, nj, P, prof);
-  if (e != hipSuccess) return fail(XD_EDEVICE, std::string("k_extend: ") + hipGetErrorString(e));
-  {
-    TierQueue q;
-    q.order = c->order;
-    q.esc = c->esc + kTiers * stride;
-    q.counters = c->counters;
-    q.next_esc = nullptr;
-    q.tier = kTiers;
-    st = spill_launch(&c->spill, s, c->jobs, q, c->counters + kHead + kTiers, c->outs, c->stats, P);
-  }
-  if (st != XD_OK) return fail(st, "k_spill launch failed");
-  if (prof) XD_HIP(hipEventRecord(c->ev[8], s));
-  hipLaunchKernelGGL(k_combine, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s,
-                     d_pairs, (int64_t)n_pairs, c->pair_status, c->outs, P.A, P.B, sc.match,
-                     sc.mismatch, d_out);
-  XD_HIP(hipGetLastError());
-  if (prof) XD_HIP(hipEventRecord(c->ev[9], s));
+  XD_HIP(hipGraphLaunch(c->graph_exec, s));
   return XD_OK;
 }
 
@@ -550,3 +683,5 @@ xd_status xd_last_stats(xd_ctx *c, xd_stats *out) {
 }
 
 }  // extern "C"
+
+#include "xd_server.h"

@@ -1,8 +1,10 @@
 // xd_queue.h -- per-tier work queues on the device (library-internal).
 //
-// All jobs are sorted once by (tier, estimated anti-diagonals descending).
-// Tier t works through its segment of that order, then through the jobs
-// escalated into it from tier t - 1 (their band outgrew the narrower window).
+// All jobs are ordered once by (tier, estimated anti-diagonals descending),
+// the latter in logarithmic cost buckets (four per octave), by a counting
+// sort.  Tier t works through its segment of that order, then through the
+// jobs escalated into it from tier t - 1 (their band outgrew the narrower
+// window).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,7 +21,18 @@ constexpr int kInit = 0, kEsc = kLists, kHead = 2 * kLists, kOff = 3 * kLists;
 constexpr int kCounters = 4 * kLists;
 // Device statistics (uint64): jobs finished, cells of those jobs, escalations.
 constexpr int kStats = 3 * kLists;
-constexpr int kKeyBits = 43;   // tier in bits 40..42, inverted cost in 0..39
+
+// Counting-sort bins: kCostBuckets per tier, longest jobs in the lowest bin.
+constexpr int kCostBuckets = 128;
+constexpr int kBins = kLists * kCostBuckets;
+
+// Bucket of an estimated cost (anti-diagonals): exact below 8, then four
+// buckets per power of two.  At most 4 * 29 + 3 for costs below 2^31.
+__device__ __forceinline__ int cost_bucket(uint32_t cost) {
+  if (cost < 8u) return (int)cost;
+  const int lg = 31 - __builtin_clz(cost);
+  return 4 * (lg - 1) + (int)((cost >> (lg - 2)) & 3u);
+}
 
 
 // Job of work item w of a tier: its segment of the sorted order, then the

@@ -135,15 +135,18 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(const Job *__restrict__
   }
 }
 
+inline xd_status spill_alloc(SpillScratch *sp) {
+  if (sp->buf) return XD_OK;
+  void *p = nullptr;
+  if (hipMalloc(&p, sizeof(int32_t) * 3 * kSpillCap * kSpillSlots) != hipSuccess) return XD_ENOMEM;
+  sp->buf = (int32_t *)p;
+  return XD_OK;
+}
+
 inline xd_status spill_launch(SpillScratch *sp, hipStream_t s, const Job *jobs,
                               const TierQueue &q, int32_t *head, JobOut *outs,
                               unsigned long long *stats, const Params &P) {
-  if (!sp->buf) {
-    void *p = nullptr;
-    if (hipMalloc(&p, sizeof(int32_t) * 3 * kSpillCap * kSpillSlots) != hipSuccess)
-      return XD_ENOMEM;
-    sp->buf = (int32_t *)p;
-  }
+  if (!sp->buf) return XD_ENOMEM;
   hipLaunchKernelGGL(k_spill, dim3(kSpillSlots), dim3(kSpillThreads), 0, s, jobs, q, head, outs,
                      stats, P, sp->buf);
   return hipGetLastError() == hipSuccess ? XD_OK : XD_EDEVICE;

@@ -40,14 +40,34 @@ class Scores(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("sched", ctypes.c_int32), ("min_tier", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("sort_jobs", ctypes.c_int32),
-                ("short_long_split", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("impl", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("long_job", ctypes.c_int32), ("long_tier_bias", ctypes.c_int32),
+                ("profile", ctypes.c_int32), ("impl", ctypes.c_int32),
+                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("jobs", ctypes.c_uint64 * 7), ("cells", ctypes.c_uint64 * 7),
                 ("escalated", ctypes.c_uint64 * 7), ("stage_ms", ctypes.c_float * 9),
                 ("profiled", ctypes.c_int32)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("max_batch_pairs", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("mem_budget", ctypes.c_uint64), ("extend_opts", Opts)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_void_p), ("a_words", ctypes.c_uint64),
+                ("b", ctypes.c_void_p), ("b_words", ctypes.c_uint64),
+                ("pairs", ctypes.c_void_p), ("n_pairs", ctypes.c_uint32),
+                ("scores", Scores)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_uint64), ("pairs", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("cells", ctypes.c_uint64),
+                ("queued", ctypes.c_uint64), ("max_inflight", ctypes.c_uint64)]
 
 
 class XdropError(RuntimeError):
@@ -81,6 +101,16 @@ def lib() -> ctypes.CDLL:
         L.xdrop_extend_host.restype = i32
         L.xd_last_stats.argtypes = [p, ctypes.POINTER(Stats)]
         L.xd_last_stats.restype = i32
+        L.xd_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(p)]
+        L.xd_server_create.restype = i32
+        L.xd_server_submit.argtypes = [p, ctypes.POINTER(Request), ctypes.POINTER(u64)]
+        L.xd_server_submit.restype = i32
+        L.xd_server_poll.argtypes = [p, u64, p, ctypes.c_int32, ctypes.POINTER(u64)]
+        L.xd_server_poll.restype = i32
+        L.xd_server_get_stats.argtypes = [p, ctypes.POINTER(ServerStats)]
+        L.xd_server_get_stats.restype = i32
+        L.xd_server_destroy.argtypes = [p]
+        L.xd_server_destroy.restype = None
         L.xd_last_error.argtypes = []
         L.xd_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -152,12 +182,12 @@ class DeviceBatch:
 
 
 def make_opts(sched: int = SCHED_AUTO, min_tier: int = 0, waves_per_cu: int = 0,
-              sort_jobs: int = 1, short_long_split: int = 0, profile: int = 0,
-              impl: int = 0) -> Opts:
+              sort_jobs: int = 1, long_job: int = 0, long_tier_bias: int = 0,
+              profile: int = 0, impl: int = 0, graph: int = 0) -> Opts:
     o = Opts()
     o.sched, o.min_tier, o.waves_per_cu = sched, min_tier, waves_per_cu
-    o.sort_jobs, o.short_long_split, o.profile = sort_jobs, short_long_split, profile
-    o.impl = impl
+    o.sort_jobs, o.long_job, o.long_tier_bias = sort_jobs, long_job, long_tier_bias
+    o.profile, o.impl, o.graph = profile, impl, graph
     return o
 
 
@@ -219,3 +249,62 @@ class Context:
         if st.profiled:
             out["stage_ms"] = np.array(list(st.stage_ms), np.float64)
         return out
+
+
+class PackedRequest:
+    """A request ready to submit: packed reads and pair records on the host."""
+
+    def __init__(self, bt):
+        self.n = bt.n
+        self.a_words = pack_codes(bt.a)
+        self.b_words = pack_codes(bt.b)
+        self.pairs = make_pairs(bt)
+        self.req = Request(self.a_words.ctypes.data, len(self.a_words), self.b_words.ctypes.data,
+                           len(self.b_words), self.pairs.ctypes.data, bt.n, Scores(*bt.scores))
+
+
+class Server:
+    """xd_server: continuous batching of extension requests on one device."""
+
+    def __init__(self, device: int = 0, slots: int = 4, max_batch_pairs: int = 2048,
+                 graph: int = 0, mem_budget: int = 0, opts: Optional[Opts] = None):
+        torch.cuda.init()
+        o = ServerOpts()
+        o.device, o.slots, o.max_batch_pairs, o.graph = device, slots, max_batch_pairs, graph
+        o.mem_budget = mem_budget
+        o.extend_opts = opts if opts is not None else make_opts()
+        h = ctypes.c_void_p()
+        _check(lib().xd_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self.h = h
+
+    def submit(self, req: PackedRequest) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().xd_server_submit(self.h, ctypes.byref(req.req), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, n_pairs: int, wait_ms: int = -1):
+        """(results, done_ns) once the ticket is done, else None."""
+        out = np.zeros(n_pairs, RESULT_DTYPE)
+        done = ctypes.c_uint64()
+        st = lib().xd_server_poll(self.h, ticket, out.ctypes.data_as(ctypes.c_void_p), wait_ms,
+                                  ctypes.byref(done))
+        if st == XD_ENOTREADY:
+            return None
+        _check(st)
+        return out, done.value
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().xd_server_get_stats(self.h, ctypes.byref(st)))
+        return {k: int(getattr(st, k)) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.h:
+            lib().xd_server_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -30,7 +30,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ["xdrop_extend", "xdrop_extend_host", "xd_pack", "xd_pack_codes", "xd_ctx_create",
-              "xd_ctx_destroy", "xd_last_error", "xd_last_stats"]:
+              "xd_ctx_destroy", "xd_last_error", "xd_last_stats", "xd_server_create",
+              "xd_server_submit", "xd_server_poll", "xd_server_get_stats", "xd_server_destroy"]:
         assert n in names
 
 
@@ -97,5 +98,17 @@ def test_struct_layouts_match_header():
     text = open(HEADER).read()
     assert "/* 40 bytes */" in text and xdrop.PAIR_DTYPE.itemsize == 40
     assert "/* 56 bytes */" in text and xdrop.RESULT_DTYPE.itemsize == 56
-    assert ctypes.sizeof(xdrop.Opts) == 32
+    assert "/* 40 bytes */" in text and ctypes.sizeof(xdrop.Opts) == 40
     assert ctypes.sizeof(xdrop.Stats) == 3 * 7 * 8 + 9 * 4 + 4
+    assert "} xd_server_opts; /* 64 bytes */" in text and ctypes.sizeof(xdrop.ServerOpts) == 64
+    assert "} xd_request; /* 56 bytes */" in text and ctypes.sizeof(xdrop.Request) == 56
+    assert ctypes.sizeof(xdrop.ServerStats) == 6 * 8
+
+
+def test_server_rejects_null_arguments_without_a_device(L):
+    from paper_2002_05200_amd import xdrop
+    assert L.xd_server_create(None, None) == xdrop.XD_EINVAL
+    assert L.xd_server_submit(None, None, None) == xdrop.XD_EINVAL
+    assert L.xd_server_poll(None, 1, None, 0, None) == xdrop.XD_EINVAL
+    assert L.xd_server_get_stats(None, None) == xdrop.XD_EINVAL
+    L.xd_server_destroy(None)

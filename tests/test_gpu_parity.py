@@ -205,3 +205,55 @@ def test_full_size_batch10k(ctx, xd):
     idx = np.linspace(0, bt.n - 1, 64).astype(np.int64)
     sub = bt.subset(idx)
     assert_same(got[idx], oracle_of(sub), "batch10k full-size, sampled pairs")
+
+
+# ------------------------------------------------------------ batch execution
+def test_launch_options_do_not_change_results(ctx, xd):
+    """Unsorted order, long jobs started wider, other persistent grid sizes:
+    same results as the oracle."""
+    from paper_2002_05200_amd import synth
+    bt = synth.concat([synth.random_cases(seed=500, n=150, len_lo=17, len_hi=2500,
+                                          x_choices=(0, 3, 10, 50, 100, 300)),
+                       synth.make_batch("uneven", n=24, start=5, stride=7919)], name="opts")
+    ref = oracle_of(bt)
+    for kw in [dict(sort_jobs=0), dict(long_job=1000, long_tier_bias=2),
+               dict(long_job=1, long_tier_bias=5), dict(waves_per_cu=4),
+               dict(sched=1, long_job=500, long_tier_bias=1)]:
+        assert_same(run(ctx, xd, bt, **kw), ref, f"opts {kw}")
+
+
+def test_graph_replays_match_eager(ctx, xd):
+    """Graph mode: the captured launch sequence replayed several times, with
+    eager calls and other device work between the replays, and once more
+    after the pair records changed in place (same buffers, new X)."""
+    import torch
+    from paper_2002_05200_amd import synth
+    bt = synth.concat([synth.random_cases(seed=600, n=200, len_lo=17, len_hi=1500,
+                                          x_choices=(0, 2, 10, 50, 200)),
+                       synth.make_batch("batch10k", n=16, start=3, stride=4001)], name="graph")
+    ref = oracle_of(bt)
+    db = xd.DeviceBatch(bt, "cuda:0")
+    s = torch.cuda.Stream()
+    eager = xd.make_opts()
+    graph = xd.make_opts(graph=1)
+    noise = torch.ones(1 << 20, device="cuda:0")
+    for rep in range(4):
+        print(f"graph replay {rep}", flush=True)
+        db.d_out.zero_()
+        ctx.extend_device(db, stream=s, opts=graph)
+        s.synchronize()
+        assert_same(db.results(), ref, f"graph replay {rep}")
+        ctx.extend_device(db, opts=eager)          # eager call on another stream between
+        noise.mul_(1.0001).sum().item()
+        torch.cuda.synchronize()
+        assert_same(db.results(), ref, f"eager after replay {rep}")
+    # same buffers, new contents: X of every pair changed
+    bt2 = synth.from_pairs([bt.pair(p)[0] for p in range(bt.n)], [bt.pair(p)[1] for p in range(bt.n)],
+                           bt.a_seed, bt.b_seed, (bt.x * 2 + 1) % 301, name="graph-x")
+    ref2 = oracle_of(bt2)
+    pr = xd.make_pairs(bt2)
+    db.d_pairs.copy_(torch.from_numpy(pr.view(np.uint8).reshape(-1)))
+    torch.cuda.synchronize()
+    ctx.extend_device(db, stream=s, opts=graph)
+    s.synchronize()
+    assert_same(db.results(), ref2, "graph replay after the pairs changed")
