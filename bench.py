@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--serving-batch", type=int, default=2048)
     ap.add_argument("--serving-graph", type=int, default=1)
+    ap.add_argument("--tuned", action="store_true",
+                    help="launch options from the autotuner's table for this workload class")
     ap.add_argument("--graph", action="store_true",
                     help="time hipGraph replays of the step (stage times then come from one "
                          "extra profiled eager step)")
@@ -181,6 +183,13 @@ def main():
     bt = synth.make_batch(args.workload, n=n_pairs, workers=min(16, os.cpu_count() or 1))
     print(f"[bench] generated {bt.n} pairs ({bt.total_bases()/1e9:.2f} Gbases) in "
           f"{time.time()-t0:.1f} s", file=sys.stderr, flush=True)
+    tuned = {}
+    if args.tuned:
+        from paper_2002_05200_amd import tune
+        tuned = tune.lookup(bt) or {}
+        tuned.pop("sched", None)
+        print(f"[bench] tuned options for {tune.batch_class(bt)}: {tuned}", file=sys.stderr,
+              flush=True)
     t0 = time.time()
     db = xdrop.DeviceBatch(bt, "cuda:0")
     del bt.a, bt.b
@@ -196,11 +205,11 @@ def main():
     ctx = xdrop.Context(0)
     sched = {"auto": xdrop.SCHED_AUTO, "plain": xdrop.SCHED_PLAIN,
              "persistent": xdrop.SCHED_PERSISTENT}[args.sched]
-    opts = xdrop.make_opts(sched=sched, profile=1)
+    opts = xdrop.make_opts(sched=sched, profile=1, **tuned)
     stream = torch.cuda.current_stream()
     if args.graph:
         stream = torch.cuda.Stream()
-        gopts = xdrop.make_opts(sched=sched, graph=1)
+        gopts = xdrop.make_opts(sched=sched, graph=1, **tuned)
 
     for _ in range(args.warmup):
         ctx.extend_device(db, stream=stream, opts=gopts if args.graph else opts)
@@ -262,7 +271,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl.describe}", "pairs": n_pairs,
                    "jobs": 2 * n_pairs, "x": wl.x, "scores": [1, -1, -1], "seed_k": 17,
-                   "sched": args.sched, "graph": bool(args.graph),
+                   "sched": args.sched, "graph": bool(args.graph), "tuned": tuned or None,
                    "cells_per_step": cells_per_step},
         "roofline": {"bound": "alu", "kernel": kname,
                      "achieved": round(achieved, 3), "peak": round(INT32_PEAK_TOPS, 3),

@@ -268,9 +268,96 @@ XD_FN bool recenter(Band<C> &bd, Scalars &st) {
   return true;
 }
 
-// Whole one-directional extension of `job` on the calling wavefront.
+// Escalation saves.  A wave whose band outgrows its window stores the state
+// of the anti-diagonal it was about to compute -- its number, pending range
+// and window base in slot coordinates, best, best cell, both W-form
+// thresholds, the cells so far, and the latest even and odd anti-diagonals
+// in slot order -- so that the next tier continues from there instead of
+// starting over.  When the pool is full the job simply restarts.
+XD_FN void save_scalars(int32_t *sv, int32_t d, int32_t lo, int32_t hi, int32_t h, int32_t best,
+                        int32_t bi, int32_t bj, int32_t bw, int32_t thr, int32_t C,
+                        uint64_t cells) {
+  store_first(sv + kSvD, d);
+  store_first(sv + kSvLo, lo);
+  store_first(sv + kSvHi, hi);
+  store_first(sv + kSvH, h);
+  store_first(sv + kSvBest, best);
+  store_first(sv + kSvBi, bi);
+  store_first(sv + kSvBj, bj);
+  store_first(sv + kSvBw, bw);
+  store_first(sv + kSvThr, thr);
+  store_first(sv + kSvC, C);
+  store_first(sv + kSvCellsLo, (int32_t)(uint32_t)cells);
+  store_first(sv + kSvCellsHi, (int32_t)(uint32_t)(cells >> 32));
+}
+
+// The save slot of job j (its own from an earlier escalation, else a new
+// one); nullptr when the pool is exhausted.
+XD_FN int32_t *save_reserve(const Params &P, int32_t j, int32_t S) {
+  if (!P.save_pool || j < 0 || 2 * S + kSaveHdr > kSaveSlotWords) return nullptr;
+  const int32_t own = P.job_save[j];
+  if (own >= 0) return P.save_pool + own;
+  const uint32_t slot = atomic_add_first(P.save_top, 1ull);
+  if ((unsigned long long)slot >= P.save_cap) return nullptr;
+  return P.save_pool + (int64_t)slot * kSaveSlotWords;
+}
+
+XD_FN void save_publish(const Params &P, int32_t j, const int32_t *sv) {
+  store_first(P.job_save + j, (int32_t)(sv - P.save_pool));
+}
+
+template <int C>
+XD_FN void save_band(const Band<C> &bd, const Scalars &st, const Params &P, int32_t j) {
+  constexpr int S = kWave * C;
+  int32_t *sv = save_reserve(P, j, S);
+  if (!sv) return;
+  save_scalars(sv, st.d, st.lo, st.hi, st.h, st.best, st.bi, st.bj, st.bw, st.thr, C,
+               st.cells + st.cells_blk);
+  const vint s0 = lane_index() * C;
+#pragma unroll
+  for (int r = 0; r < C; ++r) {
+    store_vec(sv + kSaveHdr, s0 + r, bd.E[r]);
+    store_vec(sv + kSaveHdr + S, s0 + r, bd.O[r]);
+  }
+  save_publish(P, j, sv);
+}
+
+// Restores a save of a narrower tier into the middle of this tier's window.
+template <int C>
+XD_FN bool restore_band(Band<C> &bd, Scalars &st, const Params &P, int32_t j) {
+  if (!P.save_pool || j < 0) return false;
+  const int32_t off = P.job_save[j];
+  if (off < 0) return false;
+  const int32_t *sv = P.save_pool + off;
+  const int32_t cs = sv[kSvC];
+  constexpr int S = kWave * C;
+  if (cs >= C) return false;
+  const int32_t ss = kWave * cs;
+  const int32_t shift = (S - ss) / 2;
+  st.d = sv[kSvD];
+  st.lo = sv[kSvLo] + shift;
+  st.hi = sv[kSvHi] + shift;
+  st.h = sv[kSvH] - shift;
+  st.best = sv[kSvBest]; st.bi = sv[kSvBi]; st.bj = sv[kSvBj];
+  st.bw = sv[kSvBw]; st.thr = sv[kSvThr];
+  st.cells = (uint64_t)(uint32_t)sv[kSvCellsLo] | ((uint64_t)(uint32_t)sv[kSvCellsHi] << 32);
+  st.cells_blk = 0;
+  const vint s0 = lane_index() * C;
+#pragma unroll
+  for (int r = 0; r < C; ++r) {
+    const vint old = s0 + (r - shift);
+    const vbool in = le_u(old, (uint32_t)(ss - 1));
+    const vint k = select(in, old, 0);
+    bd.E[r] = select(in, load_vec(sv + kSaveHdr, k), kNeg);
+    bd.O[r] = select(in, load_vec(sv + kSaveHdr + ss, k), kNeg);
+  }
+  return true;
+}
+
+// Whole one-directional extension of job j on the calling wavefront, resumed
+// from a narrower tier's save when there is one.
 template <int C, bool NARROW>
-XD_FN JobOut extend_job(const Job &job, const Params &P) {
+XD_FN JobOut extend_job(const Job &job, const Params &P, int32_t j) {
   constexpr int S = kWave * C;
   JobOut out;
   out.best = 0; out.bi = 0; out.bj = 0; out.status = kJobOk; out.cells = 0;
@@ -283,52 +370,56 @@ XD_FN JobOut extend_job(const Job &job, const Params &P) {
   jv.m = job.m; jv.n = job.n; jv.x = job.x; jv.dir = job.dir;
 
   Band<C> bd;
-#pragma unroll
-  for (int r = 0; r < C; ++r) { bd.E[r] = splat(kNeg); bd.O[r] = splat(kNeg); }
-  // anti-diagonal 0: the origin (score 0) in slot S/2 = lane 32, register 0
-  bd.E[0] = select(lane_index() == 32, splat(0), kNeg);
-
   Scalars st;
-  st.h = -S / 2;
-  st.d = 1;
-  {   // range of anti-diagonal 1 from the live origin: i in [0, 1]
-    const int smin = (1 - jv.n > 0 ? 1 - jv.n : 0) - 1 - st.h;
-    const int smax = jv.m - 1 - st.h;
-    st.lo = (S / 2 - 1) > smin ? (S / 2 - 1) : smin;
-    st.hi = (S / 2) < smax ? (S / 2) : smax;
+  if (!restore_band<C>(bd, st, P, j)) {
+#pragma unroll
+    for (int r = 0; r < C; ++r) { bd.E[r] = splat(kNeg); bd.O[r] = splat(kNeg); }
+    // anti-diagonal 0: the origin (score 0) in slot S/2 = lane 32, register 0
+    bd.E[0] = select(lane_index() == 32, splat(0), kNeg);
+    st.h = -S / 2;
+    st.d = 1;
+    {   // range of anti-diagonal 1 from the live origin: i in [0, 1]
+      const int smin = (1 - jv.n > 0 ? 1 - jv.n : 0) - 1 - st.h;
+      const int smax = jv.m - 1 - st.h;
+      st.lo = (S / 2 - 1) > smin ? (S / 2 - 1) : smin;
+      st.hi = (S / 2) < smax ? (S / 2) : smax;
+    }
+    st.best = 0; st.bi = 0; st.bj = 0;
+    st.bw = P.neg_gap;            // best + 1*|gap|
+    st.thr = P.neg_gap - jv.x;
+    st.cells_blk = 0;
+    st.cells = 0;
   }
-  st.best = 0; st.bi = 0; st.bj = 0;
-  st.bw = P.neg_gap;            // best + 1*|gap|
-  st.thr = P.neg_gap - jv.x;
-  st.cells_blk = 0;
-  st.cells = 0;
 
-  int32_t e0 = 0;
+  int32_t e = st.d >> 1;
+  bool odd = (st.d & 1) != 0;
+  int32_t e0 = e & ~15;
   build_words<C, NARROW>(bd, e0, st.h, jv, P);
   bool ok = true;
-  if (step<C, NARROW, 1>(bd, st, 0, jv, P)) {          // d = 1
-    for (int32_t e = 1;; ++e) {
+  for (;;) {
+    if (!odd) {
       if (st.lo < 1 || st.hi > S - 2) {
         if (!recenter<C>(bd, st)) { ok = false; break; }
         build_words<C, NARROW>(bd, e0, st.h, jv, P);
       }
-      int q = e - e0;
-      if (q == 16) {
+      if (e - e0 == 16) {
         e0 = e;
-        q = 0;
         st.cells += st.cells_blk;
         st.cells_blk = 0;
         build_words<C, NARROW>(bd, e0, st.h, jv, P);
       }
-      if (!step<C, NARROW, 0>(bd, st, q, jv, P)) break;   // d = 2e
-      if (st.lo < 1 || st.hi > S - 2) {
-        if (!recenter<C>(bd, st)) { ok = false; break; }
-        build_words<C, NARROW>(bd, e0, st.h, jv, P);
-      }
-      if (!step<C, NARROW, 1>(bd, st, q, jv, P)) break;   // d = 2e + 1
+      if (!step<C, NARROW, 0>(bd, st, e - e0, jv, P)) break;   // d = 2e
     }
+    odd = false;
+    if (st.lo < 1 || st.hi > S - 2) {
+      if (!recenter<C>(bd, st)) { ok = false; break; }
+      build_words<C, NARROW>(bd, e0, st.h, jv, P);
+    }
+    if (!step<C, NARROW, 1>(bd, st, e - e0, jv, P)) break;     // d = 2e + 1
+    ++e;
   }
   if (!ok) {
+    if (C < 32) save_band<C>(bd, st, P, j);
     out.status = kJobWider;
     return out;
   }
@@ -477,7 +568,7 @@ XD_FN uint32_t lane_sum(vint v) {
 }
 
 template <bool NARROW, class Runner = RunC>
-XD_FN JobOut extend_job_w1(const Job &job, const Params &P) {
+XD_FN JobOut extend_job_w1(const Job &job, const Params &P, int32_t j) {
   JobOut out;
   out.best = 0; out.bi = 0; out.bj = 0; out.status = kJobOk; out.cells = 0;
   if (job.m + job.n == 0) return out;
@@ -523,7 +614,18 @@ XD_FN JobOut extend_job_w1(const Job &job, const Params &P) {
     if (rc == kStepRecenter) {
       // place the pending range [lo, hi] in the middle of the 64 lanes
       const int width = st.hi - st.lo + 1;
-      if (width > kWave - 2) { out.status = kJobWider; return out; }
+      if (width > kWave - 2) {   // the next tier resumes from here
+        int32_t *sv = save_reserve(P, j, kWave);
+        if (sv) {
+          save_scalars(sv, 2 * st.e + st.par, st.lo, st.hi, st.h, st.best, st.bi, st.bj, st.bw,
+                       st.thr, 1, st.cells + lane_sum(cnt));
+          store_vec(sv + kSaveHdr, lane_index(), bd.E[0]);
+          store_vec(sv + kSaveHdr + kWave, lane_index(), bd.O[0]);
+          save_publish(P, j, sv);
+        }
+        out.status = kJobWider;
+        return out;
+      }
       const int dl = st.lo - (kWave - width) / 2;
       bd.E[0] = from_lane_offset(bd.E[0], dl, kNeg);
       bd.O[0] = from_lane_offset(bd.O[0], dl, kNeg);

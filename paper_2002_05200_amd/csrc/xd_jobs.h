@@ -42,6 +42,22 @@ struct Params {
   int32_t pat;       // delta replicated into every 2-bit field (narrow form)
   int32_t impl;      // 0: hand-scheduled loops where available, 1: C loops only
   int32_t unit_match;  // match == 1: best grows by exactly 1 when it grows
+  // Escalation saves: a job whose band outgrows its window stores its state
+  // in a bump-allocated pool so the next tier resumes instead of restarting.
+  int32_t *save_pool;              // nullptr: escalated jobs restart
+  unsigned long long save_cap;     // pool size in save slots
+  unsigned long long *save_top;    // next free slot (cleared per call)
+  int32_t *job_save;               // per job: word offset of its slot, or -1
 };
+
+// Layout of one save: a header, then the W values of the latest even and odd
+// anti-diagonals in slot order (S = 64 * C slots each).
+enum : int32_t {
+  kSvD = 0, kSvLo, kSvHi, kSvH, kSvBest, kSvBi, kSvBj, kSvBw, kSvThr, kSvC, kSvCellsLo,
+  kSvCellsHi, kSaveHdr = 16
+};
+// One save slot holds the widest band that can still escalate to a register
+// tier (C = 16); a job keeps its slot for all its escalations.
+constexpr int32_t kSaveSlotWords = kSaveHdr + 2 * 64 * 16;
 
 }  // namespace xd

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(
     int32_t match, int32_t mismatch, int32_t gap, int32_t min_tier, int32_t by_cost,
     int32_t long_job, int32_t long_bias, Job *__restrict__ jobs,
     int32_t *__restrict__ pair_status, int32_t *__restrict__ bin_of,
-    int32_t *__restrict__ bin_count) {
+    int32_t *__restrict__ bin_count, int32_t *__restrict__ job_save) {
   __shared__ int32_t hist[kBins];
   for (int i = threadIdx.x; i < kBins; i += blockDim.x) hist[i] = 0;
   __syncthreads();
@@ -78,6 +78,8 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(
     pair_status[p] = st;
     jobs[2 * p] = l;
     jobs[2 * p + 1] = r;
+    job_save[2 * p] = -1;
+    job_save[2 * p + 1] = -1;
     int tl = initial_tier(l), tr = initial_tier(r);
     if (long_job > 0) {   // long jobs start wider (their bands have longer to grow)
       if (l.m + l.n >= long_job) tl = min(tl + long_bias, kTiers - 1);
@@ -175,12 +177,12 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job *__restrict__ jobs,
     JobOut o;
     if constexpr (C == 1) {
       if (P.impl == 0) {
-        o = extend_job_w1<NARROW, RunAsm>(job, P);
+        o = extend_job_w1<NARROW, RunAsm>(job, P, j);
       } else {
-        o = extend_job_w1<NARROW, RunC>(job, P);
+        o = extend_job_w1<NARROW, RunC>(job, P, j);
       }
     } else {
-      o = extend_job<C, NARROW>(job, P);
+      o = extend_job<C, NARROW>(job, P, j);
     }
     if (lane_id() == 0) {
       if (o.status == kJobWider) {
@@ -262,6 +264,9 @@ struct xd_ctx {
   JobOut *outs = nullptr;
   int32_t *pair_status = nullptr;
   int32_t *bin_of = nullptr;     // counting-sort bin of every job
+  int32_t *job_save = nullptr;   // escalation save slot of every job (-1: none)
+  int32_t *save_pool = nullptr;  // escalation saves (separate allocation)
+  uint64_t save_slots = 0;
   int32_t *bins = nullptr;       // kBins counts, kBins cursors, kBins offsets
   int32_t *order = nullptr;
   int32_t *esc = nullptr;        // kLists escalation lists of 2 * cap_pairs entries
@@ -294,6 +299,7 @@ xd_status ensure_capacity(xd_ctx *c, int64_t n_pairs) {
   const size_t o_outs = off; off = align_up(off + sizeof(JobOut) * nj);
   const size_t o_stat = off; off = align_up(off + sizeof(int32_t) * cap);
   const size_t o_binof = off; off = align_up(off + sizeof(int32_t) * nj);
+  const size_t o_jsave = off; off = align_up(off + sizeof(int32_t) * nj);
   const size_t o_bins = off; off = align_up(off + sizeof(int32_t) * 3 * kBins);
   const size_t o_order = off; off = align_up(off + sizeof(int32_t) * nj);
   const size_t o_esc = off; off = align_up(off + sizeof(int32_t) * nj * kLists);
@@ -313,11 +319,26 @@ xd_status ensure_capacity(xd_ctx *c, int64_t n_pairs) {
   c->scratch.bytes = off;
   if (!c->spill.buf && spill_alloc(&c->spill) != XD_OK)
     return fail(XD_ENOMEM, "hipMalloc of the global-memory band buffers failed");
+  {   // escalation saves: one slot per job, at most 2 GiB
+    const uint64_t max_slots = (2ull << 30) / (sizeof(int32_t) * kSaveSlotWords);
+    const uint64_t want = std::min<uint64_t>((uint64_t)nj, max_slots);
+    if (want > c->save_slots) {
+      if (c->save_pool) XD_HIP(hipFree(c->save_pool));
+      c->save_pool = nullptr;
+      c->save_slots = 0;
+      void *sp = nullptr;
+      if (hipMalloc(&sp, sizeof(int32_t) * kSaveSlotWords * want) == hipSuccess) {
+        c->save_pool = (int32_t *)sp;
+        c->save_slots = want;
+      }   // else: escalated jobs restart from scratch
+    }
+  }
   char *b = (char *)p;
   c->jobs = (Job *)(b + o_jobs);
   c->outs = (JobOut *)(b + o_outs);
   c->pair_status = (int32_t *)(b + o_stat);
   c->bin_of = (int32_t *)(b + o_binof);
+  c->job_save = (int32_t *)(b + o_jsave);
   c->bins = (int32_t *)(b + o_bins);
   c->order = (int32_t *)(b + o_order);
   c->esc = (int32_t *)(b + o_esc);
@@ -410,6 +431,10 @@ xd_status enqueue(xd_ctx *c, hipStream_t s, const Launch &L, bool prof) {
   P.pat = (int32_t)((uint32_t)P.delta * 0x55555555u);
   P.impl = o.impl;
   P.unit_match = sc.match == 1;
+  P.save_pool = c->save_pool;
+  P.save_cap = c->save_slots;
+  P.save_top = c->stats + kSaveTop;
+  P.job_save = c->job_save;
   const bool narrow = P.delta <= 3;
 
   if (prof) XD_HIP(hipEventRecord(c->ev[0], s));
@@ -422,7 +447,8 @@ xd_status enqueue(xd_ctx *c, hipStream_t s, const Launch &L, bool prof) {
   hipLaunchKernelGGL(k_plan, dim3(plan_blocks), dim3(kPlanBlock), 0, s, L.d_pairs,
                      (int64_t)n_pairs, (int64_t)P.a_words, (int64_t)P.b_words, sc.match,
                      sc.mismatch, sc.gap, o.min_tier, (int32_t)by_cost, o.long_job,
-                     o.long_tier_bias, c->jobs, c->pair_status, c->bin_of, bin_count);
+                     o.long_tier_bias, c->jobs, c->pair_status, c->bin_of, bin_count,
+                     c->job_save);
   XD_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanBlock), 0, s, bin_count, bin_off, c->counters);
   XD_HIP(hipGetLastError());
@@ -519,6 +545,7 @@ void xd_ctx_destroy(xd_ctx *c) {
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->scratch.ptr) (void)hipFree(c->scratch.ptr);
+  if (c->save_pool) (void)hipFree(c->save_pool);
   spill_free(&c->spill);
   if (c->have_events)
     for (int i = 0; i < 10; ++i) (void)hipEventDestroy(c->ev[i]);

@@ -19,8 +19,10 @@ constexpr int kLists = kTiers + 1;          // register tiers + global-memory ti
 // tier, queue heads, segment offsets in the sorted order.
 constexpr int kInit = 0, kEsc = kLists, kHead = 2 * kLists, kOff = 3 * kLists;
 constexpr int kCounters = 4 * kLists;
-// Device statistics (uint64): jobs finished, cells of those jobs, escalations.
-constexpr int kStats = 3 * kLists;
+// Device statistics (uint64): jobs finished, cells of those jobs, escalations;
+// then the bump pointer of the escalation save pool.
+constexpr int kSaveTop = 3 * kLists;
+constexpr int kStats = 3 * kLists + 1;
 
 // Counting-sort bins: kCostBuckets per tier, longest jobs in the lowest bin.
 constexpr int kCostBuckets = 128;

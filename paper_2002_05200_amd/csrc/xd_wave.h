@@ -106,6 +106,20 @@ XD_FN vint load_word(const uint32_t *words, vint idx) {
   return {(int32_t)words[idx.x]};
 }
 
+// Per-job save memory: a store by the first lane only, one int32 per lane
+// stored or loaded at per-lane indices, and an atomic add by the first lane
+// whose old value every lane receives.
+XD_FN void store_first(int32_t *p, int32_t v) {
+  if (__lane_id() == 0) *p = v;
+}
+XD_FN void store_vec(int32_t *base, vint idx, vint v) { base[idx.x] = v.x; }
+XD_FN vint load_vec(const int32_t *base, vint idx) { return {base[idx.x]}; }
+XD_FN uint32_t atomic_add_first(unsigned long long *p, unsigned long long v) {
+  uint32_t old = 0;
+  if (__lane_id() == 0) old = (uint32_t)atomicAdd(p, v);
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)old);
+}
+
 XD_FN int ctz64(uint64_t m) { return __builtin_ctzll(m); }
 XD_FN int last_bit64(uint64_t m) { return 63 - __builtin_clzll(m); }
 XD_FN int ctz32(uint32_t m) { return __builtin_ctz(m); }

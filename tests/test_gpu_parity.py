@@ -257,3 +257,19 @@ def test_graph_replays_match_eager(ctx, xd):
     ctx.extend_device(db, stream=s, opts=graph)
     s.synchronize()
     assert_same(db.results(), ref2, "graph replay after the pairs changed")
+
+
+@pytest.mark.parametrize("scores", [(1, -1, -1), (2, -3, -2)])
+def test_escalated_jobs_resume_in_the_wider_tier(ctx, xd, scores):
+    """Bands that outgrow several windows in a row (mostly unrelated reads,
+    X up to 700): each escalation hands its state to the next tier, and the
+    results still equal the oracle's."""
+    from paper_2002_05200_amd import synth
+    bt = synth.random_cases(seed=910, n=120, len_lo=200, len_hi=3000,
+                            x_choices=(30, 60, 100, 200, 400, 700), spurious_frac=0.7,
+                            scores=scores)
+    got = run(ctx, xd, bt)
+    st = ctx.stats()
+    assert st["escalated"][:5].sum() > 20, st
+    assert_same(got, oracle_of(bt), f"escalations {scores}")
+    assert_same(run(ctx, xd, bt, impl=1), got, "escalations, C loops")
