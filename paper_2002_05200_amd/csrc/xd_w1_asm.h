@@ -399,6 +399,8 @@ struct RunAsm {
       const int64_t reach = ((int64_t)(jv.m + jv.n) >> 4) + 16;
       const AsmView av_a = make_asm_view(P.A, P.a_words, jv.a_start, reach);
       const AsmView av_b = make_asm_view(P.B, P.b_words, jv.b_start, reach);
+      // the loop leaves score words of block words_e0 built for this window base
+      words_h = st.h;
       if (jv.dir > 0) {
         return P.unit_match
                    ? run_w1_asm<NARROW, true, true>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0)

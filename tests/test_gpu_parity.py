@@ -273,3 +273,48 @@ def test_escalated_jobs_resume_in_the_wider_tier(ctx, xd, scores):
     assert st["escalated"][:5].sum() > 20, st
     assert_same(got, oracle_of(bt), f"escalations {scores}")
     assert_same(run(ctx, xd, bt, impl=1), got, "escalations, C loops")
+
+
+def asymmetric_cases(seed, n=150):
+    """Pairs whose reads differ in length and content in every way the
+    band bookkeeping meets near read ends: noisy copies cut short or
+    extended by random tails, unrelated reads, X from 1 to 79."""
+    from paper_2002_05200_amd import synth
+    r = np.random.default_rng(seed)
+    a_l, b_l, pa, pb, xs = [], [], [], [], []
+    for _ in range(n):
+        a = r.integers(0, 4, int(r.integers(20, 1600))).astype(np.uint8)
+        if r.random() < 0.7:
+            e = r.uniform(0.02, 0.2) / 3
+            b = synth.mutate(r, a, e, e, e)
+            if r.random() < 0.5:
+                b = b[: int(len(b) * r.uniform(0.3, 1.0))]
+            else:
+                b = np.concatenate([b, r.integers(0, 4, int(r.integers(0, 800))).astype(np.uint8)])
+        else:
+            b = r.integers(0, 4, int(r.integers(20, 1600))).astype(np.uint8)
+        if len(b) < 17:
+            b = np.concatenate([b, r.integers(0, 4, 17).astype(np.uint8)])
+        p = int(r.integers(0, len(a) - 16))
+        q = int(r.integers(0, len(b) - 16))
+        b[q:q + 17] = a[p:p + 17]
+        a_l.append(a); b_l.append(b); pa.append(p); pb.append(q); xs.append(int(r.integers(1, 80)))
+    return synth.from_pairs(a_l, b_l, pa, pb, xs, name=f"asymmetric{seed}")
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_asymmetric_reads(ctx, xd, seed):
+    """Regression: after the hand-scheduled loop left a block, the matrix-
+    clipping loop reused score words built for an older window base."""
+    bt = asymmetric_cases(seed)
+    assert_same(run(ctx, xd, bt), oracle_of(bt), f"asymmetric seed {seed}")
+
+
+def test_score_words_follow_the_window_after_a_recentre(ctx, xd):
+    """Regression for the same bug on the pair that exposed it: a 192 x 443
+    right extension at X = 21 that recentres and then reaches the end of A."""
+    from paper_2002_05200_amd import synth
+    bt = synth.random_cases(seed=600, n=200, len_lo=17, len_hi=1500, x_choices=(0, 2, 10, 50, 200))
+    a, b = bt.pair(196)
+    one = synth.from_pairs([a], [b], [int(bt.a_seed[196])], [int(bt.b_seed[196])], [21], name="p196")
+    assert_same(run(ctx, xd, one), oracle_of(one), "pair 196, X = 21")
