@@ -10,14 +10,15 @@
 // segments over HBM-resident anti-diagonals):
 //
 //  * Diagonal-stationary slots.  A cell (i, j) lies on anti-diagonal d = i + j
-//    and diagonal k = i - j.  The wave owns S = 64 * C slots; slot s on
-//    anti-diagonal d holds the cell with i = s + ceil(d/2) + h (h is the
-//    window base, moved only when the band drifts).  Slot s therefore follows
-//    one diagonal: its diagonal predecessor (d-2) sits in the same slot, and
-//    its up/left predecessors (d-1) sit in slots {s-1, s} for even d and
-//    {s, s+1} for odd d.  Lane t keeps slots C*t .. C*t + C - 1 in registers,
-//    so one DPP lane shift per anti-diagonal is the only cross-lane traffic
-//    of the cell update; nothing of the band lives in LDS or HBM.
+//    and diagonal k = i - j.  The wave owns S slots; slot s on anti-diagonal
+//    d holds the cell with i = s + ceil(d/2) + h (h is the window base, moved
+//    only when the band drifts).  Slot s therefore follows one diagonal: its
+//    diagonal predecessor (d-2) sits in the same slot, and its up/left
+//    predecessors (d-1) sit in slots {s-1, s} for even d and {s, s+1} for odd
+//    d.  This file holds the shared pieces and the one-register band (S = 64,
+//    lane t = slot t), whose only cross-lane traffic per anti-diagonal is one
+//    DPP lane shift; xd_wide.h holds the wider bands.  Nothing of a band
+//    lives in LDS or HBM.
 //
 //  * Gap-free form.  Values are stored as W_d = V_d + d*|gap|.  Then the
 //    up/left terms need no add (W_d = max(W_{d-2} + s + 2|gap|, W_{d-1}(nbrs)))
@@ -30,8 +31,8 @@
 //    one v_add3_u32 for its diagonal term W_{d-2} + s + 2|gap|.
 //
 //  * Exact bookkeeping per anti-diagonal in scalar registers: the computed
-//    range is a lane mask (C == 1) or a per-lane range test (C > 1), ANDed
-//    with the prune test; the first/last surviving slot give the next range;
+//    range is a lane mask ANDed with the prune test; the first/last
+//    surviving slot give the next range;
 //    improvement of best is detected with one compare + ballot, and the best
 //    cell (first anti-diagonal reaching the final best, smallest i on it) is
 //    taken with one more compare + ballot only when best improves.
@@ -98,24 +99,14 @@ struct Band {
   vint SO[C];  // score words for odd anti-diagonals
 };
 
-struct Scalars {
-  int32_t d;        // anti-diagonal about to be computed
-  int32_t lo, hi;   // its computed range, slot coordinates
-  int32_t h;        // window base
-  int32_t best, bi, bj;
-  int32_t bw;       // best + d*|gap|: a W value above this improves best
-  int32_t thr;      // bw - X: a W value below this is pruned
-  uint32_t cells_blk;
-  uint64_t cells;
-};
-
 struct JobView {
   SeqView A, B;
   int64_t a_start, b_start;
   int32_t m, n, x, dir;
 };
 
-// Score words of the 16 steps e0 .. e0+15 for every slot (both parities).
+// Score words of the 16 steps e0 .. e0+15 for every slot (both parities),
+// slot C*t + r in register r of lane t.
 // Slot s at step e: even anti-diagonal 2e holds (i, j) = (s+h+e, e-s-h),
 // odd anti-diagonal 2e+1 holds (s+h+e+1, e-s-h).
 template <int C, bool NARROW>
@@ -146,126 +137,6 @@ XD_FN void build_words(Band<C> &bd, int32_t e0, int32_t h, const JobView &jv, co
     bd.SE[r] = score_word<NARROW>(xe, P.pat);
     bd.SO[r] = score_word<NARROW>(xo, P.pat);
   }
-}
-
-// Computes anti-diagonal st.d (parity PAR) at score-word step q, then
-// prepares st for d + 1.  Returns false once the extension has ended.
-template <int C, bool NARROW, int PAR>
-XD_FN bool step(Band<C> &bd, Scalars &st, int q, const JobView &jv, const Params &P) {
-  vint *cur = PAR ? bd.O : bd.E;   // holds d - 2 on entry, d on exit
-  vint *prv = PAR ? bd.E : bd.O;   // holds d - 1
-  const vint *sw = PAR ? bd.SO : bd.SE;
-  const int pos = 2 * q;
-  vint v[C];
-  if (PAR == 0) {   // even d: predecessors in slots s-1, s
-    vint nbr = from_prev_lane(prv[C - 1], kNeg);
-#pragma unroll
-    for (int r = 0; r < C; ++r) {
-      vint a = (r == 0) ? nbr : prv[r - 1];
-      v[r] = vmax3(diag_term<NARROW>(cur[r], sw[r], pos, P), a, prv[r]);
-    }
-  } else {          // odd d: predecessors in slots s, s+1
-    vint nbr = from_next_lane(prv[0], kNeg);
-#pragma unroll
-    for (int r = 0; r < C; ++r) {
-      vint b = (r == C - 1) ? nbr : prv[r + 1];
-      v[r] = vmax3(diag_term<NARROW>(cur[r], sw[r], pos, P), prv[r], b);
-    }
-  }
-  st.cells_blk += (uint32_t)(st.hi - st.lo + 1);
-
-  // prune (strictly below best - X) and clip to the computed range
-  int a_s, b_s;
-  if (C == 1) {
-    uint64_t live = ballot(v[0] >= st.thr) & lane_range_mask(st.lo, st.hi);
-    cur[0] = select(lanes(live), v[0], kNeg);
-    if (live == 0) return false;
-    a_s = ctz64(live);
-    b_s = last_bit64(live);
-  } else {
-    vint s0 = lane_index() * C;
-    vint lbits = splat(0);
-    const uint32_t width = (uint32_t)(st.hi - st.lo);
-#pragma unroll
-    for (int r = 0; r < C; ++r) {
-      vbool lv = both(v[r] >= st.thr, le_u(s0 + (r - st.lo), width));
-      cur[r] = select(lv, v[r], kNeg);
-      lbits = lbits | bit_if(lv, r);
-    }
-    uint64_t any = ballot(lbits != 0);
-    if (any == 0) return false;
-    int ta = ctz64(any), tb = last_bit64(any);
-    a_s = C * ta + ctz32((uint32_t)readlane(lbits, ta));
-    b_s = C * tb + last_bit32((uint32_t)readlane(lbits, tb));
-  }
-
-  // best is updated once the whole anti-diagonal is known (Section IV-A)
-  vint mx = cur[0];
-#pragma unroll
-  for (int r = 1; r < C; ++r) mx = vmax(mx, cur[r]);
-  if (ballot(mx > st.bw) != 0) {
-    int inc = 1;
-    while (ballot(mx > st.bw + inc) != 0) ++inc;
-    st.bw += inc;
-    st.thr += inc;
-    st.best += inc;
-    int sbest;
-    if (C == 1) {
-      sbest = ctz64(ballot(cur[0] == st.bw));
-    } else {
-      vint eq = splat(0);
-#pragma unroll
-      for (int r = 0; r < C; ++r) eq = eq | bit_if(cur[r] == st.bw, r);
-      int t = ctz64(ballot(eq != 0));
-      sbest = C * t + ctz32((uint32_t)readlane(eq, t));
-    }
-    st.bi = sbest + ((st.d + 1) >> 1) + st.h;
-    st.bj = st.d - st.bi;
-  }
-
-  // next anti-diagonal: [first live, last live + 1] in i, clipped to the matrix
-  const int d1 = st.d + 1;
-  if (d1 > jv.m + jv.n) return false;
-  int lo = PAR ? a_s : a_s - 1;
-  int hi = PAR ? b_s + 1 : b_s;
-  const int c1 = (d1 + 1) >> 1;
-  const int i_min = d1 - jv.n > 0 ? d1 - jv.n : 0;
-  const int smin = i_min - c1 - st.h;
-  const int smax = jv.m - c1 - st.h;
-  lo = lo > smin ? lo : smin;
-  hi = hi < smax ? hi : smax;
-  if (lo > hi) return false;
-  st.d = d1;
-  st.lo = lo;
-  st.hi = hi;
-  st.bw += P.neg_gap;
-  st.thr += P.neg_gap;
-  return true;
-}
-
-// Moves the window so the next range sits in its middle.  Returns false when
-// the range is wider than the window allows (the job needs a wider tier).
-template <int C>
-XD_FN bool recenter(Band<C> &bd, Scalars &st) {
-  constexpr int S = kWave * C;
-  const int width = st.hi - st.lo + 1;
-  if (width > S - 2) return false;
-  const int target_lo = (S - width) / 2;
-  int dl = st.lo - target_lo;
-  dl = dl >= 0 ? dl / C : -((-dl + C - 1) / C);   // floor division by C
-  int nlo = st.lo - C * dl, nhi = st.hi - C * dl;
-  if (nlo < 1) { dl -= 1; nlo += C; nhi += C; }
-  if (nhi > S - 2) { dl += 1; nlo -= C; nhi -= C; }
-  if (nlo < 1 || nhi > S - 2) return false;
-#pragma unroll
-  for (int r = 0; r < C; ++r) {
-    bd.E[r] = from_lane_offset(bd.E[r], dl, kNeg);
-    bd.O[r] = from_lane_offset(bd.O[r], dl, kNeg);
-  }
-  st.h += C * dl;
-  st.lo = nlo;
-  st.hi = nhi;
-  return true;
 }
 
 // Escalation saves.  A wave whose band outgrows its window stores the state
@@ -305,131 +176,6 @@ XD_FN int32_t *save_reserve(const Params &P, int32_t j, int32_t S) {
 XD_FN void save_publish(const Params &P, int32_t j, const int32_t *sv) {
   store_first(P.job_save + j, (int32_t)(sv - P.save_pool));
 }
-
-template <int C>
-XD_FN void save_band(const Band<C> &bd, const Scalars &st, const Params &P, int32_t j) {
-  constexpr int S = kWave * C;
-  int32_t *sv = save_reserve(P, j, S);
-  if (!sv) return;
-  save_scalars(sv, st.d, st.lo, st.hi, st.h, st.best, st.bi, st.bj, st.bw, st.thr, C,
-               st.cells + st.cells_blk);
-  const vint s0 = lane_index() * C;
-#pragma unroll
-  for (int r = 0; r < C; ++r) {
-    store_vec(sv + kSaveHdr, s0 + r, bd.E[r]);
-    store_vec(sv + kSaveHdr + S, s0 + r, bd.O[r]);
-  }
-  save_publish(P, j, sv);
-}
-
-// Restores a save of a narrower tier into the middle of this tier's window.
-template <int C>
-XD_FN bool restore_band(Band<C> &bd, Scalars &st, const Params &P, int32_t j) {
-  if (!P.save_pool || j < 0) return false;
-  const int32_t off = P.job_save[j];
-  if (off < 0) return false;
-  const int32_t *sv = P.save_pool + off;
-  const int32_t cs = sv[kSvC];
-  constexpr int S = kWave * C;
-  if (cs >= C) return false;
-  const int32_t ss = kWave * cs;
-  const int32_t shift = (S - ss) / 2;
-  st.d = sv[kSvD];
-  st.lo = sv[kSvLo] + shift;
-  st.hi = sv[kSvHi] + shift;
-  st.h = sv[kSvH] - shift;
-  st.best = sv[kSvBest]; st.bi = sv[kSvBi]; st.bj = sv[kSvBj];
-  st.bw = sv[kSvBw]; st.thr = sv[kSvThr];
-  st.cells = (uint64_t)(uint32_t)sv[kSvCellsLo] | ((uint64_t)(uint32_t)sv[kSvCellsHi] << 32);
-  st.cells_blk = 0;
-  const vint s0 = lane_index() * C;
-#pragma unroll
-  for (int r = 0; r < C; ++r) {
-    const vint old = s0 + (r - shift);
-    const vbool in = le_u(old, (uint32_t)(ss - 1));
-    const vint k = select(in, old, 0);
-    bd.E[r] = select(in, load_vec(sv + kSaveHdr, k), kNeg);
-    bd.O[r] = select(in, load_vec(sv + kSaveHdr + ss, k), kNeg);
-  }
-  return true;
-}
-
-// Whole one-directional extension of job j on the calling wavefront, resumed
-// from a narrower tier's save when there is one.
-template <int C, bool NARROW>
-XD_FN JobOut extend_job(const Job &job, const Params &P, int32_t j) {
-  constexpr int S = kWave * C;
-  JobOut out;
-  out.best = 0; out.bi = 0; out.bj = 0; out.status = kJobOk; out.cells = 0;
-  if (job.m + job.n == 0) return out;
-
-  JobView jv;
-  jv.A = make_view(P.A, P.a_words, job.a_start);
-  jv.B = make_view(P.B, P.b_words, job.b_start);
-  jv.a_start = job.a_start; jv.b_start = job.b_start;
-  jv.m = job.m; jv.n = job.n; jv.x = job.x; jv.dir = job.dir;
-
-  Band<C> bd;
-  Scalars st;
-  if (!restore_band<C>(bd, st, P, j)) {
-#pragma unroll
-    for (int r = 0; r < C; ++r) { bd.E[r] = splat(kNeg); bd.O[r] = splat(kNeg); }
-    // anti-diagonal 0: the origin (score 0) in slot S/2 = lane 32, register 0
-    bd.E[0] = select(lane_index() == 32, splat(0), kNeg);
-    st.h = -S / 2;
-    st.d = 1;
-    {   // range of anti-diagonal 1 from the live origin: i in [0, 1]
-      const int smin = (1 - jv.n > 0 ? 1 - jv.n : 0) - 1 - st.h;
-      const int smax = jv.m - 1 - st.h;
-      st.lo = (S / 2 - 1) > smin ? (S / 2 - 1) : smin;
-      st.hi = (S / 2) < smax ? (S / 2) : smax;
-    }
-    st.best = 0; st.bi = 0; st.bj = 0;
-    st.bw = P.neg_gap;            // best + 1*|gap|
-    st.thr = P.neg_gap - jv.x;
-    st.cells_blk = 0;
-    st.cells = 0;
-  }
-
-  int32_t e = st.d >> 1;
-  bool odd = (st.d & 1) != 0;
-  int32_t e0 = e & ~15;
-  build_words<C, NARROW>(bd, e0, st.h, jv, P);
-  bool ok = true;
-  for (;;) {
-    if (!odd) {
-      if (st.lo < 1 || st.hi > S - 2) {
-        if (!recenter<C>(bd, st)) { ok = false; break; }
-        build_words<C, NARROW>(bd, e0, st.h, jv, P);
-      }
-      if (e - e0 == 16) {
-        e0 = e;
-        st.cells += st.cells_blk;
-        st.cells_blk = 0;
-        build_words<C, NARROW>(bd, e0, st.h, jv, P);
-      }
-      if (!step<C, NARROW, 0>(bd, st, e - e0, jv, P)) break;   // d = 2e
-    }
-    odd = false;
-    if (st.lo < 1 || st.hi > S - 2) {
-      if (!recenter<C>(bd, st)) { ok = false; break; }
-      build_words<C, NARROW>(bd, e0, st.h, jv, P);
-    }
-    if (!step<C, NARROW, 1>(bd, st, e - e0, jv, P)) break;     // d = 2e + 1
-    ++e;
-  }
-  if (!ok) {
-    if (C < 32) save_band<C>(bd, st, P, j);
-    out.status = kJobWider;
-    return out;
-  }
-  out.best = st.best;
-  out.bi = st.bi;
-  out.bj = st.bj;
-  out.cells = st.cells + st.cells_blk;
-  return out;
-}
-
 
 // ---------------------------------------------------------------------------
 // One register per lane (64 diagonals).  The computed range, the survivors

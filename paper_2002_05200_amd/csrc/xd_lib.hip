@@ -36,6 +36,7 @@
 #include "xd_queue.h"
 #include "xd_spill.h"
 #include "xd_w1_asm.h"
+#include "xd_wide.h"
 
 namespace xd {
 
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job *__restrict__ jobs,
         o = extend_job_w1<NARROW, RunC>(job, P, j);
       }
     } else {
-      o = extend_job<C, NARROW>(job, P, j);
+      o = extend_job_wide<C, NARROW>(job, P, j);
     }
     if (lane_id() == 0) {
       if (o.status == kJobWider) {

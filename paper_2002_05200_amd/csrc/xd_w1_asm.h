@@ -23,7 +23,7 @@
 // An improvement of best costs 3 SALU + 1 VALU out of line; best itself is
 // not tracked in the loop but recovered from bw afterwards.
 // Block transition (every 32 anti-diagonals): 3 window shifts, 3 clamped
-// prefetch loads, 3 v_alignbit, 2 v_xor, 4 VALU per score word.
+// prefetch loads, 3 v_alignbit, 2 v_xor, 2-4 VALU per score word.
 //
 // Window edges: an even anti-diagonal may not use lane 0 (wave_shr leaves it
 // without a neighbour) and an odd one may not use lane 63.  Checking after
@@ -64,7 +64,7 @@ XD_FN AsmView make_asm_view(const uint32_t *words, int64_t nwords, int64_t start
 // (lo, hi) holding it now, the word prefetched for the next block, the index
 // of the word to prefetch after that, and the window's bit offset.
 struct Win {
-  vint lo, hi, nx, idx, sh;
+  vint lo, hi, nx, idx, sh;   // idx: byte offset of the next word to fetch
 };
 
 XD_FN vint load_clamped(const AsmView &v, vint w) { return load_word(v.base, clamp(w, 0, v.hi_rel)); }
@@ -78,7 +78,7 @@ XD_FN Win make_win(const AsmView &v, vint off) {
   w.sh = (g & 15) << 1;
   w.lo = load_clamped(v, wi);
   w.hi = load_clamped(v, wi + 1);
-  w.idx = FWD ? wi + 2 : wi - 1;   // next block: one word further along the read
+  w.idx = (FWD ? wi + 2 : wi - 1) << 2;   // next block's word, as a byte offset
   w.nx = splat(0);
   return w;
 }
@@ -98,25 +98,29 @@ XD_FN Win make_win(const AsmView &v, vint off) {
   "v_bitop3_b32 %[u], %[u], %[k55], %[" X "] bitop3:4\n\t"          \
   "v_lshl_add_u32 %[u], %[u], 1, %[u]\n\t"                          \
   "v_and_b32 %[" S "], %[pat], %[u]\n\t"
+// delta = 2: ~(x | x << 1) keeps a match flag in the high bit of each field,
+// which is the value 2 itself.
+#define XD_SW_D2(S, X)                                              \
+  "v_lshlrev_b32 %[u], 1, %[" X "]\n\t"                             \
+  "v_bitop3_b32 %[" S "], %[u], %[pat], %[" X "] bitop3:4\n\t"
 #define XD_SW_WIDE(S, X)                                            \
   "v_lshrrev_b32 %[u], 1, %[" X "]\n\t"                             \
   "v_bitop3_b32 %[" S "], %[u], %[k55], %[" X "] bitop3:4\n\t"
 
-// Prefetch of window K's next word.
+// Prefetch of window K's next word (byte offset clamped into the read's view).
 #define XD_PREFETCH(K, HI, BASE)                                    \
   "v_med3_i32 %[p" K "], %[idx" K "], 0, %[" HI "]\n\t"             \
-  "v_lshlrev_b32 %[p" K "], 2, %[p" K "]\n\t"                       \
   "global_load_dword %[nx" K "], %[p" K "], %[" BASE "]\n\t"
 
 // Window K moves one word along the read.
 #define XD_SHIFT_FWD(K)                                             \
   "v_mov_b32 %[lo" K "], %[hi" K "]\n\t"                            \
   "v_mov_b32 %[hi" K "], %[nx" K "]\n\t"                            \
-  "v_add_u32 %[idx" K "], 1, %[idx" K "]\n\t"
+  "v_add_u32 %[idx" K "], 4, %[idx" K "]\n\t"
 #define XD_SHIFT_BWD(K)                                             \
   "v_mov_b32 %[hi" K "], %[lo" K "]\n\t"                            \
   "v_mov_b32 %[lo" K "], %[nx" K "]\n\t"                            \
-  "v_add_u32 %[idx" K "], -1, %[idx" K "]\n\t"
+  "v_add_u32 %[idx" K "], -4, %[idx" K "]\n\t"
 
 #define XD_WORDS(SW, REV)                                           \
   "v_alignbit_b32 %[x0], %[hi0], %[lo0], %[sh0]\n\t"                \
@@ -241,7 +245,7 @@ XD_FN Win make_win(const AsmView &v, vint off) {
 
 enum : int { kStepLeave = 3 };
 
-template <bool NARROW, bool UNIT, bool FWD>
+template <bool NARROW, bool UNIT, bool FWD, bool D2>
 XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &jv,
                      const AsmView &av_a, const AsmView &av_b, const Params &P,
                      int32_t &words_e0) {
@@ -264,7 +268,7 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
   uint64_t live = 0;
   const uint64_t edge = 0xC000000000000001ull;   // lanes 0, 62, 63
   const int32_t k55 = 0x55555555;
-  const int32_t hi_a = av_a.hi_rel, hi_b = av_b.hi_rel;
+  const int32_t hi_a = av_a.hi_rel << 2, hi_b = av_b.hi_rel << 2;   // bytes
   const uint32_t *base_a = av_a.base, *base_b = av_b.base;
   int32_t par = st.par;
   int32_t bw = st.bw;
@@ -341,7 +345,10 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
       : "vcc", "scc", "memory", "s40", "s41", "s42")
 #define XD_REV_NONE ""
 #define XD_REV_BOTH "v_bfrev_b32 %[x0], %[x0]\n\tv_bfrev_b32 %[x1], %[x1]\n\t"
-  if (FWD) {
+  if (D2) {   // match = 1 and match - mismatch = 2 (e.g. +1/-1/-1)
+    if (FWD) { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_UNIT, XD_SW_D2, XD_SHIFT_FWD, XD_REV_NONE); }
+    else { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_UNIT, XD_SW_D2, XD_SHIFT_BWD, XD_REV_BOTH); }
+  } else if (FWD) {
     if (NARROW) {
       if (UNIT) { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_UNIT, XD_SW_NARROW, XD_SHIFT_FWD, XD_REV_NONE); }
       else { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_LOOP, XD_SW_NARROW, XD_SHIFT_FWD, XD_REV_NONE); }
@@ -401,14 +408,19 @@ struct RunAsm {
       const AsmView av_b = make_asm_view(P.B, P.b_words, jv.b_start, reach);
       // the loop leaves score words of block words_e0 built for this window base
       words_h = st.h;
+      if (NARROW && P.unit_match && P.delta == 2) {
+        return jv.dir > 0
+                   ? run_w1_asm<NARROW, true, true, true>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0)
+                   : run_w1_asm<NARROW, true, false, true>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0);
+      }
       if (jv.dir > 0) {
         return P.unit_match
-                   ? run_w1_asm<NARROW, true, true>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0)
-                   : run_w1_asm<NARROW, false, true>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0);
+                   ? run_w1_asm<NARROW, true, true, false>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0)
+                   : run_w1_asm<NARROW, false, true, false>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0);
       }
       return P.unit_match
-                 ? run_w1_asm<NARROW, true, false>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0)
-                 : run_w1_asm<NARROW, false, false>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0);
+                 ? run_w1_asm<NARROW, true, false, false>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0)
+                 : run_w1_asm<NARROW, false, false, false>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0);
     }
   }
 };

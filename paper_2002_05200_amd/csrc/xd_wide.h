@@ -1,0 +1,356 @@
+// xd_wide.h -- one X-drop extension per wavefront for bands wider than one
+// register: C registers per lane, the S = 64 C diagonal slots interleaved
+// across registers (slot s lives in lane s mod 64 of register s / 64).
+//
+// Same arithmetic as xd_extend.h (Section III-A recurrence in the gap-free W
+// form, pruning against the best of the previous anti-diagonals, next range
+// [first live, last live + 1] clipped to the matrix), laid out so that every
+// register is a run of 64 consecutive slots:
+//   * an anti-diagonal's computed range covers a contiguous span of
+//     registers and only that span is updated, so the work follows the
+//     band's width rather than the window's;
+//   * survivors and the range are 64-bit lane masks per register (compare,
+//     ballot, s_ff1 / s_flbit), as in the one-register loop;
+//   * the neighbour on the previous anti-diagonal is one whole-wave DPP
+//     rotation, with lane 0 (lane 63) taken from the rotated register below
+//     (above).
+// Registers outside the span last computed on a parity hold -inf, so the
+// neighbour lookups at the span's edges read -inf.
+#pragma once
+
+#include "xd_extend.h"
+
+namespace xd {
+
+template <int C>
+struct WBand {
+  vint E[C];   // latest even anti-diagonal, W form
+  vint O[C];   // latest odd anti-diagonal
+  vint SE[C];  // score words, even anti-diagonals of the block
+  vint SO[C];  // score words, odd anti-diagonals
+};
+
+struct WScalars {
+  int32_t d;                      // anti-diagonal about to be computed
+  int32_t lo, hi;                 // its computed range (slots)
+  int32_t h;                      // window base: slot s holds i = s + ceil(d/2) + h
+  int32_t best, bi, bj;
+  int32_t bw, thr;                // W-form improvement and prune thresholds of d
+  int32_t span_lo[2], span_hi[2]; // registers last computed on even / odd d
+  int32_t w_lo, w_hi;             // registers whose score words are built
+  uint32_t cells_blk;
+  uint64_t cells;
+};
+
+// Score words of registers [r0, r1] for the 16 steps e0 .. e0 + 15 (slot s at
+// step e: even anti-diagonal 2e holds (s+h+e, e-s-h), odd 2e+1 holds
+// (s+h+e+1, e-s-h)).
+template <int C, bool NARROW>
+XD_FN void wbuild(WBand<C> &bd, WScalars &st, int32_t e0, int32_t r0, int32_t r1,
+                  const JobView &jv, const Params &P) {
+  if (r0 < 0) r0 = 0;
+  if (r1 > C - 1) r1 = C - 1;
+  const vint l = lane_index();
+#pragma unroll
+  for (int r = 0; r < C; ++r) {
+    if (r < r0 || r > r1) continue;
+    const vint s = l + 64 * r;
+    const vint i0 = s + (st.h + e0);
+    const vint j0 = splat(e0 - st.h) - s;
+    vint offAe, offAo, offB;
+    if (jv.dir > 0) {          // a_i = A[start + i - 1]
+      offAe = i0 - 1;
+      offAo = i0;
+      offB = j0 - 1;
+    } else {                   // a_i = A[start - i + 1]: window of the 16 bases below
+      offAe = splat(-14) - i0;
+      offAo = splat(-15) - i0;
+      offB = splat(-14) - j0;
+    }
+    const vint wb = window16(jv.B, offB);
+    vint xe = window16(jv.A, offAe) ^ wb;
+    vint xo = window16(jv.A, offAo) ^ wb;
+    if (jv.dir < 0) {
+      xe = bit_reverse(xe);
+      xo = bit_reverse(xo);
+    }
+    bd.SE[r] = score_word<NARROW>(xe, P.pat);
+    bd.SO[r] = score_word<NARROW>(xo, P.pat);
+  }
+  st.w_lo = r0;
+  st.w_hi = r1;
+}
+
+// Anti-diagonal st.d (parity PAR) at step q of the score-word block; then
+// prepares st for d + 1.  Returns false once the extension has ended.
+template <int C, bool NARROW, int PAR>
+XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Params &P) {
+  vint *cur = PAR ? bd.O : bd.E;          // d - 2 on entry, d on exit
+  const vint *prv = PAR ? bd.E : bd.O;    // d - 1
+  const vint *sw = PAR ? bd.SO : bd.SE;
+  const int pos = 2 * q;
+  const int rlo = st.lo >> 6, rhi = st.hi >> 6;
+  const int plo = st.span_lo[PAR], phi = st.span_hi[PAR];
+  const uint64_t lo_mask = ~0ull << (st.lo & 63);
+  const uint64_t hi_mask = ~0ull >> (63 - (st.hi & 63));
+  uint64_t imp = 0;
+  int first = -1, last = -1;
+#pragma unroll
+  for (int r = 0; r < C; ++r) {
+    if (r < rlo || r > rhi) {
+      if (r >= plo && r <= phi) cur[r] = splat(kNeg);   // left the span
+      continue;
+    }
+    vint t;
+    if (PAR == 0) {   // even d: predecessors in slots s-1 and s
+      const vint own = rot_prev(prv[r]);
+      const vint below = r > 0 ? rot_prev(prv[r - 1]) : splat(kNeg);
+      t = select(lanes(1ull), below, own);
+    } else {          // odd d: predecessors in slots s and s+1
+      const vint own = rot_next(prv[r]);
+      const vint above = r < C - 1 ? rot_next(prv[r + 1]) : splat(kNeg);
+      t = select(lanes(1ull << 63), above, own);
+    }
+    const vint v = vmax3(diag_term<NARROW>(cur[r], sw[r], pos, P), prv[r], t);
+    uint64_t range = ~0ull;
+    if (r == rlo) range &= lo_mask;
+    if (r == rhi) range &= hi_mask;
+    const uint64_t live = ballot(v >= st.thr) & range;
+    cur[r] = select(lanes(live), v, kNeg);
+    if (live != 0) {
+      if (first < 0) first = 64 * r + ctz64(live);
+      last = 64 * r + last_bit64(live);
+    }
+    imp |= ballot(cur[r] > st.bw);
+  }
+  st.span_lo[PAR] = rlo;
+  st.span_hi[PAR] = rhi;
+  st.cells_blk += (uint32_t)(st.hi - st.lo + 1);
+  if (first < 0) return false;
+
+  // best is updated once the whole anti-diagonal is known (Section IV-A)
+  if (imp != 0) {
+    int inc = 1;
+    for (;;) {
+      uint64_t more = 0;
+#pragma unroll
+      for (int r = 0; r < C; ++r)
+        if (r >= rlo && r <= rhi) more |= ballot(cur[r] > st.bw + inc);
+      if (more == 0) break;
+      ++inc;
+    }
+    st.bw += inc;
+    st.thr += inc;
+    st.best += inc;
+    int sbest = -1;
+#pragma unroll
+    for (int r = 0; r < C; ++r) {
+      if (sbest >= 0 || r < rlo || r > rhi) continue;
+      const uint64_t m = ballot(cur[r] == st.bw);
+      if (m != 0) sbest = 64 * r + ctz64(m);
+    }
+    st.bi = sbest + ((st.d + 1) >> 1) + st.h;
+    st.bj = st.d - st.bi;
+  }
+
+  // next anti-diagonal: [first live, last live + 1] in i, clipped to the matrix
+  const int d1 = st.d + 1;
+  if (d1 > jv.m + jv.n) return false;
+  int lo = PAR ? first : first - 1;
+  int hi = PAR ? last + 1 : last;
+  const int c1 = (d1 + 1) >> 1;
+  const int i_min = d1 - jv.n > 0 ? d1 - jv.n : 0;
+  const int smin = i_min - c1 - st.h;
+  const int smax = jv.m - c1 - st.h;
+  lo = lo > smin ? lo : smin;
+  hi = hi < smax ? hi : smax;
+  if (lo > hi) return false;
+  st.d = d1;
+  st.lo = lo;
+  st.hi = hi;
+  st.bw += P.neg_gap;
+  st.thr += P.neg_gap;
+  return true;
+}
+
+// new slot s <- old slot s + m, 0 < |m| < 64; slots from outside the window
+// become -inf.
+template <int C>
+XD_FN void wshift(vint *a, int m) {
+  vint out[C];
+#pragma unroll
+  for (int r = 0; r < C; ++r) {
+    if (m > 0) {
+      const vint here = from_lane_offset(a[r], m, kNeg);
+      const vint next = r + 1 < C ? from_lane_offset(a[r + 1], m - 64, kNeg) : splat(kNeg);
+      out[r] = vmax(here, next);   // exactly one of the two is a slot; the other is -inf
+    } else {
+      const vint here = from_lane_offset(a[r], m, kNeg);
+      const vint prev = r > 0 ? from_lane_offset(a[r - 1], m + 64, kNeg) : splat(kNeg);
+      out[r] = vmax(here, prev);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < C; ++r) a[r] = out[r];
+}
+
+// Moves the window so the pending range sits in its middle.  Returns false
+// when the range is too wide for this tier.
+template <int C>
+XD_FN bool wrecenter(WBand<C> &bd, WScalars &st) {
+  constexpr int S = kWave * C;
+  const int width = st.hi - st.lo + 1;
+  if (width > S - 2) return false;
+  int dl = st.lo - (S - width) / 2;   // new slot = old slot - dl
+  while (dl != 0) {
+    const int m = dl > 63 ? 63 : (dl < -63 ? -63 : dl);
+    wshift<C>(bd.E, m);
+    wshift<C>(bd.O, m);
+    st.h += m;
+    st.lo -= m;
+    st.hi -= m;
+    dl -= m;
+  }
+  st.span_lo[0] = st.span_lo[1] = 0;   // any register may now hold values
+  st.span_hi[0] = st.span_hi[1] = C - 1;
+  st.w_lo = 1;                          // score words belong to the old window
+  st.w_hi = 0;
+  return true;
+}
+
+template <int C>
+XD_FN void wsave(const WBand<C> &bd, const WScalars &st, const Params &P, int32_t j) {
+  constexpr int S = kWave * C;
+  int32_t *sv = save_reserve(P, j, S);
+  if (!sv) return;
+  save_scalars(sv, st.d, st.lo, st.hi, st.h, st.best, st.bi, st.bj, st.bw, st.thr, C,
+               st.cells + st.cells_blk);
+  const vint l = lane_index();
+#pragma unroll
+  for (int r = 0; r < C; ++r) {
+    store_vec(sv + kSaveHdr, l + 64 * r, bd.E[r]);
+    store_vec(sv + kSaveHdr + S, l + 64 * r, bd.O[r]);
+  }
+  save_publish(P, j, sv);
+}
+
+// Restores a narrower tier's save (slot order) into the middle of the window.
+template <int C>
+XD_FN bool wrestore(WBand<C> &bd, WScalars &st, const Params &P, int32_t j) {
+  if (!P.save_pool || j < 0) return false;
+  const int32_t off = P.job_save[j];
+  if (off < 0) return false;
+  const int32_t *sv = P.save_pool + off;
+  const int32_t cs = sv[kSvC];
+  constexpr int S = kWave * C;
+  if (cs >= C) return false;
+  const int32_t ss = kWave * cs;
+  const int32_t shift = (S - ss) / 2;
+  st.d = sv[kSvD];
+  st.lo = sv[kSvLo] + shift;
+  st.hi = sv[kSvHi] + shift;
+  st.h = sv[kSvH] - shift;
+  st.best = sv[kSvBest]; st.bi = sv[kSvBi]; st.bj = sv[kSvBj];
+  st.bw = sv[kSvBw]; st.thr = sv[kSvThr];
+  st.cells = (uint64_t)(uint32_t)sv[kSvCellsLo] | ((uint64_t)(uint32_t)sv[kSvCellsHi] << 32);
+  st.cells_blk = 0;
+  const vint l = lane_index();
+#pragma unroll
+  for (int r = 0; r < C; ++r) {
+    const vint old = l + (64 * r - shift);
+    const vbool in = le_u(old, (uint32_t)(ss - 1));
+    const vint k = select(in, old, 0);
+    bd.E[r] = select(in, load_vec(sv + kSaveHdr, k), kNeg);
+    bd.O[r] = select(in, load_vec(sv + kSaveHdr + ss, k), kNeg);
+  }
+  st.span_lo[0] = st.span_lo[1] = 0;
+  st.span_hi[0] = st.span_hi[1] = C - 1;
+  return true;
+}
+
+// Whole one-directional extension of job j, resumed from a narrower tier's
+// save when there is one.
+template <int C, bool NARROW>
+XD_FN JobOut extend_job_wide(const Job &job, const Params &P, int32_t j) {
+  constexpr int S = kWave * C;
+  JobOut out;
+  out.best = 0; out.bi = 0; out.bj = 0; out.status = kJobOk; out.cells = 0;
+  if (job.m + job.n == 0) return out;
+
+  JobView jv;
+  jv.A = make_view(P.A, P.a_words, job.a_start);
+  jv.B = make_view(P.B, P.b_words, job.b_start);
+  jv.a_start = job.a_start; jv.b_start = job.b_start;
+  jv.m = job.m; jv.n = job.n; jv.x = job.x; jv.dir = job.dir;
+
+  WBand<C> bd;
+  WScalars st;
+  if (!wrestore<C>(bd, st, P, j)) {
+    const vbool origin = lane_index() == 0;
+#pragma unroll
+    for (int r = 0; r < C; ++r) {   // anti-diagonal 0: the origin in slot S/2
+      bd.E[r] = (r == C / 2) ? select(origin, splat(0), kNeg) : splat(kNeg);
+      bd.O[r] = splat(kNeg);
+    }
+    st.h = -S / 2;
+    st.d = 1;
+    {   // range of anti-diagonal 1 from the live origin: i in [0, 1]
+      const int smin = (1 - jv.n > 0 ? 1 - jv.n : 0) - 1 - st.h;
+      const int smax = jv.m - 1 - st.h;
+      st.lo = (S / 2 - 1) > smin ? (S / 2 - 1) : smin;
+      st.hi = (S / 2) < smax ? (S / 2) : smax;
+    }
+    st.best = 0; st.bi = 0; st.bj = 0;
+    st.bw = P.neg_gap;            // best + 1*|gap|
+    st.thr = P.neg_gap - jv.x;
+    st.cells_blk = 0;
+    st.cells = 0;
+    st.span_lo[0] = st.span_hi[0] = C / 2;   // the origin's register
+    st.span_lo[1] = 1;                        // nothing odd yet
+    st.span_hi[1] = 0;
+  }
+  st.w_lo = 1;
+  st.w_hi = 0;
+
+  int32_t e = st.d >> 1;
+  bool odd = (st.d & 1) != 0;
+  int32_t e0 = e & ~15;
+  bool ok = true;
+  for (;;) {
+    if (!odd) {
+      if (st.lo < 1 || st.hi > S - 2) {
+        if (!wrecenter<C>(bd, st)) { ok = false; break; }
+      }
+      if (e - e0 == 16) {
+        e0 = e;
+        st.cells += st.cells_blk;
+        st.cells_blk = 0;
+        st.w_lo = 1;
+        st.w_hi = 0;
+      }
+      if ((st.lo >> 6) < st.w_lo || (st.hi >> 6) > st.w_hi)
+        wbuild<C, NARROW>(bd, st, e0, (st.lo >> 6) - 1, (st.hi >> 6) + 1, jv, P);
+      if (!wstep<C, NARROW, 0>(bd, st, e - e0, jv, P)) break;   // d = 2e
+    }
+    odd = false;
+    if (st.lo < 1 || st.hi > S - 2) {
+      if (!wrecenter<C>(bd, st)) { ok = false; break; }
+    }
+    if ((st.lo >> 6) < st.w_lo || (st.hi >> 6) > st.w_hi)
+      wbuild<C, NARROW>(bd, st, e0, (st.lo >> 6) - 1, (st.hi >> 6) + 1, jv, P);
+    if (!wstep<C, NARROW, 1>(bd, st, e - e0, jv, P)) break;     // d = 2e + 1
+    ++e;
+  }
+  if (!ok) {
+    if (C < 32) wsave<C>(bd, st, P, j);
+    out.status = kJobWider;
+    return out;
+  }
+  out.best = st.best;
+  out.bi = st.bi;
+  out.bj = st.bj;
+  out.cells = st.cells + st.cells_blk;
+  return out;
+}
+
+}  // namespace xd
