@@ -270,7 +270,8 @@ struct xd_ctx {
   uint64_t save_slots = 0;
   int32_t *bins = nullptr;       // kBins counts, kBins cursors, kBins offsets
   int32_t *order = nullptr;
-  int32_t *esc = nullptr;        // kLists escalation lists of 2 * cap_pairs entries
+  int32_t *esc = nullptr;        // kLists + 1 lists of 2 * cap_pairs entries: escalations
+                                 // into each tier, then the spill tier's second pass
   int32_t *counters = nullptr;   // kCounters
   unsigned long long *stats = nullptr;  // kStats
   uint32_t *dummy = nullptr;     // one zero word for empty arenas
@@ -303,7 +304,7 @@ xd_status ensure_capacity(xd_ctx *c, int64_t n_pairs) {
   const size_t o_jsave = off; off = align_up(off + sizeof(int32_t) * nj);
   const size_t o_bins = off; off = align_up(off + sizeof(int32_t) * 3 * kBins);
   const size_t o_order = off; off = align_up(off + sizeof(int32_t) * nj);
-  const size_t o_esc = off; off = align_up(off + sizeof(int32_t) * nj * kLists);
+  const size_t o_esc = off; off = align_up(off + sizeof(int32_t) * nj * (kLists + 1));
   const size_t o_cnt = off; off = align_up(off + sizeof(int32_t) * kCounters);
   const size_t o_stats = off; off = align_up(off + sizeof(unsigned long long) * kStats);
   const size_t o_dummy = off; off = align_up(off + 64);
@@ -467,8 +468,9 @@ xd_status enqueue(xd_ctx *c, hipStream_t s, const Launch &L, bool prof) {
     q.counters = c->counters;
     q.next_esc = nullptr;
     q.tier = kTiers;
-    if (spill_launch(&c->spill, s, c->jobs, q, c->counters + kHead + kTiers, c->outs, c->stats,
-                     P) != XD_OK)
+    if (spill_launch(&c->spill, s, c->jobs, q, c->counters + kHead + kTiers,
+                     c->counters + kHugeHead, c->esc + kLists * stride, c->counters + kHugeCount,
+                     c->outs, c->stats, P) != XD_OK)
       return fail(XD_EDEVICE, "k_spill launch failed");
   }
   if (prof) XD_HIP(hipEventRecord(c->ev[8], s));

@@ -18,7 +18,9 @@ constexpr int kLists = kTiers + 1;          // register tiers + global-memory ti
 // Device counters (int32): initial jobs per tier, jobs escalated into each
 // tier, queue heads, segment offsets in the sorted order.
 constexpr int kInit = 0, kEsc = kLists, kHead = 2 * kLists, kOff = 3 * kLists;
-constexpr int kCounters = 4 * kLists;
+// the spill tier's second pass: jobs moved to it and its queue head
+constexpr int kHugeCount = 4 * kLists, kHugeHead = 4 * kLists + 1;
+constexpr int kCounters = 4 * kLists + 2;
 // Device statistics (uint64): jobs finished, cells of those jobs, escalations;
 // then the bump pointer of the escalation save pool.
 constexpr int kSaveTop = 3 * kLists;

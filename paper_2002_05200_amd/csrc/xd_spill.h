@@ -18,11 +18,27 @@
 namespace xd {
 
 constexpr int kSpillThreads = 256;
-constexpr int kSpillSlots = 8;                 // concurrent spill jobs
-constexpr int64_t kSpillCap = (1 << 20) + 4;   // cells per stored anti-diagonal
+// Two passes: many workgroups whose anti-diagonal buffers hold up to
+// kSpillCap cells, then a few with room for kHugeCap cells for the jobs whose
+// band outgrew the first (they start over there).
+constexpr int kSpillSlots = 512;
+constexpr int64_t kSpillCap = 16384;
+constexpr int kHugeSlots = 8;
+constexpr int64_t kHugeCap = (1 << 20) + 4;
 
 struct SpillScratch {
-  int32_t *buf = nullptr;   // kSpillSlots * 3 * kSpillCap
+  int32_t *buf = nullptr;    // kSpillSlots * 3 * kSpillCap
+  int32_t *huge = nullptr;   // kHugeSlots * 3 * kHugeCap
+};
+
+// Where a spill pass takes its jobs from: a tier queue, or a plain list.
+struct SpillSource {
+  TierQueue q;
+  const int32_t *list;        // nullptr: the tier queue
+  const int32_t *list_count;
+  int32_t *overflow;          // jobs too wide for this pass (nullptr: fail them)
+  int32_t *overflow_count;
+  int64_t cap;                // cells per stored anti-diagonal
 };
 
 __device__ __forceinline__ uint32_t base_at(const uint32_t *W, int64_t g) {
@@ -30,18 +46,20 @@ __device__ __forceinline__ uint32_t base_at(const uint32_t *W, int64_t g) {
 }
 
 __global__ __launch_bounds__(kSpillThreads) void k_spill(const Job *__restrict__ jobs,
-                                                         TierQueue q,
+                                                         SpillSource src,
                                                          int32_t *head, JobOut *__restrict__ outs,
                                                          unsigned long long *stats, Params P,
                                                          int32_t *__restrict__ scratch) {
   __shared__ int32_t s_job;
   __shared__ int32_t s_first, s_last, s_max, s_imax;
   const int tid = threadIdx.x;
-  const int32_t n_init = q.counters[kInit + q.tier];
-  const int32_t n_esc = q.counters[kEsc + q.tier];
+  const TierQueue &q = src.q;
+  const int32_t n_init = src.list ? 0 : q.counters[kInit + q.tier];
+  const int32_t n_esc = src.list ? *src.list_count : q.counters[kEsc + q.tier];
   const int32_t count = n_init + n_esc;
+  const int64_t cap = src.cap;
   int32_t *bufs[3];
-  for (int t = 0; t < 3; ++t) bufs[t] = scratch + ((int64_t)blockIdx.x * 3 + t) * kSpillCap;
+  for (int t = 0; t < 3; ++t) bufs[t] = scratch + ((int64_t)blockIdx.x * 3 + t) * cap;
   const int32_t gap = -P.neg_gap;
   const int32_t mismatch = P.base + 2 * gap;
   const int32_t match = mismatch + P.delta;
@@ -52,16 +70,12 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(const Job *__restrict__
     const int32_t w = s_job;
     __syncthreads();
     if (w >= count) break;
-    const int32_t j = tier_job(q, w, n_init, n_esc);
+    const int32_t j = src.list ? src.list[w] : tier_job(q, w, n_init, n_esc);
     const Job job = jobs[j];
     JobOut out;
     out.best = 0; out.bi = 0; out.bj = 0; out.status = kJobOk; out.cells = 0;
     const int32_t m = job.m, n = job.n;
-    if ((int64_t)(m < n ? m : n) + 2 > kSpillCap) {
-      out.status = XD_ENOMEM;
-      if (tid == 0) outs[j] = out;
-      continue;
-    }
+    bool moved = false;
     // rotating anti-diagonals: [2] = d-2, [1] = d-1, [0] = d
     int32_t *vb[3] = {bufs[0], bufs[1], bufs[2]};
     int32_t lo2 = 1, hi2 = 0;          // d-2 empty
@@ -75,6 +89,10 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(const Job *__restrict__
       int32_t lo = live_lo > d - n ? live_lo : d - n;
       int32_t hi = live_hi + 1 < m ? live_hi + 1 : m;
       if (lo > hi) break;
+      if ((int64_t)(hi - lo + 1) > cap) {   // band wider than this pass holds
+        moved = true;
+        break;
+      }
       const int32_t thr = best - job.x;
       int32_t my_first = 0x7fffffff, my_last = -1, my_max = kNeg, my_imax = 0x7fffffff;
       for (int32_t i = lo + tid; i <= hi; i += kSpillThreads) {
@@ -127,34 +145,68 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(const Job *__restrict__
     }
     out.best = best; out.bi = bi; out.bj = bj; out.cells = cells;
     if (tid == 0) {
-      outs[j] = out;
-      atomicAdd(&stats[q.tier], 1ull);
-      atomicAdd(&stats[kLists + q.tier], (unsigned long long)cells);
+      if (moved && src.overflow) {
+        src.overflow[atomicAdd(src.overflow_count, 1)] = j;
+        atomicAdd(&stats[2 * kLists + q.tier], 1ull);
+      } else {
+        if (moved) out.status = XD_ENOMEM;
+        outs[j] = out;
+        atomicAdd(&stats[q.tier], 1ull);
+        atomicAdd(&stats[kLists + q.tier], (unsigned long long)cells);
+      }
     }
     __syncthreads();
   }
 }
 
 inline xd_status spill_alloc(SpillScratch *sp) {
-  if (sp->buf) return XD_OK;
-  void *p = nullptr;
-  if (hipMalloc(&p, sizeof(int32_t) * 3 * kSpillCap * kSpillSlots) != hipSuccess) return XD_ENOMEM;
-  sp->buf = (int32_t *)p;
+  if (!sp->buf) {
+    void *p = nullptr;
+    if (hipMalloc(&p, sizeof(int32_t) * 3 * kSpillCap * kSpillSlots) != hipSuccess)
+      return XD_ENOMEM;
+    sp->buf = (int32_t *)p;
+  }
+  if (!sp->huge) {
+    void *p = nullptr;
+    if (hipMalloc(&p, sizeof(int32_t) * 3 * kHugeCap * kHugeSlots) != hipSuccess)
+      return XD_ENOMEM;
+    sp->huge = (int32_t *)p;
+  }
   return XD_OK;
 }
 
+// Both passes over the spill tier's queue; `huge_list` has room for every job.
 inline xd_status spill_launch(SpillScratch *sp, hipStream_t s, const Job *jobs,
-                              const TierQueue &q, int32_t *head, JobOut *outs,
+                              const TierQueue &q, int32_t *head, int32_t *huge_head,
+                              int32_t *huge_list, int32_t *huge_count, JobOut *outs,
                               unsigned long long *stats, const Params &P) {
-  if (!sp->buf) return XD_ENOMEM;
-  hipLaunchKernelGGL(k_spill, dim3(kSpillSlots), dim3(kSpillThreads), 0, s, jobs, q, head, outs,
+  if (!sp->buf || !sp->huge) return XD_ENOMEM;
+  SpillSource a;
+  a.q = q;
+  a.list = nullptr;
+  a.list_count = nullptr;
+  a.overflow = huge_list;
+  a.overflow_count = huge_count;
+  a.cap = kSpillCap;
+  hipLaunchKernelGGL(k_spill, dim3(kSpillSlots), dim3(kSpillThreads), 0, s, jobs, a, head, outs,
                      stats, P, sp->buf);
+  if (hipGetLastError() != hipSuccess) return XD_EDEVICE;
+  SpillSource b = a;
+  b.list = huge_list;
+  b.list_count = huge_count;
+  b.overflow = nullptr;
+  b.overflow_count = nullptr;
+  b.cap = kHugeCap;
+  hipLaunchKernelGGL(k_spill, dim3(kHugeSlots), dim3(kSpillThreads), 0, s, jobs, b, huge_head,
+                     outs, stats, P, sp->huge);
   return hipGetLastError() == hipSuccess ? XD_OK : XD_EDEVICE;
 }
 
 inline void spill_free(SpillScratch *sp) {
   if (sp->buf) (void)hipFree(sp->buf);
+  if (sp->huge) (void)hipFree(sp->huge);
   sp->buf = nullptr;
+  sp->huge = nullptr;
 }
 
 }  // namespace xd

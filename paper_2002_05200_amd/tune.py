@@ -98,6 +98,8 @@ def tune(ctx, db, reps: int = 3, log=None) -> dict:
                 continue                      # the split does nothing without a bias
             if cand["long_tier_bias"] > 0 and cand["long_job"] == 0:
                 cand["long_job"] = CANDIDATES["long_job"][0]
+            if log:
+                log(f"  timing {cand}")
             ms = time_opts(ctx, db, cand, reps)
             tried.append((dict(cand), ms))
             if log:
@@ -115,13 +117,18 @@ def main():
     ap = argparse.ArgumentParser(description="tune launch options per workload class")
     ap.add_argument("--workloads", default="batch10k,uneven,ultralong,plain1k")
     ap.add_argument("--pairs", type=int, default=0, help="0 = the whole workload")
+    ap.add_argument("--sample", type=int, default=20000,
+                    help="tune on an evenly spread sample of this many pairs (0 = all)")
     ap.add_argument("--out", default=TABLE_PATH)
     args = ap.parse_args()
     table = load_table(args.out)
     ctx = xdrop.Context(0)
     for wl in args.workloads.split(","):
-        n = args.pairs or synth.WORKLOADS[wl].n_pairs
-        bt = synth.make_batch(wl, n=n, workers=min(16, os.cpu_count() or 1))
+        total = args.pairs or synth.WORKLOADS[wl].n_pairs
+        if args.sample and args.sample < total:
+            bt = synth.make_batch(wl, n=args.sample, stride=total // args.sample)
+        else:
+            bt = synth.make_batch(wl, n=total, workers=min(16, os.cpu_count() or 1))
         db = xdrop.DeviceBatch(bt, "cuda:0")
         cls = batch_class(bt)
         print(f"[tune] {wl}: class {cls}, {bt.n} pairs", flush=True)

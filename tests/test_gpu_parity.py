@@ -318,3 +318,21 @@ def test_score_words_follow_the_window_after_a_recentre(ctx, xd):
     a, b = bt.pair(196)
     one = synth.from_pairs([a], [b], [int(bt.a_seed[196])], [int(bt.b_seed[196])], [21], name="p196")
     assert_same(run(ctx, xd, one), oracle_of(one), "pair 196, X = 21")
+
+
+def test_bands_wider_than_the_first_spill_pass(ctx, xd):
+    """Unbounded X on 40 kb unrelated reads seeded in the middle: anti-
+    diagonals reach 20,000 cells, more than the first global-memory pass
+    holds, so the job moves to the second pass and starts over there."""
+    from paper_2002_05200_amd import synth
+    r = np.random.default_rng(7)
+    L = 40000
+    a = r.integers(0, 4, L).astype(np.uint8)
+    b = r.integers(0, 4, L).astype(np.uint8)
+    b[L // 2: L // 2 + 17] = a[L // 2: L // 2 + 17]
+    bt = synth.from_pairs([a], [b], [L // 2], [L // 2], [1 << 20], name="x_unbounded_40k")
+    got = run(ctx, xd, bt)
+    st = ctx.stats()
+    assert st["escalated"][6] == 2, st
+    assert st["jobs"][6] == 2, st
+    assert_same(got, oracle_of(bt), "second spill pass")
