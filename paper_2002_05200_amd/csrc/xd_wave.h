@@ -96,8 +96,9 @@ XD_FN vint from_next_lane(vint a, int32_t fill) {
 }
 // whole-wave rotations: lane t receives lane t-1 (lane 0 receives lane 63),
 // resp. lane t+1 (lane 63 receives lane 0)  -> wave_ror:1 / wave_rol:1
-XD_FN vint rot_prev(vint a) { return {__builtin_amdgcn_update_dpp(a.x, a.x, 0x13c, 0xf, 0xf, false)}; }
-XD_FN vint rot_next(vint a) { return {__builtin_amdgcn_update_dpp(a.x, a.x, 0x134, 0xf, 0xf, false)}; }
+// (every lane is written, so no "old" value is needed)
+XD_FN vint rot_prev(vint a) { return {__builtin_amdgcn_mov_dpp(a.x, 0x13c, 0xf, 0xf, false)}; }
+XD_FN vint rot_next(vint a) { return {__builtin_amdgcn_mov_dpp(a.x, 0x134, 0xf, 0xf, false)}; }
 // lane t receives lane (t + delta)'s value, `fill` where that lane does not exist
 XD_FN vint from_lane_offset(vint a, int delta, int32_t fill) {
   int src = lane_id() + delta;

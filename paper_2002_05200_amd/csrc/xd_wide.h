@@ -81,8 +81,61 @@ XD_FN void wbuild(WBand<C> &bd, WScalars &st, int32_t e0, int32_t r0, int32_t r1
   st.w_hi = r1;
 }
 
+// Cell update of register R of the span (no range clipping; see wstep).
+template <int C, bool NARROW, int PAR, int R>
+XD_FN void wcell(vint *cur, const vint *prv, const vint *sw, int pos, int32_t thr, int32_t bw,
+                 uint64_t &imp, const Params &P) {
+  vint t;
+  if (PAR == 0) {   // even d: predecessors in slots s-1 and s
+    const vint own = rot_prev(prv[R]);
+    const vint below = R > 0 ? rot_prev(prv[R > 0 ? R - 1 : 0]) : splat(kNeg);
+    t = select(lanes(1ull), below, own);
+  } else {          // odd d: predecessors in slots s and s+1
+    const vint own = rot_next(prv[R]);
+    const vint above = R < C - 1 ? rot_next(prv[R < C - 1 ? R + 1 : R]) : splat(kNeg);
+    t = select(lanes(1ull << 63), above, own);
+  }
+  const vint v = vmax3(diag_term<NARROW>(cur[R], sw[R], pos, P), prv[R], t);
+  cur[R] = select(v >= thr, v, kNeg);
+  imp |= ballot(cur[R] > bw);
+}
+
+// Clips register R, an edge of the span, to the range lanes in `mask`;
+// returns its surviving lanes.
+template <int R>
+XD_FN uint64_t wclip(vint *cur, uint64_t mask) {
+  cur[R] = select(lanes(mask), cur[R], kNeg);
+  return ballot(cur[R] != kNeg);
+}
+
+template <int C>
+XD_FN uint64_t wclip_at(vint *cur, int r, uint64_t mask) {
+  switch (r) {
+#define XD_CLIP_CASE(R) \
+  case R:               \
+    if constexpr (R < C) return wclip<R>(cur, mask); \
+    return 0;
+    XD_CLIP_CASE(0) XD_CLIP_CASE(1) XD_CLIP_CASE(2) XD_CLIP_CASE(3) XD_CLIP_CASE(4)
+    XD_CLIP_CASE(5) XD_CLIP_CASE(6) XD_CLIP_CASE(7) XD_CLIP_CASE(8) XD_CLIP_CASE(9)
+    XD_CLIP_CASE(10) XD_CLIP_CASE(11) XD_CLIP_CASE(12) XD_CLIP_CASE(13) XD_CLIP_CASE(14)
+    XD_CLIP_CASE(15) XD_CLIP_CASE(16) XD_CLIP_CASE(17) XD_CLIP_CASE(18) XD_CLIP_CASE(19)
+    XD_CLIP_CASE(20) XD_CLIP_CASE(21) XD_CLIP_CASE(22) XD_CLIP_CASE(23) XD_CLIP_CASE(24)
+    XD_CLIP_CASE(25) XD_CLIP_CASE(26) XD_CLIP_CASE(27) XD_CLIP_CASE(28) XD_CLIP_CASE(29)
+    XD_CLIP_CASE(30) XD_CLIP_CASE(31)
+#undef XD_CLIP_CASE
+    default:
+      return 0;
+  }
+}
+
 // Anti-diagonal st.d (parity PAR) at step q of the score-word block; then
 // prepares st for d + 1.  Returns false once the extension has ended.
+//
+// The span's registers rlo .. rhi are updated in one fall-through sequence
+// entered at rlo (a jump table), each followed by a test for rhi; range
+// clipping is applied afterwards to the two edge registers only.  Lanes
+// outside the range in those registers may briefly hold values above best,
+// so an improvement seen during the update is confirmed after clipping.
 template <int C, bool NARROW, int PAR>
 XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Params &P) {
   vint *cur = PAR ? bd.O : bd.E;          // d - 2 on entry, d on exit
@@ -91,42 +144,75 @@ XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Par
   const int pos = 2 * q;
   const int rlo = st.lo >> 6, rhi = st.hi >> 6;
   const int plo = st.span_lo[PAR], phi = st.span_hi[PAR];
+  if (plo < rlo || phi > rhi) {           // registers leaving the span become -inf
+#pragma unroll
+    for (int r = 0; r < C; ++r)
+      if ((r < rlo || r > rhi) && r >= plo && r <= phi) cur[r] = splat(kNeg);
+  }
+  const int32_t thr = st.thr, bw = st.bw;
+  uint64_t imp = 0;
+  switch (rlo) {
+#define XD_SPAN_CASE(R)                                               \
+  case R:                                                             \
+    if constexpr (R < C) {                                            \
+      wcell<C, NARROW, PAR, R>(cur, prv, sw, pos, thr, bw, imp, P);   \
+      if (rhi == R) break;                                            \
+    }                                                                 \
+    [[fallthrough]];
+    XD_SPAN_CASE(0) XD_SPAN_CASE(1) XD_SPAN_CASE(2) XD_SPAN_CASE(3) XD_SPAN_CASE(4)
+    XD_SPAN_CASE(5) XD_SPAN_CASE(6) XD_SPAN_CASE(7) XD_SPAN_CASE(8) XD_SPAN_CASE(9)
+    XD_SPAN_CASE(10) XD_SPAN_CASE(11) XD_SPAN_CASE(12) XD_SPAN_CASE(13) XD_SPAN_CASE(14)
+    XD_SPAN_CASE(15) XD_SPAN_CASE(16) XD_SPAN_CASE(17) XD_SPAN_CASE(18) XD_SPAN_CASE(19)
+    XD_SPAN_CASE(20) XD_SPAN_CASE(21) XD_SPAN_CASE(22) XD_SPAN_CASE(23) XD_SPAN_CASE(24)
+    XD_SPAN_CASE(25) XD_SPAN_CASE(26) XD_SPAN_CASE(27) XD_SPAN_CASE(28) XD_SPAN_CASE(29)
+    XD_SPAN_CASE(30) XD_SPAN_CASE(31)
+#undef XD_SPAN_CASE
+    default:
+      break;
+  }
+  // clip the edge registers to the computed range
   const uint64_t lo_mask = ~0ull << (st.lo & 63);
   const uint64_t hi_mask = ~0ull >> (63 - (st.hi & 63));
-  uint64_t imp = 0;
-  int first = -1, last = -1;
-#pragma unroll
-  for (int r = 0; r < C; ++r) {
-    if (r < rlo || r > rhi) {
-      if (r >= plo && r <= phi) cur[r] = splat(kNeg);   // left the span
-      continue;
-    }
-    vint t;
-    if (PAR == 0) {   // even d: predecessors in slots s-1 and s
-      const vint own = rot_prev(prv[r]);
-      const vint below = r > 0 ? rot_prev(prv[r - 1]) : splat(kNeg);
-      t = select(lanes(1ull), below, own);
-    } else {          // odd d: predecessors in slots s and s+1
-      const vint own = rot_next(prv[r]);
-      const vint above = r < C - 1 ? rot_next(prv[r + 1]) : splat(kNeg);
-      t = select(lanes(1ull << 63), above, own);
-    }
-    const vint v = vmax3(diag_term<NARROW>(cur[r], sw[r], pos, P), prv[r], t);
-    uint64_t range = ~0ull;
-    if (r == rlo) range &= lo_mask;
-    if (r == rhi) range &= hi_mask;
-    const uint64_t live = ballot(v >= st.thr) & range;
-    cur[r] = select(lanes(live), v, kNeg);
-    if (live != 0) {
-      if (first < 0) first = 64 * r + ctz64(live);
-      last = 64 * r + last_bit64(live);
-    }
-    imp |= ballot(cur[r] > st.bw);
+  uint64_t live_lo, live_hi;
+  if (rlo == rhi) {
+    live_lo = live_hi = wclip_at<C>(cur, rlo, lo_mask & hi_mask);
+  } else {
+    live_lo = wclip_at<C>(cur, rlo, lo_mask);
+    live_hi = wclip_at<C>(cur, rhi, hi_mask);
   }
   st.span_lo[PAR] = rlo;
   st.span_hi[PAR] = rhi;
   st.cells_blk += (uint32_t)(st.hi - st.lo + 1);
+
+  // first and last survivors: normally in the edge registers, else searched
+  int first = -1, last = -1;
+  if (live_lo != 0) {
+    first = 64 * rlo + ctz64(live_lo);
+  } else {
+#pragma unroll
+    for (int r = 0; r < C; ++r) {
+      if (first >= 0 || r <= rlo || r > rhi) continue;
+      const uint64_t m = ballot(cur[r] != kNeg);
+      if (m != 0) first = 64 * r + ctz64(m);
+    }
+  }
   if (first < 0) return false;
+  if (live_hi != 0) {
+    last = 64 * rhi + last_bit64(live_hi);
+  } else {
+#pragma unroll
+    for (int r = C - 1; r >= 0; --r) {
+      if (last >= 0 || r < rlo || r >= rhi) continue;
+      const uint64_t m = ballot(cur[r] != kNeg);
+      if (m != 0) last = 64 * r + last_bit64(m);
+    }
+  }
+  if (imp != 0) {   // confirm on the clipped registers
+    imp = 0;
+#pragma unroll
+    for (int r = 0; r < C; ++r)
+      if (r >= rlo && r <= rhi) imp |= ballot(cur[r] > st.bw);
+  }
 
   // best is updated once the whole anti-diagonal is known (Section IV-A)
   if (imp != 0) {
@@ -173,25 +259,91 @@ XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Par
   return true;
 }
 
+// Lanes [lo, hi] of a 64-lane register, empty when the range misses it.
+XD_FN uint64_t lane_span(int lo, int hi) {
+  lo = lo < 0 ? 0 : lo;
+  hi = hi > 63 ? 63 : hi;
+  return lo > hi ? 0ull : ((~0ull >> (63 - hi)) & (~0ull << lo));
+}
+
+// Two registers (128 slots): the same step in straight-line form, both
+// registers always updated and clipped by their lane masks.
+template <bool NARROW, int PAR>
+XD_FN bool wstep2(WBand<2> &bd, WScalars &st, int q, const JobView &jv, const Params &P) {
+  vint *cur = PAR ? bd.O : bd.E;
+  const vint *prv = PAR ? bd.E : bd.O;
+  const vint *sw = PAR ? bd.SO : bd.SE;
+  const int pos = 2 * q;
+  vint t0, t1;
+  if (PAR == 0) {   // slots s-1, s: register 1's lane 0 reads register 0's lane 63
+    t0 = rot_prev(prv[0]);
+    t1 = select(lanes(1ull), t0, rot_prev(prv[1]));
+  } else {          // slots s, s+1: register 0's lane 63 reads register 1's lane 0
+    t1 = rot_next(prv[1]);
+    t0 = select(lanes(1ull << 63), t1, rot_next(prv[0]));
+  }
+  const vint v0 = vmax3(diag_term<NARROW>(cur[0], sw[0], pos, P), prv[0], t0);
+  const vint v1 = vmax3(diag_term<NARROW>(cur[1], sw[1], pos, P), prv[1], t1);
+  const uint64_t m0 = ballot(v0 >= st.thr) & lane_span(st.lo, st.hi);
+  const uint64_t m1 = ballot(v1 >= st.thr) & lane_span(st.lo - 64, st.hi - 64);
+  cur[0] = select(lanes(m0), v0, kNeg);
+  cur[1] = select(lanes(m1), v1, kNeg);
+  st.span_lo[PAR] = 0;
+  st.span_hi[PAR] = 1;
+  st.cells_blk += (uint32_t)(st.hi - st.lo + 1);
+  if ((m0 | m1) == 0) return false;
+  const int first = m0 ? ctz64(m0) : 64 + ctz64(m1);
+  const int last = m1 ? 64 + last_bit64(m1) : last_bit64(m0);
+  if ((ballot(cur[0] > st.bw) | ballot(cur[1] > st.bw)) != 0) {
+    int inc = 1;
+    while ((ballot(cur[0] > st.bw + inc) | ballot(cur[1] > st.bw + inc)) != 0) ++inc;
+    st.bw += inc;
+    st.thr += inc;
+    st.best += inc;
+    const uint64_t e0 = ballot(cur[0] == st.bw);
+    const int sbest = e0 ? ctz64(e0) : 64 + ctz64(ballot(cur[1] == st.bw));
+    st.bi = sbest + ((st.d + 1) >> 1) + st.h;
+    st.bj = st.d - st.bi;
+  }
+  const int d1 = st.d + 1;
+  if (d1 > jv.m + jv.n) return false;
+  int lo = PAR ? first : first - 1;
+  int hi = PAR ? last + 1 : last;
+  const int c1 = (d1 + 1) >> 1;
+  const int i_min = d1 - jv.n > 0 ? d1 - jv.n : 0;
+  const int smin = i_min - c1 - st.h;
+  const int smax = jv.m - c1 - st.h;
+  lo = lo > smin ? lo : smin;
+  hi = hi < smax ? hi : smax;
+  if (lo > hi) return false;
+  st.d = d1;
+  st.lo = lo;
+  st.hi = hi;
+  st.bw += P.neg_gap;
+  st.thr += P.neg_gap;
+  return true;
+}
+
 // new slot s <- old slot s + m, 0 < |m| < 64; slots from outside the window
-// become -inf.
+// become -inf.  In place: upward shifts read registers r and r+1, so they run
+// in ascending order; downward ones read r and r-1 and run descending.
 template <int C>
 XD_FN void wshift(vint *a, int m) {
-  vint out[C];
+  if (m > 0) {
 #pragma unroll
-  for (int r = 0; r < C; ++r) {
-    if (m > 0) {
+    for (int r = 0; r < C; ++r) {
       const vint here = from_lane_offset(a[r], m, kNeg);
       const vint next = r + 1 < C ? from_lane_offset(a[r + 1], m - 64, kNeg) : splat(kNeg);
-      out[r] = vmax(here, next);   // exactly one of the two is a slot; the other is -inf
-    } else {
+      a[r] = vmax(here, next);   // exactly one of the two is a slot; the other is -inf
+    }
+  } else {
+#pragma unroll
+    for (int r = C - 1; r >= 0; --r) {
       const vint here = from_lane_offset(a[r], m, kNeg);
       const vint prev = r > 0 ? from_lane_offset(a[r - 1], m + 64, kNeg) : splat(kNeg);
-      out[r] = vmax(here, prev);
+      a[r] = vmax(here, prev);
     }
   }
-#pragma unroll
-  for (int r = 0; r < C; ++r) a[r] = out[r];
 }
 
 // Moves the window so the pending range sits in its middle.  Returns false
@@ -330,7 +482,10 @@ XD_FN JobOut extend_job_wide(const Job &job, const Params &P, int32_t j) {
       }
       if ((st.lo >> 6) < st.w_lo || (st.hi >> 6) > st.w_hi)
         wbuild<C, NARROW>(bd, st, e0, (st.lo >> 6) - 1, (st.hi >> 6) + 1, jv, P);
-      if (!wstep<C, NARROW, 0>(bd, st, e - e0, jv, P)) break;   // d = 2e
+      bool go;
+      if constexpr (C == 2) go = wstep2<NARROW, 0>(bd, st, e - e0, jv, P);
+      else go = wstep<C, NARROW, 0>(bd, st, e - e0, jv, P);
+      if (!go) break;                                           // d = 2e
     }
     odd = false;
     if (st.lo < 1 || st.hi > S - 2) {
@@ -338,7 +493,10 @@ XD_FN JobOut extend_job_wide(const Job &job, const Params &P, int32_t j) {
     }
     if ((st.lo >> 6) < st.w_lo || (st.hi >> 6) > st.w_hi)
       wbuild<C, NARROW>(bd, st, e0, (st.lo >> 6) - 1, (st.hi >> 6) + 1, jv, P);
-    if (!wstep<C, NARROW, 1>(bd, st, e - e0, jv, P)) break;     // d = 2e + 1
+    bool go;
+    if constexpr (C == 2) go = wstep2<NARROW, 1>(bd, st, e - e0, jv, P);
+    else go = wstep<C, NARROW, 1>(bd, st, e - e0, jv, P);
+    if (!go) break;                                             // d = 2e + 1
     ++e;
   }
   if (!ok) {
