@@ -56,8 +56,8 @@ enum : int32_t {
   kSvD = 0, kSvLo, kSvHi, kSvH, kSvBest, kSvBi, kSvBj, kSvBw, kSvThr, kSvC, kSvCellsLo,
   kSvCellsHi, kSaveHdr = 16
 };
-// One save slot holds the widest band that can still escalate to a register
-// tier (C = 16); a job keeps its slot for all its escalations.
-constexpr int32_t kSaveSlotWords = kSaveHdr + 2 * 64 * 16;
+// One save slot holds the widest single-wave band (C = 32); a job keeps its
+// slot for all its escalations.
+constexpr int32_t kSaveSlotWords = kSaveHdr + 2 * 64 * 32;
 
 }  // namespace xd

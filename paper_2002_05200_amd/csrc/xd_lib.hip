@@ -37,6 +37,7 @@
 #include "xd_spill.h"
 #include "xd_w1_asm.h"
 #include "xd_wide.h"
+#include "xd_multi.h"
 
 namespace xd {
 
@@ -319,7 +320,7 @@ xd_status ensure_capacity(xd_ctx *c, int64_t n_pairs) {
   if (hipMalloc(&p, off) != hipSuccess) return fail(XD_ENOMEM, "hipMalloc of job scratch failed");
   c->scratch.ptr = p;
   c->scratch.bytes = off;
-  if (!c->spill.buf && spill_alloc(&c->spill) != XD_OK)
+  if (!c->spill.huge && spill_alloc(&c->spill) != XD_OK)
     return fail(XD_ENOMEM, "hipMalloc of the global-memory band buffers failed");
   {   // escalation saves: one slot per job, at most 2 GiB
     const uint64_t max_slots = (2ull << 30) / (sizeof(int32_t) * kSaveSlotWords);
@@ -461,16 +462,25 @@ xd_status enqueue(xd_ctx *c, hipStream_t s, const Launch &L, bool prof) {
   hipError_t e = narrow ? launch_tiers<true>(c, s, persistent, o.waves_per_cu, nj, P, prof)
                         : launch_tiers<false>(c, s, persistent, o.waves_per_cu, nj, P, prof);
   if (e != hipSuccess) return fail(XD_EDEVICE, std::string("k_extend: ") + hipGetErrorString(e));
-  {
+  {   // bands wider than one wavefront: a workgroup per job, then global memory
     TierQueue q;
     q.order = c->order;
     q.esc = c->esc + kTiers * stride;
     q.counters = c->counters;
     q.next_esc = nullptr;
     q.tier = kTiers;
-    if (spill_launch(&c->spill, s, c->jobs, q, c->counters + kHead + kTiers,
-                     c->counters + kHugeHead, c->esc + kLists * stride, c->counters + kHugeCount,
-                     c->outs, c->stats, P) != XD_OK)
+    int32_t *huge_list = c->esc + kLists * stride;
+    if (narrow)
+      hipLaunchKernelGGL(k_extend_mw<true>, dim3((unsigned)c->num_cu), dim3(kMwThreads), 0, s,
+                         c->jobs, q, c->counters + kHead + kTiers, c->outs, c->stats, P,
+                         huge_list, c->counters + kHugeCount);
+    else
+      hipLaunchKernelGGL(k_extend_mw<false>, dim3((unsigned)c->num_cu), dim3(kMwThreads), 0, s,
+                         c->jobs, q, c->counters + kHead + kTiers, c->outs, c->stats, P,
+                         huge_list, c->counters + kHugeCount);
+    XD_HIP(hipGetLastError());
+    if (spill_launch(&c->spill, s, c->jobs, q, c->counters + kHugeHead, huge_list,
+                     c->counters + kHugeCount, c->outs, c->stats, P) != XD_OK)
       return fail(XD_EDEVICE, "k_spill launch failed");
   }
   if (prof) XD_HIP(hipEventRecord(c->ev[8], s));

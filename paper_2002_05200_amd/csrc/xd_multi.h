@@ -1,0 +1,430 @@
+// xd_multi.h -- X-drop extension of one job by a whole workgroup, for bands
+// wider than one wavefront's registers hold (more than 2,046 cells).
+//
+// kMwWaves wavefronts each own a chunk of kMwC registers (64 kMwC slots, the
+// slots interleaved across the chunk's registers as in xd_wide.h), so the
+// window is kMwSlots = 64 kMwC kMwWaves diagonal slots.  Per anti-diagonal
+// every wave updates the part of the computed range that falls in its chunk
+// with the single-wave step, clips its edge registers, and posts to LDS
+//   * its chunk's first and last slot values (the neighbours the adjacent
+//     waves need on the next anti-diagonal), and
+//   * its first and last survivor and its best value with the first slot
+//     holding it;
+// after one barrier every wave reduces the posts identically (first live =
+// min, last live = max, best = max with the lowest slot), so all waves carry
+// the same scalar state and take the same branches.  Posts alternate between
+// two LDS buffers by parity, so one barrier per anti-diagonal suffices.  This
+// is the paper's many-threads-per-alignment layout (Section IV-A) with the
+// band in registers instead of global memory.
+#pragma once
+
+#include "xd_wide.h"
+#ifndef XD_EMULATION
+#include "xd_queue.h"
+#endif
+
+namespace xd {
+
+constexpr int kMwWaves = 16;
+constexpr int kMwC = 8;
+constexpr int kMwChunk = 64 * kMwC;
+constexpr int kMwSlots = kMwChunk * kMwWaves;   // 8192
+constexpr int kMwThreads = 64 * kMwWaves;
+
+struct MwShared {
+  int32_t job;
+  int32_t edge[2][kMwWaves][2];   // by parity: chunk's first and last slot value
+  int32_t red[2][kMwWaves][4];    // by parity: first, last, best value, its slot
+  int32_t stage[kMwSlots];        // window moves: one anti-diagonal by slot
+};
+
+// Block-wide scalar state (every wave keeps an identical copy).
+struct MwScalars {
+  int32_t d, lo, hi, h;           // global slots
+  int32_t best, bi, bj, bw, thr;
+  int32_t span_lo[2], span_hi[2]; // this wave's registers last computed per parity
+  int32_t w_lo, w_hi;             // this wave's registers with score words
+  uint32_t cells_blk;
+  uint64_t cells;
+};
+
+// Score words of this wave's registers [r0, r1] (chunk starting at slot base).
+template <bool NARROW>
+XD_FN void mw_build(WBand<kMwC> &bd, MwScalars &st, int32_t base, int32_t e0, int32_t r0,
+                    int32_t r1, const JobView &jv, const Params &P) {
+  if (r0 < 0) r0 = 0;
+  if (r1 > kMwC - 1) r1 = kMwC - 1;
+  const vint l = lane_index();
+#pragma unroll
+  for (int r = 0; r < kMwC; ++r) {
+    if (r < r0 || r > r1) continue;
+    const vint s = l + (base + 64 * r);
+    const vint i0 = s + (st.h + e0);
+    const vint j0 = splat(e0 - st.h) - s;
+    vint offAe, offAo, offB;
+    if (jv.dir > 0) {
+      offAe = i0 - 1;
+      offAo = i0;
+      offB = j0 - 1;
+    } else {
+      offAe = splat(-14) - i0;
+      offAo = splat(-15) - i0;
+      offB = splat(-14) - j0;
+    }
+    const vint wb = window16(jv.B, offB);
+    vint xe = window16(jv.A, offAe) ^ wb;
+    vint xo = window16(jv.A, offAo) ^ wb;
+    if (jv.dir < 0) {
+      xe = bit_reverse(xe);
+      xo = bit_reverse(xo);
+    }
+    bd.SE[r] = score_word<NARROW>(xe, P.pat);
+    bd.SO[r] = score_word<NARROW>(xo, P.pat);
+  }
+  st.w_lo = r0;
+  st.w_hi = r1;
+}
+
+// Posts both parities' chunk-edge values (after the band was (re)loaded).
+XD_FN void mw_post_edges(const WBand<kMwC> &bd, MwShared &sh, int w) {
+  if (lane_id() == 0) {
+    sh.edge[0][w][0] = readlane(bd.E[0], 0);
+    sh.edge[0][w][1] = readlane(bd.E[kMwC - 1], 63);
+    sh.edge[1][w][0] = readlane(bd.O[0], 0);
+    sh.edge[1][w][1] = readlane(bd.O[kMwC - 1], 63);
+  }
+}
+
+// Anti-diagonal st.d (parity PAR).  Returns false once the extension ended.
+template <bool NARROW, int PAR>
+XD_FN bool mw_step(WBand<kMwC> &bd, MwScalars &st, MwShared &sh, int w, int q,
+                   const JobView &jv, const Params &P) {
+  constexpr int C = kMwC;
+  vint *cur = PAR ? bd.O : bd.E;
+  const vint *prv = PAR ? bd.E : bd.O;
+  const vint *sw = PAR ? bd.SO : bd.SE;
+  const int pos = 2 * q;
+  const int base = w * kMwChunk;
+  // this chunk's part of the range
+  const int cl = st.lo - base > 0 ? st.lo - base : 0;
+  const int ch = st.hi - base < kMwChunk - 1 ? st.hi - base : kMwChunk - 1;
+  const bool active = cl <= ch;
+  const int rlo = active ? cl >> 6 : 1, rhi = active ? ch >> 6 : 0;
+  const int plo = st.span_lo[PAR], phi = st.span_hi[PAR];
+  if (plo < rlo || phi > rhi) {
+#pragma unroll
+    for (int r = 0; r < C; ++r)
+      if ((r < rlo || r > rhi) && r >= plo && r <= phi) cur[r] = splat(kNeg);
+  }
+  int first = 0x7fffffff, last = -1, bestv = kNeg, bests = 0x7fffffff;
+  if (active) {
+    if (rlo < st.w_lo || rhi > st.w_hi)
+      mw_build<NARROW>(bd, st, base, (st.d >> 1) - q, rlo - 1, rhi + 1, jv, P);
+    // neighbours in the adjacent chunks, posted on the previous anti-diagonal
+    const int32_t nb_below = w > 0 ? sh.edge[1 - PAR][w - 1][1] : kNeg;
+    const int32_t nb_above = w < kMwWaves - 1 ? sh.edge[1 - PAR][w + 1][0] : kNeg;
+    const int32_t thr = st.thr, bw = st.bw;
+    uint64_t imp = 0;
+    switch (rlo) {
+#define XD_MW_CASE(R)                                                                      \
+  case R:                                                                                  \
+    if constexpr (R < C) {                                                                 \
+      wcell<C, NARROW, PAR, R>(cur, prv, sw, pos, thr, bw, imp, P, nb_below, nb_above);    \
+      if (rhi == R) break;                                                                 \
+    }                                                                                      \
+    [[fallthrough]];
+      XD_MW_CASE(0) XD_MW_CASE(1) XD_MW_CASE(2) XD_MW_CASE(3) XD_MW_CASE(4) XD_MW_CASE(5)
+      XD_MW_CASE(6) XD_MW_CASE(7)
+#undef XD_MW_CASE
+      default:
+        break;
+    }
+    const uint64_t lo_mask = ~0ull << (cl & 63);
+    const uint64_t hi_mask = ~0ull >> (63 - (ch & 63));
+    uint64_t live_lo, live_hi;
+    if (rlo == rhi) {
+      live_lo = live_hi = wclip_at<C>(cur, rlo, lo_mask & hi_mask);
+    } else {
+      live_lo = wclip_at<C>(cur, rlo, lo_mask);
+      live_hi = wclip_at<C>(cur, rhi, hi_mask);
+    }
+    if (live_lo != 0) {
+      first = base + 64 * rlo + ctz64(live_lo);
+    } else {
+#pragma unroll
+      for (int r = 0; r < C; ++r) {
+        if (first != 0x7fffffff || r <= rlo || r > rhi) continue;
+        const uint64_t m = ballot(cur[r] != kNeg);
+        if (m != 0) first = base + 64 * r + ctz64(m);
+      }
+    }
+    if (live_hi != 0) {
+      last = base + 64 * rhi + last_bit64(live_hi);
+    } else {
+#pragma unroll
+      for (int r = C - 1; r >= 0; --r) {
+        if (last >= 0 || r < rlo || r >= rhi) continue;
+        const uint64_t m = ballot(cur[r] != kNeg);
+        if (m != 0) last = base + 64 * r + last_bit64(m);
+      }
+    }
+    if (imp != 0) {   // this chunk's best value above bw and its first slot
+      int inc = 0;
+      for (;;) {
+        uint64_t more = 0;
+#pragma unroll
+        for (int r = 0; r < C; ++r)
+          if (r >= rlo && r <= rhi) more |= ballot(cur[r] > bw + inc);
+        if (more == 0) break;
+        ++inc;
+      }
+      if (inc > 0) {
+        bestv = bw + inc;
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+          if (bests != 0x7fffffff || r < rlo || r > rhi) continue;
+          const uint64_t m = ballot(cur[r] == bestv);
+          if (m != 0) bests = base + 64 * r + ctz64(m);
+        }
+      }
+    }
+  }
+  st.span_lo[PAR] = rlo;
+  st.span_hi[PAR] = rhi;
+  if (lane_id() == 0) {
+    sh.edge[PAR][w][0] = readlane(cur[0], 0);
+    sh.edge[PAR][w][1] = readlane(cur[C - 1], 63);
+    sh.red[PAR][w][0] = first;
+    sh.red[PAR][w][1] = last;
+    sh.red[PAR][w][2] = bestv;
+    sh.red[PAR][w][3] = bests;
+  }
+  __syncthreads();
+  int gfirst = 0x7fffffff, glast = -1, gbest = kNeg, gslot = 0x7fffffff;
+#pragma unroll
+  for (int v = 0; v < kMwWaves; ++v) {
+    const int f = sh.red[PAR][v][0], l = sh.red[PAR][v][1], b = sh.red[PAR][v][2];
+    gfirst = f < gfirst ? f : gfirst;
+    glast = l > glast ? l : glast;
+    if (b > gbest) {   // waves are in slot order: the first wave with the max
+      gbest = b;
+      gslot = sh.red[PAR][v][3];
+    }
+  }
+  st.cells_blk += (uint32_t)(st.hi - st.lo + 1);
+  if (glast < 0) return false;
+  if (gbest > st.bw) {
+    const int inc = gbest - st.bw;
+    st.bw += inc;
+    st.thr += inc;
+    st.best += inc;
+    st.bi = gslot + ((st.d + 1) >> 1) + st.h;
+    st.bj = st.d - st.bi;
+  }
+  const int d1 = st.d + 1;
+  if (d1 > jv.m + jv.n) return false;
+  int lo = PAR ? gfirst : gfirst - 1;
+  int hi = PAR ? glast + 1 : glast;
+  const int c1 = (d1 + 1) >> 1;
+  const int i_min = d1 - jv.n > 0 ? d1 - jv.n : 0;
+  const int smin = i_min - c1 - st.h;
+  const int smax = jv.m - c1 - st.h;
+  lo = lo > smin ? lo : smin;
+  hi = hi < smax ? hi : smax;
+  if (lo > hi) return false;
+  st.d = d1;
+  st.lo = lo;
+  st.hi = hi;
+  st.bw += P.neg_gap;
+  st.thr += P.neg_gap;
+  return true;
+}
+
+// Window move through the LDS stage, one anti-diagonal at a time: new slot
+// s <- old slot s + dl (-inf from outside the window).
+XD_FN void mw_move(vint *a, MwShared &sh, int base, int dl) {
+  const vint l = lane_index();
+  __syncthreads();                       // the stage is free
+#pragma unroll
+  for (int r = 0; r < kMwC; ++r) store_vec(sh.stage + base + 64 * r, l, a[r]);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kMwC; ++r) {
+    const vint src = l + (base + 64 * r + dl);
+    const vbool in = le_u(src, (uint32_t)(kMwSlots - 1));
+    a[r] = select(in, load_vec(sh.stage, select(in, src, 0)), kNeg);
+  }
+}
+
+XD_FN void mw_full_spans(MwScalars &st) {
+  st.span_lo[0] = st.span_lo[1] = 0;
+  st.span_hi[0] = st.span_hi[1] = kMwC - 1;
+  st.w_lo = 1;
+  st.w_hi = 0;
+}
+
+// Moves the whole window so the pending range sits in its middle (through
+// the LDS stage).  Returns false when the range is wider than the window.
+XD_FN bool mw_recenter(WBand<kMwC> &bd, MwScalars &st, MwShared &sh, int w) {
+  const int width = st.hi - st.lo + 1;
+  if (width > kMwSlots - 2) return false;
+  const int dl = st.lo - (kMwSlots - width) / 2;
+  mw_move(bd.E, sh, w * kMwChunk, dl);
+  mw_move(bd.O, sh, w * kMwChunk, dl);
+  st.h += dl;
+  st.lo -= dl;
+  st.hi -= dl;
+  mw_full_spans(st);
+  mw_post_edges(bd, sh, w);
+  __syncthreads();
+  return true;
+}
+
+// Restores a single-wave tier's save into the middle of the window.
+XD_FN bool mw_restore(WBand<kMwC> &bd, MwScalars &st, MwShared &sh, int w, const Params &P,
+                      int32_t j) {
+  if (!P.save_pool || j < 0) return false;
+  const int32_t off = P.job_save[j];
+  if (off < 0) return false;
+  const int32_t *sv = P.save_pool + off;
+  const int32_t ss = kWave * sv[kSvC];
+  const int32_t shift = (kMwSlots - ss) / 2;
+  st.d = sv[kSvD];
+  st.lo = sv[kSvLo] + shift;
+  st.hi = sv[kSvHi] + shift;
+  st.h = sv[kSvH] - shift;
+  st.best = sv[kSvBest]; st.bi = sv[kSvBi]; st.bj = sv[kSvBj];
+  st.bw = sv[kSvBw]; st.thr = sv[kSvThr];
+  st.cells = (uint64_t)(uint32_t)sv[kSvCellsLo] | ((uint64_t)(uint32_t)sv[kSvCellsHi] << 32);
+  st.cells_blk = 0;
+  const vint l = lane_index();
+  const int base = w * kMwChunk;
+#pragma unroll
+  for (int r = 0; r < kMwC; ++r) {
+    const vint old = l + (base + 64 * r - shift);
+    const vbool in = le_u(old, (uint32_t)(ss - 1));
+    const vint k = select(in, old, 0);
+    bd.E[r] = select(in, load_vec(sv + kSaveHdr, k), kNeg);
+    bd.O[r] = select(in, load_vec(sv + kSaveHdr + ss, k), kNeg);
+  }
+  mw_full_spans(st);
+  return true;
+}
+
+// Whole extension of job j by the workgroup.  kJobWider when the band
+// outgrows the window.
+template <bool NARROW>
+XD_FN JobOut mw_extend(const Job &job, const Params &P, int32_t j, MwShared &sh, int w) {
+  JobOut out;
+  out.best = 0; out.bi = 0; out.bj = 0; out.status = kJobOk; out.cells = 0;
+  if (job.m + job.n == 0) return out;
+  JobView jv;
+  jv.A = make_view(P.A, P.a_words, job.a_start);
+  jv.B = make_view(P.B, P.b_words, job.b_start);
+  jv.a_start = job.a_start; jv.b_start = job.b_start;
+  jv.m = job.m; jv.n = job.n; jv.x = job.x; jv.dir = job.dir;
+
+  WBand<kMwC> bd;
+  MwScalars st;
+  if (!mw_restore(bd, st, sh, w, P, j)) {
+    // anti-diagonal 0: the origin in slot kMwSlots / 2 (register 0, lane 0 of
+    // wave kMwWaves / 2)
+    const vbool origin = lane_index() == 0;
+#pragma unroll
+    for (int r = 0; r < kMwC; ++r) {
+      bd.E[r] = (r == 0 && w == kMwWaves / 2) ? select(origin, splat(0), kNeg) : splat(kNeg);
+      bd.O[r] = splat(kNeg);
+    }
+    st.h = -kMwSlots / 2;
+    st.d = 1;
+    {
+      const int smin = (1 - jv.n > 0 ? 1 - jv.n : 0) - 1 - st.h;
+      const int smax = jv.m - 1 - st.h;
+      st.lo = (kMwSlots / 2 - 1) > smin ? (kMwSlots / 2 - 1) : smin;
+      st.hi = (kMwSlots / 2) < smax ? (kMwSlots / 2) : smax;
+    }
+    st.best = 0; st.bi = 0; st.bj = 0;
+    st.bw = P.neg_gap;
+    st.thr = P.neg_gap - jv.x;
+    st.cells_blk = 0;
+    st.cells = 0;
+    mw_full_spans(st);
+  }
+  mw_post_edges(bd, sh, w);
+  __syncthreads();
+
+  int32_t e = st.d >> 1;
+  bool odd = (st.d & 1) != 0;
+  int32_t e0 = e & ~15;
+  bool ok = true;
+  for (;;) {
+    if (!odd) {
+      if (st.lo < 1 || st.hi > kMwSlots - 2) {
+        if (!mw_recenter(bd, st, sh, w)) { ok = false; break; }
+      }
+      if (e - e0 == 16) {
+        e0 = e;
+        st.cells += st.cells_blk;
+        st.cells_blk = 0;
+        st.w_lo = 1;
+        st.w_hi = 0;
+      }
+      if (!mw_step<NARROW, 0>(bd, st, sh, w, e - e0, jv, P)) break;   // d = 2e
+    }
+    odd = false;
+    if (st.lo < 1 || st.hi > kMwSlots - 2) {
+      if (!mw_recenter(bd, st, sh, w)) { ok = false; break; }
+    }
+    if (!mw_step<NARROW, 1>(bd, st, sh, w, e - e0, jv, P)) break;     // d = 2e + 1
+    ++e;
+  }
+  if (!ok) {
+    out.status = kJobWider;
+    return out;
+  }
+  out.best = st.best;
+  out.bi = st.bi;
+  out.bj = st.bj;
+  out.cells = st.cells + st.cells_blk;
+  return out;
+}
+
+#ifndef XD_EMULATION
+// Persistent workgroups over the spill tier's queue; jobs whose band outgrows
+// the window go to `overflow` for the global-memory pass.
+template <bool NARROW>
+__global__ __launch_bounds__(kMwThreads) void k_extend_mw(const Job *__restrict__ jobs,
+                                                          TierQueue q, int32_t *head,
+                                                          JobOut *__restrict__ outs,
+                                                          unsigned long long *stats, Params P,
+                                                          int32_t *overflow,
+                                                          int32_t *overflow_count) {
+  __shared__ MwShared sh;
+  const int32_t n_init = q.counters[kInit + q.tier];
+  const int32_t n_esc = q.counters[kEsc + q.tier];
+  const int32_t count = n_init + n_esc;
+  for (;;) {
+    if (threadIdx.x == 0) sh.job = atomicAdd(head, 1);
+    __syncthreads();
+    const int32_t widx = sh.job;
+    __syncthreads();
+    if (widx >= count) break;
+    const int32_t j = tier_job(q, widx, n_init, n_esc);
+    const Job job = jobs[j];
+    const JobOut o = mw_extend<NARROW>(job, P, j, sh, (int)(threadIdx.x >> 6));
+    if (threadIdx.x == 0) {
+      if (o.status == kJobWider) {
+        overflow[atomicAdd(overflow_count, 1)] = j;
+        atomicAdd(&stats[2 * kLists + q.tier], 1ull);
+      } else {
+        outs[j] = o;
+        atomicAdd(&stats[q.tier], 1ull);
+        atomicAdd(&stats[kLists + q.tier], (unsigned long long)o.cells);
+      }
+    }
+    __syncthreads();
+  }
+}
+#endif
+
+}  // namespace xd

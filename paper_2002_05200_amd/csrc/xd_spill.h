@@ -18,16 +18,12 @@
 namespace xd {
 
 constexpr int kSpillThreads = 256;
-// Two passes: many workgroups whose anti-diagonal buffers hold up to
-// kSpillCap cells, then a few with room for kHugeCap cells for the jobs whose
-// band outgrew the first (they start over there).
-constexpr int kSpillSlots = 512;
-constexpr int64_t kSpillCap = 16384;
+// Jobs whose band outgrows the multi-wave tier's window start over here:
+// kHugeSlots workgroups with room for kHugeCap cells per anti-diagonal.
 constexpr int kHugeSlots = 8;
 constexpr int64_t kHugeCap = (1 << 20) + 4;
 
 struct SpillScratch {
-  int32_t *buf = nullptr;    // kSpillSlots * 3 * kSpillCap
   int32_t *huge = nullptr;   // kHugeSlots * 3 * kHugeCap
 };
 
@@ -160,12 +156,6 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(const Job *__restrict__
 }
 
 inline xd_status spill_alloc(SpillScratch *sp) {
-  if (!sp->buf) {
-    void *p = nullptr;
-    if (hipMalloc(&p, sizeof(int32_t) * 3 * kSpillCap * kSpillSlots) != hipSuccess)
-      return XD_ENOMEM;
-    sp->buf = (int32_t *)p;
-  }
   if (!sp->huge) {
     void *p = nullptr;
     if (hipMalloc(&p, sizeof(int32_t) * 3 * kHugeCap * kHugeSlots) != hipSuccess)
@@ -175,37 +165,26 @@ inline xd_status spill_alloc(SpillScratch *sp) {
   return XD_OK;
 }
 
-// Both passes over the spill tier's queue; `huge_list` has room for every job.
+// The global-memory pass over `list` (jobs the multi-wave tier could not hold).
 inline xd_status spill_launch(SpillScratch *sp, hipStream_t s, const Job *jobs,
-                              const TierQueue &q, int32_t *head, int32_t *huge_head,
-                              int32_t *huge_list, int32_t *huge_count, JobOut *outs,
+                              const TierQueue &q, int32_t *head, const int32_t *list,
+                              const int32_t *list_count, JobOut *outs,
                               unsigned long long *stats, const Params &P) {
-  if (!sp->buf || !sp->huge) return XD_ENOMEM;
-  SpillSource a;
-  a.q = q;
-  a.list = nullptr;
-  a.list_count = nullptr;
-  a.overflow = huge_list;
-  a.overflow_count = huge_count;
-  a.cap = kSpillCap;
-  hipLaunchKernelGGL(k_spill, dim3(kSpillSlots), dim3(kSpillThreads), 0, s, jobs, a, head, outs,
-                     stats, P, sp->buf);
-  if (hipGetLastError() != hipSuccess) return XD_EDEVICE;
-  SpillSource b = a;
-  b.list = huge_list;
-  b.list_count = huge_count;
+  if (!sp->huge) return XD_ENOMEM;
+  SpillSource b;
+  b.q = q;
+  b.list = list;
+  b.list_count = list_count;
   b.overflow = nullptr;
   b.overflow_count = nullptr;
   b.cap = kHugeCap;
-  hipLaunchKernelGGL(k_spill, dim3(kHugeSlots), dim3(kSpillThreads), 0, s, jobs, b, huge_head,
-                     outs, stats, P, sp->huge);
+  hipLaunchKernelGGL(k_spill, dim3(kHugeSlots), dim3(kSpillThreads), 0, s, jobs, b, head, outs,
+                     stats, P, sp->huge);
   return hipGetLastError() == hipSuccess ? XD_OK : XD_EDEVICE;
 }
 
 inline void spill_free(SpillScratch *sp) {
-  if (sp->buf) (void)hipFree(sp->buf);
   if (sp->huge) (void)hipFree(sp->huge);
-  sp->buf = nullptr;
   sp->huge = nullptr;
 }
 

@@ -336,3 +336,16 @@ def test_bands_wider_than_the_first_spill_pass(ctx, xd):
     assert st["escalated"][6] == 2, st
     assert st["jobs"][6] == 2, st
     assert_same(got, oracle_of(bt), "second spill pass")
+
+
+def test_multi_wave_tier_from_the_start(ctx, xd):
+    """Every job straight to the workgroup-per-job tier (16 wavefronts, 8,192
+    slots): narrow and wide bands, recentring across wavefronts."""
+    from paper_2002_05200_amd import synth
+    bt = synth.concat([synth.random_cases(seed=700, n=60, len_lo=17, len_hi=900,
+                                          x_choices=(0, 1, 5, 20, 100)),
+                       synth.make_batch("uneven", n=6, start=11, stride=20011)], name="mw")
+    got = run(ctx, xd, bt, min_tier=6)
+    st = ctx.stats()
+    assert st["jobs"][6] == 2 * bt.n, st
+    assert_same(got, oracle_of(bt), "multi-wave tier")
