@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--serving-batch", type=int, default=2048)
     ap.add_argument("--serving-graph", type=int, default=1)
+    ap.add_argument("--multi-wave", type=int, default=None,
+                    help="force the multi_wave launch option (default: tuned table or 0)")
     ap.add_argument("--tuned", action="store_true",
                     help="launch options from the autotuner's table for this workload class")
     ap.add_argument("--graph", action="store_true",
@@ -190,6 +192,8 @@ def main():
         tuned.pop("sched", None)
         print(f"[bench] tuned options for {tune.batch_class(bt)}: {tuned}", file=sys.stderr,
               flush=True)
+    if args.multi_wave is not None:
+        tuned["multi_wave"] = args.multi_wave
     t0 = time.time()
     db = xdrop.DeviceBatch(bt, "cuda:0")
     del bt.a, bt.b

@@ -355,7 +355,7 @@ xd_status ensure_capacity(xd_ctx *c, int64_t n_pairs) {
 
 template <int C, bool NARROW>
 hipError_t launch_tier(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_cu,
-                       int64_t max_jobs, int tier, const Params &P) {
+                       int64_t max_jobs, int tier, const Params &P, bool multi_wave) {
   const int64_t stride = 2 * c->cap_pairs;
   TierQueue q;
   q.order = c->order;
@@ -364,6 +364,17 @@ hipError_t launch_tier(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_
   q.next_esc = c->esc + (tier + 1) * stride;
   q.tier = tier;
   int32_t *head = persistent ? c->counters + kHead + tier : nullptr;
+  if constexpr (C >= 8) {
+    if (multi_wave) {   // four wavefronts per job, C / 4 registers each
+      constexpr int NW = 4;
+      int64_t groups = persistent ? ((int64_t)c->num_cu * waves_per_cu + NW - 1) / NW : max_jobs;
+      if (groups < 1) groups = 1;
+      hipLaunchKernelGGL((k_extend_mw<NW, C / NW, NARROW>), dim3((unsigned)groups), dim3(64 * NW),
+                         0, s, c->jobs, q, head, c->outs, c->stats, P, q.next_esc,
+                         c->counters + kEsc + tier + 1);
+      return hipGetLastError();
+    }
+  }
   int64_t blocks;
   if (persistent) {
     blocks = ((int64_t)c->num_cu * waves_per_cu + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -378,23 +389,23 @@ hipError_t launch_tier(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_
 
 template <bool NARROW>
 hipError_t launch_tiers(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_cu,
-                        int64_t nj, const Params &P, bool prof) {
+                        int64_t nj, const Params &P, bool prof, bool mw) {
   // waves per CU suited to each tier's register footprint
   const int wpc[kTiers] = {32, 32, 24, 16, 8, 4};
   auto w = [&](int t) { return waves_per_cu > 0 ? waves_per_cu : wpc[t]; };
   hipError_t e;
   auto mark = [&](int i) { return prof ? hipEventRecord(c->ev[i], s) : hipSuccess; };
-  if ((e = launch_tier<1, NARROW>(c, s, persistent, w(0), nj, 0, P)) != hipSuccess) return e;
+  if ((e = launch_tier<1, NARROW>(c, s, persistent, w(0), nj, 0, P, mw)) != hipSuccess) return e;
   if ((e = mark(2)) != hipSuccess) return e;
-  if ((e = launch_tier<2, NARROW>(c, s, persistent, w(1), nj, 1, P)) != hipSuccess) return e;
+  if ((e = launch_tier<2, NARROW>(c, s, persistent, w(1), nj, 1, P, mw)) != hipSuccess) return e;
   if ((e = mark(3)) != hipSuccess) return e;
-  if ((e = launch_tier<4, NARROW>(c, s, persistent, w(2), nj, 2, P)) != hipSuccess) return e;
+  if ((e = launch_tier<4, NARROW>(c, s, persistent, w(2), nj, 2, P, mw)) != hipSuccess) return e;
   if ((e = mark(4)) != hipSuccess) return e;
-  if ((e = launch_tier<8, NARROW>(c, s, persistent, w(3), nj, 3, P)) != hipSuccess) return e;
+  if ((e = launch_tier<8, NARROW>(c, s, persistent, w(3), nj, 3, P, mw)) != hipSuccess) return e;
   if ((e = mark(5)) != hipSuccess) return e;
-  if ((e = launch_tier<16, NARROW>(c, s, persistent, w(4), nj, 4, P)) != hipSuccess) return e;
+  if ((e = launch_tier<16, NARROW>(c, s, persistent, w(4), nj, 4, P, mw)) != hipSuccess) return e;
   if ((e = mark(6)) != hipSuccess) return e;
-  if ((e = launch_tier<32, NARROW>(c, s, persistent, w(5), nj, 5, P)) != hipSuccess) return e;
+  if ((e = launch_tier<32, NARROW>(c, s, persistent, w(5), nj, 5, P, mw)) != hipSuccess) return e;
   return mark(7);
 }
 
@@ -459,8 +470,9 @@ xd_status enqueue(xd_ctx *c, hipStream_t s, const Launch &L, bool prof) {
                      bin_off, bin_cursor, c->order);
   XD_HIP(hipGetLastError());
   if (prof) XD_HIP(hipEventRecord(c->ev[1], s));
-  hipError_t e = narrow ? launch_tiers<true>(c, s, persistent, o.waves_per_cu, nj, P, prof)
-                        : launch_tiers<false>(c, s, persistent, o.waves_per_cu, nj, P, prof);
+  const bool mw = o.multi_wave != 0;
+  hipError_t e = narrow ? launch_tiers<true>(c, s, persistent, o.waves_per_cu, nj, P, prof, mw)
+                        : launch_tiers<false>(c, s, persistent, o.waves_per_cu, nj, P, prof, mw);
   if (e != hipSuccess) return fail(XD_EDEVICE, std::string("k_extend: ") + hipGetErrorString(e));
   {   // bands wider than one wavefront: a workgroup per job, then global memory
     TierQueue q;
@@ -471,11 +483,11 @@ xd_status enqueue(xd_ctx *c, hipStream_t s, const Launch &L, bool prof) {
     q.tier = kTiers;
     int32_t *huge_list = c->esc + kLists * stride;
     if (narrow)
-      hipLaunchKernelGGL(k_extend_mw<true>, dim3((unsigned)c->num_cu), dim3(kMwThreads), 0, s,
+      hipLaunchKernelGGL((k_extend_mw<16, 8, true>), dim3((unsigned)c->num_cu), dim3(64 * 16), 0, s,
                          c->jobs, q, c->counters + kHead + kTiers, c->outs, c->stats, P,
                          huge_list, c->counters + kHugeCount);
     else
-      hipLaunchKernelGGL(k_extend_mw<false>, dim3((unsigned)c->num_cu), dim3(kMwThreads), 0, s,
+      hipLaunchKernelGGL((k_extend_mw<16, 8, false>), dim3((unsigned)c->num_cu), dim3(64 * 16), 0, s,
                          c->jobs, q, c->counters + kHead + kTiers, c->outs, c->stats, P,
                          huge_list, c->counters + kHugeCount);
     XD_HIP(hipGetLastError());
@@ -591,6 +603,8 @@ xd_status xdrop_extend(xd_ctx *c, const uint32_t *d_a, uint64_t a_words, const u
   if (o.impl < 0 || o.impl > 1) return fail(XD_EINVAL, "xdrop_extend: impl out of range");
   if (o.long_job < 0 || o.long_tier_bias < 0 || o.long_tier_bias >= kTiers)
     return fail(XD_EINVAL, "xdrop_extend: long_job / long_tier_bias out of range");
+  if (o.multi_wave < 0 || o.multi_wave > 1)
+    return fail(XD_EINVAL, "xdrop_extend: multi_wave out of range");
   if (o.waves_per_cu < 0 || o.waves_per_cu > 64)
     return fail(XD_EINVAL, "xdrop_extend: waves_per_cu out of range");
   const bool graph = o.graph != 0;

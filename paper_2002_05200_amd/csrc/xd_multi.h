@@ -1,9 +1,9 @@
 // xd_multi.h -- X-drop extension of one job by a whole workgroup, for bands
 // wider than one wavefront's registers hold (more than 2,046 cells).
 //
-// kMwWaves wavefronts each own a chunk of kMwC registers (64 kMwC slots, the
+// NW wavefronts each own a chunk of C registers (64 C slots, the
 // slots interleaved across the chunk's registers as in xd_wide.h), so the
-// window is kMwSlots = 64 kMwC kMwWaves diagonal slots.  Per anti-diagonal
+// window is (64 * C * NW) = 64 C NW diagonal slots.  Per anti-diagonal
 // every wave updates the part of the computed range that falls in its chunk
 // with the single-wave step, clips its edge registers, and posts to LDS
 //   * its chunk's first and last slot values (the neighbours the adjacent
@@ -25,17 +25,24 @@
 
 namespace xd {
 
-constexpr int kMwWaves = 16;
-constexpr int kMwC = 8;
-constexpr int kMwChunk = 64 * kMwC;
-constexpr int kMwSlots = kMwChunk * kMwWaves;   // 8192
-constexpr int kMwThreads = 64 * kMwWaves;
+// Shapes: NW wavefronts per job, C registers per wavefront.  The widest
+// (16 x 8, 8,192 slots) takes bands no single wavefront holds; narrower ones
+// (4 x 4, 4 x 8) shorten each anti-diagonal of very long jobs by spreading a
+// band one wavefront could hold over several.
+template <int NW, int C>
+struct MwShape {
+  static constexpr int kChunk = 64 * C;
+  static constexpr int kSlots = kChunk * NW;
+  static constexpr int kThreads = 64 * NW;
+};
 
+template <int NW, int C>
 struct MwShared {
   int32_t job;
-  int32_t edge[2][kMwWaves][2];   // by parity: chunk's first and last slot value
-  int32_t red[2][kMwWaves][4];    // by parity: first, last, best value, its slot
-  int32_t stage[kMwSlots];        // window moves: one anti-diagonal by slot
+  int32_t edge[2][NW][2];   // by parity: chunk's first and last slot value
+  int32_t red[2][NW][4];    // by parity: first, last, best value, its slot
+  int32_t stage[64 * C * NW];   // window moves: one anti-diagonal by slot
+  int32_t save_off;             // escalation save slot of the current job
 };
 
 // Block-wide scalar state (every wave keeps an identical copy).
@@ -49,14 +56,14 @@ struct MwScalars {
 };
 
 // Score words of this wave's registers [r0, r1] (chunk starting at slot base).
-template <bool NARROW>
-XD_FN void mw_build(WBand<kMwC> &bd, MwScalars &st, int32_t base, int32_t e0, int32_t r0,
+template <int C, bool NARROW>
+XD_FN void mw_build(WBand<C> &bd, MwScalars &st, int32_t base, int32_t e0, int32_t r0,
                     int32_t r1, const JobView &jv, const Params &P) {
   if (r0 < 0) r0 = 0;
-  if (r1 > kMwC - 1) r1 = kMwC - 1;
+  if (r1 > C - 1) r1 = C - 1;
   const vint l = lane_index();
 #pragma unroll
-  for (int r = 0; r < kMwC; ++r) {
+  for (int r = 0; r < C; ++r) {
     if (r < r0 || r > r1) continue;
     const vint s = l + (base + 64 * r);
     const vint i0 = s + (st.h + e0);
@@ -86,28 +93,28 @@ XD_FN void mw_build(WBand<kMwC> &bd, MwScalars &st, int32_t base, int32_t e0, in
 }
 
 // Posts both parities' chunk-edge values (after the band was (re)loaded).
-XD_FN void mw_post_edges(const WBand<kMwC> &bd, MwShared &sh, int w) {
+template <int NW, int C>
+XD_FN void mw_post_edges(const WBand<C> &bd, MwShared<NW, C> &sh, int w) {
   if (lane_id() == 0) {
     sh.edge[0][w][0] = readlane(bd.E[0], 0);
-    sh.edge[0][w][1] = readlane(bd.E[kMwC - 1], 63);
+    sh.edge[0][w][1] = readlane(bd.E[C - 1], 63);
     sh.edge[1][w][0] = readlane(bd.O[0], 0);
-    sh.edge[1][w][1] = readlane(bd.O[kMwC - 1], 63);
+    sh.edge[1][w][1] = readlane(bd.O[C - 1], 63);
   }
 }
 
 // Anti-diagonal st.d (parity PAR).  Returns false once the extension ended.
-template <bool NARROW, int PAR>
-XD_FN bool mw_step(WBand<kMwC> &bd, MwScalars &st, MwShared &sh, int w, int q,
+template <int NW, int C, bool NARROW, int PAR>
+XD_FN bool mw_step(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w, int q,
                    const JobView &jv, const Params &P) {
-  constexpr int C = kMwC;
   vint *cur = PAR ? bd.O : bd.E;
   const vint *prv = PAR ? bd.E : bd.O;
   const vint *sw = PAR ? bd.SO : bd.SE;
   const int pos = 2 * q;
-  const int base = w * kMwChunk;
+  const int base = w * (64 * C);
   // this chunk's part of the range
   const int cl = st.lo - base > 0 ? st.lo - base : 0;
-  const int ch = st.hi - base < kMwChunk - 1 ? st.hi - base : kMwChunk - 1;
+  const int ch = st.hi - base < (64 * C) - 1 ? st.hi - base : (64 * C) - 1;
   const bool active = cl <= ch;
   const int rlo = active ? cl >> 6 : 1, rhi = active ? ch >> 6 : 0;
   const int plo = st.span_lo[PAR], phi = st.span_hi[PAR];
@@ -119,10 +126,10 @@ XD_FN bool mw_step(WBand<kMwC> &bd, MwScalars &st, MwShared &sh, int w, int q,
   int first = 0x7fffffff, last = -1, bestv = kNeg, bests = 0x7fffffff;
   if (active) {
     if (rlo < st.w_lo || rhi > st.w_hi)
-      mw_build<NARROW>(bd, st, base, (st.d >> 1) - q, rlo - 1, rhi + 1, jv, P);
+      mw_build<C, NARROW>(bd, st, base, (st.d >> 1) - q, rlo - 1, rhi + 1, jv, P);
     // neighbours in the adjacent chunks, posted on the previous anti-diagonal
     const int32_t nb_below = w > 0 ? sh.edge[1 - PAR][w - 1][1] : kNeg;
-    const int32_t nb_above = w < kMwWaves - 1 ? sh.edge[1 - PAR][w + 1][0] : kNeg;
+    const int32_t nb_above = w < NW - 1 ? sh.edge[1 - PAR][w + 1][0] : kNeg;
     const int32_t thr = st.thr, bw = st.bw;
     uint64_t imp = 0;
     switch (rlo) {
@@ -134,7 +141,8 @@ XD_FN bool mw_step(WBand<kMwC> &bd, MwScalars &st, MwShared &sh, int w, int q,
     }                                                                                      \
     [[fallthrough]];
       XD_MW_CASE(0) XD_MW_CASE(1) XD_MW_CASE(2) XD_MW_CASE(3) XD_MW_CASE(4) XD_MW_CASE(5)
-      XD_MW_CASE(6) XD_MW_CASE(7)
+      XD_MW_CASE(6) XD_MW_CASE(7) XD_MW_CASE(8) XD_MW_CASE(9) XD_MW_CASE(10) XD_MW_CASE(11)
+      XD_MW_CASE(12) XD_MW_CASE(13) XD_MW_CASE(14) XD_MW_CASE(15)
 #undef XD_MW_CASE
       default:
         break;
@@ -202,7 +210,7 @@ XD_FN bool mw_step(WBand<kMwC> &bd, MwScalars &st, MwShared &sh, int w, int q,
   __syncthreads();
   int gfirst = 0x7fffffff, glast = -1, gbest = kNeg, gslot = 0x7fffffff;
 #pragma unroll
-  for (int v = 0; v < kMwWaves; ++v) {
+  for (int v = 0; v < NW; ++v) {
     const int f = sh.red[PAR][v][0], l = sh.red[PAR][v][1], b = sh.red[PAR][v][2];
     gfirst = f < gfirst ? f : gfirst;
     glast = l > glast ? l : glast;
@@ -242,53 +250,58 @@ XD_FN bool mw_step(WBand<kMwC> &bd, MwScalars &st, MwShared &sh, int w, int q,
 
 // Window move through the LDS stage, one anti-diagonal at a time: new slot
 // s <- old slot s + dl (-inf from outside the window).
-XD_FN void mw_move(vint *a, MwShared &sh, int base, int dl) {
+template <int NW, int C>
+XD_FN void mw_move(vint *a, MwShared<NW, C> &sh, int base, int dl) {
   const vint l = lane_index();
   __syncthreads();                       // the stage is free
 #pragma unroll
-  for (int r = 0; r < kMwC; ++r) store_vec(sh.stage + base + 64 * r, l, a[r]);
+  for (int r = 0; r < C; ++r) store_vec(sh.stage + base + 64 * r, l, a[r]);
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kMwC; ++r) {
+  for (int r = 0; r < C; ++r) {
     const vint src = l + (base + 64 * r + dl);
-    const vbool in = le_u(src, (uint32_t)(kMwSlots - 1));
+    const vbool in = le_u(src, (uint32_t)((64 * C * NW) - 1));
     a[r] = select(in, load_vec(sh.stage, select(in, src, 0)), kNeg);
   }
 }
 
+template <int C>
 XD_FN void mw_full_spans(MwScalars &st) {
   st.span_lo[0] = st.span_lo[1] = 0;
-  st.span_hi[0] = st.span_hi[1] = kMwC - 1;
+  st.span_hi[0] = st.span_hi[1] = C - 1;
   st.w_lo = 1;
   st.w_hi = 0;
 }
 
 // Moves the whole window so the pending range sits in its middle (through
 // the LDS stage).  Returns false when the range is wider than the window.
-XD_FN bool mw_recenter(WBand<kMwC> &bd, MwScalars &st, MwShared &sh, int w) {
+template <int NW, int C>
+XD_FN bool mw_recenter(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w) {
   const int width = st.hi - st.lo + 1;
-  if (width > kMwSlots - 2) return false;
-  const int dl = st.lo - (kMwSlots - width) / 2;
-  mw_move(bd.E, sh, w * kMwChunk, dl);
-  mw_move(bd.O, sh, w * kMwChunk, dl);
+  if (width > (64 * C * NW) - 2) return false;
+  const int dl = st.lo - ((64 * C * NW) - width) / 2;
+  mw_move<NW, C>(bd.E, sh, w * (64 * C), dl);
+  mw_move<NW, C>(bd.O, sh, w * (64 * C), dl);
   st.h += dl;
   st.lo -= dl;
   st.hi -= dl;
-  mw_full_spans(st);
-  mw_post_edges(bd, sh, w);
+  mw_full_spans<C>(st);
+  mw_post_edges<NW, C>(bd, sh, w);
   __syncthreads();
   return true;
 }
 
 // Restores a single-wave tier's save into the middle of the window.
-XD_FN bool mw_restore(WBand<kMwC> &bd, MwScalars &st, MwShared &sh, int w, const Params &P,
+template <int NW, int C>
+XD_FN bool mw_restore(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w, const Params &P,
                       int32_t j) {
   if (!P.save_pool || j < 0) return false;
   const int32_t off = P.job_save[j];
   if (off < 0) return false;
   const int32_t *sv = P.save_pool + off;
   const int32_t ss = kWave * sv[kSvC];
-  const int32_t shift = (kMwSlots - ss) / 2;
+  if (ss >= 64 * C * NW) return false;
+  const int32_t shift = ((64 * C * NW) - ss) / 2;
   st.d = sv[kSvD];
   st.lo = sv[kSvLo] + shift;
   st.hi = sv[kSvHi] + shift;
@@ -298,23 +311,52 @@ XD_FN bool mw_restore(WBand<kMwC> &bd, MwScalars &st, MwShared &sh, int w, const
   st.cells = (uint64_t)(uint32_t)sv[kSvCellsLo] | ((uint64_t)(uint32_t)sv[kSvCellsHi] << 32);
   st.cells_blk = 0;
   const vint l = lane_index();
-  const int base = w * kMwChunk;
+  const int base = w * (64 * C);
 #pragma unroll
-  for (int r = 0; r < kMwC; ++r) {
+  for (int r = 0; r < C; ++r) {
     const vint old = l + (base + 64 * r - shift);
     const vbool in = le_u(old, (uint32_t)(ss - 1));
     const vint k = select(in, old, 0);
     bd.E[r] = select(in, load_vec(sv + kSaveHdr, k), kNeg);
     bd.O[r] = select(in, load_vec(sv + kSaveHdr + ss, k), kNeg);
   }
-  mw_full_spans(st);
+  mw_full_spans<C>(st);
   return true;
+}
+
+// Stores the workgroup's state in the job's save slot (slot order, C field =
+// slots / 64) for the next, wider tier; nothing when the window is wider than
+// a save slot holds or the pool is full.
+template <int NW, int C>
+XD_FN void mw_save(const WBand<C> &bd, const MwScalars &st, MwShared<NW, C> &sh, int w,
+                   const Params &P, int32_t j) {
+  constexpr int S = 64 * C * NW;
+  if (w == 0) {
+    int32_t *sv = save_reserve(P, j, S);
+    if (lane_id() == 0) sh.save_off = sv ? (int32_t)(sv - P.save_pool) : -1;
+    if (sv)
+      save_scalars(sv, st.d, st.lo, st.hi, st.h, st.best, st.bi, st.bj, st.bw, st.thr, C * NW,
+                   st.cells + st.cells_blk);
+  }
+  __syncthreads();
+  const int32_t off = sh.save_off;
+  if (off >= 0) {
+    int32_t *sv = P.save_pool + off;
+    const vint l = lane_index();
+#pragma unroll
+    for (int r = 0; r < C; ++r) {
+      store_vec(sv + kSaveHdr, l + (w * 64 * C + 64 * r), bd.E[r]);
+      store_vec(sv + kSaveHdr + S, l + (w * 64 * C + 64 * r), bd.O[r]);
+    }
+  }
+  __syncthreads();
+  if (w == 0 && off >= 0) save_publish(P, j, P.save_pool + off);
 }
 
 // Whole extension of job j by the workgroup.  kJobWider when the band
 // outgrows the window.
-template <bool NARROW>
-XD_FN JobOut mw_extend(const Job &job, const Params &P, int32_t j, MwShared &sh, int w) {
+template <int NW, int C, bool NARROW>
+XD_FN JobOut mw_extend(const Job &job, const Params &P, int32_t j, MwShared<NW, C> &sh, int w) {
   JobOut out;
   out.best = 0; out.bi = 0; out.bj = 0; out.status = kJobOk; out.cells = 0;
   if (job.m + job.n == 0) return out;
@@ -324,33 +366,33 @@ XD_FN JobOut mw_extend(const Job &job, const Params &P, int32_t j, MwShared &sh,
   jv.a_start = job.a_start; jv.b_start = job.b_start;
   jv.m = job.m; jv.n = job.n; jv.x = job.x; jv.dir = job.dir;
 
-  WBand<kMwC> bd;
+  WBand<C> bd;
   MwScalars st;
-  if (!mw_restore(bd, st, sh, w, P, j)) {
-    // anti-diagonal 0: the origin in slot kMwSlots / 2 (register 0, lane 0 of
-    // wave kMwWaves / 2)
+  if (!mw_restore<NW, C>(bd, st, sh, w, P, j)) {
+    // anti-diagonal 0: the origin in slot (64 * C * NW) / 2 (register 0, lane 0 of
+    // wave NW / 2)
     const vbool origin = lane_index() == 0;
 #pragma unroll
-    for (int r = 0; r < kMwC; ++r) {
-      bd.E[r] = (r == 0 && w == kMwWaves / 2) ? select(origin, splat(0), kNeg) : splat(kNeg);
+    for (int r = 0; r < C; ++r) {
+      bd.E[r] = (r == 0 && w == NW / 2) ? select(origin, splat(0), kNeg) : splat(kNeg);
       bd.O[r] = splat(kNeg);
     }
-    st.h = -kMwSlots / 2;
+    st.h = -(64 * C * NW) / 2;
     st.d = 1;
     {
       const int smin = (1 - jv.n > 0 ? 1 - jv.n : 0) - 1 - st.h;
       const int smax = jv.m - 1 - st.h;
-      st.lo = (kMwSlots / 2 - 1) > smin ? (kMwSlots / 2 - 1) : smin;
-      st.hi = (kMwSlots / 2) < smax ? (kMwSlots / 2) : smax;
+      st.lo = ((64 * C * NW) / 2 - 1) > smin ? ((64 * C * NW) / 2 - 1) : smin;
+      st.hi = ((64 * C * NW) / 2) < smax ? ((64 * C * NW) / 2) : smax;
     }
     st.best = 0; st.bi = 0; st.bj = 0;
     st.bw = P.neg_gap;
     st.thr = P.neg_gap - jv.x;
     st.cells_blk = 0;
     st.cells = 0;
-    mw_full_spans(st);
+    mw_full_spans<C>(st);
   }
-  mw_post_edges(bd, sh, w);
+  mw_post_edges<NW, C>(bd, sh, w);
   __syncthreads();
 
   int32_t e = st.d >> 1;
@@ -359,8 +401,8 @@ XD_FN JobOut mw_extend(const Job &job, const Params &P, int32_t j, MwShared &sh,
   bool ok = true;
   for (;;) {
     if (!odd) {
-      if (st.lo < 1 || st.hi > kMwSlots - 2) {
-        if (!mw_recenter(bd, st, sh, w)) { ok = false; break; }
+      if (st.lo < 1 || st.hi > (64 * C * NW) - 2) {
+        if (!mw_recenter<NW, C>(bd, st, sh, w)) { ok = false; break; }
       }
       if (e - e0 == 16) {
         e0 = e;
@@ -369,16 +411,17 @@ XD_FN JobOut mw_extend(const Job &job, const Params &P, int32_t j, MwShared &sh,
         st.w_lo = 1;
         st.w_hi = 0;
       }
-      if (!mw_step<NARROW, 0>(bd, st, sh, w, e - e0, jv, P)) break;   // d = 2e
+      if (!mw_step<NW, C, NARROW, 0>(bd, st, sh, w, e - e0, jv, P)) break;   // d = 2e
     }
     odd = false;
-    if (st.lo < 1 || st.hi > kMwSlots - 2) {
-      if (!mw_recenter(bd, st, sh, w)) { ok = false; break; }
+    if (st.lo < 1 || st.hi > (64 * C * NW) - 2) {
+      if (!mw_recenter<NW, C>(bd, st, sh, w)) { ok = false; break; }
     }
-    if (!mw_step<NARROW, 1>(bd, st, sh, w, e - e0, jv, P)) break;     // d = 2e + 1
+    if (!mw_step<NW, C, NARROW, 1>(bd, st, sh, w, e - e0, jv, P)) break;     // d = 2e + 1
     ++e;
   }
   if (!ok) {
+    mw_save<NW, C>(bd, st, sh, w, P, j);
     out.status = kJobWider;
     return out;
   }
@@ -390,28 +433,32 @@ XD_FN JobOut mw_extend(const Job &job, const Params &P, int32_t j, MwShared &sh,
 }
 
 #ifndef XD_EMULATION
-// Persistent workgroups over the spill tier's queue; jobs whose band outgrows
-// the window go to `overflow` for the global-memory pass.
-template <bool NARROW>
-__global__ __launch_bounds__(kMwThreads) void k_extend_mw(const Job *__restrict__ jobs,
-                                                          TierQueue q, int32_t *head,
-                                                          JobOut *__restrict__ outs,
-                                                          unsigned long long *stats, Params P,
-                                                          int32_t *overflow,
-                                                          int32_t *overflow_count) {
-  __shared__ MwShared sh;
+// One job per workgroup.  Plain (head == nullptr): workgroup b takes work item
+// b.  Persistent: workgroups pop work items.  A job whose band outgrows the
+// window is appended to `overflow` (the next tier's escalation list, with its
+// state saved, or the global-memory pass's list).
+template <int NW, int C, bool NARROW>
+__global__ __launch_bounds__(64 * NW) void k_extend_mw(const Job *__restrict__ jobs, TierQueue q,
+                                                       int32_t *head, JobOut *__restrict__ outs,
+                                                       unsigned long long *stats, Params P,
+                                                       int32_t *overflow,
+                                                       int32_t *overflow_count) {
+  __shared__ MwShared<NW, C> sh;
   const int32_t n_init = q.counters[kInit + q.tier];
   const int32_t n_esc = q.counters[kEsc + q.tier];
   const int32_t count = n_init + n_esc;
+  int32_t widx = (int32_t)blockIdx.x;
   for (;;) {
-    if (threadIdx.x == 0) sh.job = atomicAdd(head, 1);
-    __syncthreads();
-    const int32_t widx = sh.job;
-    __syncthreads();
+    if (head != nullptr) {
+      if (threadIdx.x == 0) sh.job = atomicAdd(head, 1);
+      __syncthreads();
+      widx = sh.job;
+      __syncthreads();
+    }
     if (widx >= count) break;
     const int32_t j = tier_job(q, widx, n_init, n_esc);
     const Job job = jobs[j];
-    const JobOut o = mw_extend<NARROW>(job, P, j, sh, (int)(threadIdx.x >> 6));
+    const JobOut o = mw_extend<NW, C, NARROW>(job, P, j, sh, (int)(threadIdx.x >> 6));
     if (threadIdx.x == 0) {
       if (o.status == kJobWider) {
         overflow[atomicAdd(overflow_count, 1)] = j;
@@ -423,6 +470,7 @@ __global__ __launch_bounds__(kMwThreads) void k_extend_mw(const Job *__restrict_
       }
     }
     __syncthreads();
+    if (head == nullptr) break;
   }
 }
 #endif

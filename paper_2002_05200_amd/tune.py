@@ -5,7 +5,8 @@ The kernels' results never depend on these options, only their speed does:
 - long_job / long_tier_bias: the short/long split (jobs with m + n at least
   long_job start long_tier_bias lane-width tiers wider, so bands that will
   grow wide skip the narrow windows they would outgrow);
-- sort_jobs: longest-estimated-job-first order on or off.
+- sort_jobs: longest-estimated-job-first order on or off;
+- multi_wave: four wavefronts per job in the widest single-job tiers.
 
 `tune` times candidates on a sample batch already resident on the device
 (coordinate descent from the defaults, median of a few repetitions, timed
@@ -33,8 +34,10 @@ CANDIDATES: Dict[str, List[int]] = {
     "long_job": [2000, 10000, 40000],
     "waves_per_cu": [0, 8, 16, 24],
     "sort_jobs": [1, 0],
+    "multi_wave": [1],
 }
-DEFAULTS = {"sched": 0, "waves_per_cu": 0, "sort_jobs": 1, "long_job": 0, "long_tier_bias": 0}
+DEFAULTS = {"sched": 0, "waves_per_cu": 0, "sort_jobs": 1, "long_job": 0, "long_tier_bias": 0,
+            "multi_wave": 0}
 
 
 def workload_class(x: np.ndarray, a_len: np.ndarray, b_len: np.ndarray) -> str:

@@ -42,7 +42,7 @@ class Opts(ctypes.Structure):
                 ("waves_per_cu", ctypes.c_int32), ("sort_jobs", ctypes.c_int32),
                 ("long_job", ctypes.c_int32), ("long_tier_bias", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("impl", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("multi_wave", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -183,11 +183,11 @@ class DeviceBatch:
 
 def make_opts(sched: int = SCHED_AUTO, min_tier: int = 0, waves_per_cu: int = 0,
               sort_jobs: int = 1, long_job: int = 0, long_tier_bias: int = 0,
-              profile: int = 0, impl: int = 0, graph: int = 0) -> Opts:
+              profile: int = 0, impl: int = 0, graph: int = 0, multi_wave: int = 0) -> Opts:
     o = Opts()
     o.sched, o.min_tier, o.waves_per_cu = sched, min_tier, waves_per_cu
     o.sort_jobs, o.long_job, o.long_tier_bias = sort_jobs, long_job, long_tier_bias
-    o.profile, o.impl, o.graph = profile, impl, graph
+    o.profile, o.impl, o.graph, o.multi_wave = profile, impl, graph, multi_wave
     return o
 
 

@@ -26,5 +26,6 @@ def test_shipped_table_is_well_formed():
     t = tune.load_table()
     for cls, e in t.items():
         assert cls.startswith("x<=")
-        assert set(e["opts"]) <= {"sched", "waves_per_cu", "sort_jobs", "long_job", "long_tier_bias"}
+        assert set(e["opts"]) <= {"sched", "waves_per_cu", "sort_jobs", "long_job", "long_tier_bias",
+                                  "multi_wave"}
         assert e["ms"] <= e["default_ms"]
