@@ -134,7 +134,8 @@ XD_FN Win make_win(const AsmView &v, vint off) {
 
 // Cell update and prune of one anti-diagonal (field P of the score word),
 // then its thresholds and survivor ends.  TAG names the step's exits:
-// .Ld (nothing survived), .Li (best improved, returns to .Lr).
+// .Ld (nothing survived), .Li (best improved; returns to .Lr, or past the drift
+// to .Lq).
 #define XD_CORE(TAG, DIAG, CUR, PRV, SW, SHIFT, P)                                \
   "v_addc_co_u32_e64 %[cnt], vcc, 0, %[cnt], %[range]\n\t"                        \
   "v_mov_b32_dpp %[t], %[" PRV "] " SHIFT " row_mask:0xf bank_mask:0xf\n\t"        \
@@ -148,7 +149,8 @@ XD_FN Win make_win(const AsmView &v, vint off) {
   "s_cbranch_vccnz .Li" TAG "_%=\n"                                                \
   ".Lr" TAG "_%=:\n\t"                                                             \
   "s_add_i32 %[thr], %[thr], %[ng]\n\t"                                           \
-  "v_add_u32 %[bw], %[ng], %[bw]\n\t"                                             \
+  "v_add_u32 %[bw], %[ng], %[bw]\n"                                               \
+  ".Lq" TAG "_%=:\n\t"                                                             \
   "s_ff1_i32_b64 %[a], %[live]\n\t"                                               \
   "s_flbit_i32_b64 %[f], %[live]\n\t"
 
@@ -160,31 +162,45 @@ XD_FN Win make_win(const AsmView &v, vint off) {
   "s_sub_i32 %[tmp], 65, %[tmp]\n\t"                                              \
   "s_add_i32 %[a], %[a], -1\n\t"                                                  \
   "s_bfm_b64 %[range], %[tmp], %[a]\n"
-// Odd anti-diagonal 2(e0 + K) + 1: leave for a recentre when a survivor sits
-// in lane 0, 62 or 63 (.Lc), else the next (even) range is [a, 64 - f].
+// Odd anti-diagonal 2(e0 + K) + 1: the next (even) range is [a, 64 - f].  On
+// odd K the step first leaves for a recentre (.Lc) when a survivor sits in
+// lanes 0-1 or 61-63.  Survivors in lanes [2, 60] there keep the ranges of
+// the next four anti-diagonals inside lanes [0, 62], 63 lanes at most, with
+// lane 0 out of even ranges and lane 63 out of odd ones (the lanes whose
+// shifted neighbour does not exist); the loop is entered only with the
+// range inside lanes [2, 60], which bounds the steps before the first check
+// the same way.
+#define XD_ODD_RANGE                                                              \
+  "s_add_i32 %[tmp], %[a], %[f]\n\t"                                              \
+  "s_sub_i32 %[tmp], 65, %[tmp]\n\t"                                              \
+  "s_bfm_b64 %[range], %[tmp], %[a]\n"
 #define XD_ODD(K, P, DIAG)                                                        \
+  ".Lo" K "_%=:\n\t"                                                               \
+  XD_CORE("o" K, DIAG, "O", "E", "SO", "wave_shl:1", P)                           \
+  XD_ODD_RANGE
+#define XD_ODD_EDGE(K, P, DIAG)                                                   \
   ".Lo" K "_%=:\n\t"                                                               \
   XD_CORE("o" K, DIAG, "O", "E", "SO", "wave_shl:1", P)                           \
   "s_and_b64 vcc, %[live], %[edge]\n\t"                                           \
   "s_cbranch_scc1 .Lco" K "_%=\n\t"                                                \
-  "s_add_i32 %[tmp], %[a], %[f]\n\t"                                              \
-  "s_sub_i32 %[tmp], 65, %[tmp]\n\t"                                              \
-  "s_bfm_b64 %[range], %[tmp], %[a]\n"
+  XD_ODD_RANGE
 #define XD_PAIR(K, P, DIAG) XD_EVEN(K, P, DIAG) XD_ODD(K, P, DIAG)
+#define XD_PAIR_EDGE(K, P, DIAG) XD_EVEN(K, P, DIAG) XD_ODD_EDGE(K, P, DIAG)
 
 // Improvement of best on anti-diagonal e0x2 + BP.  The new best W value is
 // bw + inc with the smallest inc that no lane exceeds; with match = 1 it is
 // always bw + 1 (best grows by at most `match` per anti-diagonal), so the
 // lanes above bw are exactly the lanes holding the new best.  The first of
 // them and the anti-diagonal are recorded; (i, j) and best itself are
-// derived after the loop.
+// derived after the loop.  The unit form applies the anti-diagonal's drift of
+// both thresholds together with the raise and rejoins the step after it.
 #define XD_IMP_UNIT(TAG, CUR, BP)                                                 \
   ".Li" TAG "_%=:\n\t"                                                             \
   "s_ff1_i32_b64 %[bs], vcc\n\t"                                                  \
   "s_add_i32 %[bpos], %[e0x2], " BP "\n\t"                                        \
-  "s_add_i32 %[thr], %[thr], 1\n\t"                                               \
-  "v_add_u32 %[bw], 1, %[bw]\n\t"                                                 \
-  "s_branch .Lr" TAG "_%=\n"
+  "s_add_i32 %[thr], %[thr], %[ng1]\n\t"                                          \
+  "v_add_u32 %[bw], %[ng1], %[bw]\n\t"                                            \
+  "s_branch .Lq" TAG "_%=\n"
 #define XD_IMP_LOOP(TAG, CUR, BP)                                                 \
   ".Li" TAG "_%=:\n\t"                                                             \
   "s_mov_b32 %[inc], 1\n"                                                         \
@@ -222,12 +238,14 @@ XD_FN Win make_win(const AsmView &v, vint off) {
 #define XD_TABLE(K) "s_branch .Le" K "_%=\n\ts_branch .Lo" K "_%=\n\t"
 
 #define XD_ALL_PAIRS(DIAG)                                                        \
-  XD_PAIR("0", "0", DIAG) XD_PAIR("1", "2", DIAG) XD_PAIR("2", "4", DIAG)         \
-  XD_PAIR("3", "6", DIAG) XD_PAIR("4", "8", DIAG) XD_PAIR("5", "10", DIAG)        \
-  XD_PAIR("6", "12", DIAG) XD_PAIR("7", "14", DIAG) XD_PAIR("8", "16", DIAG)      \
-  XD_PAIR("9", "18", DIAG) XD_PAIR("10", "20", DIAG) XD_PAIR("11", "22", DIAG)    \
-  XD_PAIR("12", "24", DIAG) XD_PAIR("13", "26", DIAG) XD_PAIR("14", "28", DIAG)   \
-  XD_PAIR("15", "30", DIAG)
+  XD_PAIR("0", "0", DIAG) XD_PAIR_EDGE("1", "2", DIAG) XD_PAIR("2", "4", DIAG)    \
+  XD_PAIR_EDGE("3", "6", DIAG) XD_PAIR("4", "8", DIAG)                            \
+  XD_PAIR_EDGE("5", "10", DIAG) XD_PAIR("6", "12", DIAG)                          \
+  XD_PAIR_EDGE("7", "14", DIAG) XD_PAIR("8", "16", DIAG)                          \
+  XD_PAIR_EDGE("9", "18", DIAG) XD_PAIR("10", "20", DIAG)                         \
+  XD_PAIR_EDGE("11", "22", DIAG) XD_PAIR("12", "24", DIAG)                        \
+  XD_PAIR_EDGE("13", "26", DIAG) XD_PAIR("14", "28", DIAG)                        \
+  XD_PAIR_EDGE("15", "30", DIAG)
 #define XD_ALL_STUBS(IMP)                                                         \
   XD_STUBS("0", "0", "1", "2", IMP) XD_STUBS("1", "2", "3", "4", IMP)             \
   XD_STUBS("2", "4", "5", "6", IMP) XD_STUBS("3", "6", "7", "8", IMP)             \
@@ -244,6 +262,9 @@ XD_FN Win make_win(const AsmView &v, vint off) {
   XD_TABLE("15")
 
 enum : int { kStepLeave = 3 };
+// Lanes [2, 60]: the assembly loop starts only with the computed range inside
+// them (its edge checks come every fourth anti-diagonal).
+constexpr uint64_t kAsmEntryLanes = ((1ull << 59) - 1ull) << 2;
 
 template <bool NARROW, bool UNIT, bool FWD, bool D2>
 XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &jv,
@@ -266,8 +287,9 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
   int32_t a = 0, f = 0, tmp = 0, inc = 0;
   int32_t bs = 0, bpos = -1;   // lane and anti-diagonal of the last improvement
   uint64_t live = 0;
-  const uint64_t edge = 0xC000000000000001ull;   // lanes 0, 62, 63
+  const uint64_t edge = 0xE000000000000003ull;   // lanes 0, 1, 61, 62, 63
   const int32_t k55 = 0x55555555;
+  const int32_t ng1 = P.neg_gap + 1;   // drift of an anti-diagonal that raised best by 1
   const int32_t hi_a = av_a.hi_rel << 2, hi_b = av_b.hi_rel << 2;   // bytes
   const uint32_t *base_a = av_a.base, *base_b = av_b.base;
   int32_t par = st.par;
@@ -339,7 +361,8 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
         [live] "+s"(live), [a] "+s"(a), [f] "+s"(f), [tmp] "+s"(tmp), [inc] "+s"(inc), \
         [status] "+s"(status)                                                         \
       : [sh0] "v"(w0.sh.x), [sh1] "v"(w1.sh.x), [sh2] "v"(w2.sh.x), [base] "s"(P.base), \
-        [delta] "s"(P.delta), [ng] "s"(P.neg_gap), [lim2] "s"(lim2), [edge] "s"(edge), \
+        [delta] "s"(P.delta), [ng] "s"(P.neg_gap), [ng1] "s"(ng1), [lim2] "s"(lim2),   \
+        [edge] "s"(edge),                                                             \
         [k55] "s"(k55), [pat] "s"(P.pat), [hi_a] "s"(hi_a), [hi_b] "s"(hi_b),          \
         [base_a] "s"(base_a), [base_b] "s"(base_b)                                    \
       : "vcc", "scc", "memory", "s40", "s41", "s42")
@@ -403,6 +426,10 @@ struct RunAsm {
       ensure_words_w1<NARROW>(bd, st, e0, jv, P, words_e0, words_h);
       return run_w1<NARROW, true>(bd, st, e0, e_end, jv, P);
     } else {
+      if (st.range & ~kAsmEntryLanes) {   // too near the edges: C steps for this block
+        ensure_words_w1<NARROW>(bd, st, e0, jv, P, words_e0, words_h);
+        return run_w1<NARROW, false>(bd, st, e0, e_end, jv, P);
+      }
       const int64_t reach = ((int64_t)(jv.m + jv.n) >> 4) + 16;
       const AsmView av_a = make_asm_view(P.A, P.a_words, jv.a_start, reach);
       const AsmView av_b = make_asm_view(P.B, P.b_words, jv.b_start, reach);
