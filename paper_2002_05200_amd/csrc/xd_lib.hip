@@ -37,6 +37,7 @@
 #include "xd_spill.h"
 #include "xd_w1_asm.h"
 #include "xd_wide.h"
+#include "xd_w2_asm.h"
 #include "xd_multi.h"
 
 namespace xd {
@@ -182,6 +183,12 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job *__restrict__ jobs,
         o = extend_job_w1<NARROW, RunAsm>(job, P, j);
       } else {
         o = extend_job_w1<NARROW, RunC>(job, P, j);
+      }
+    } else if constexpr (C == 2) {
+      if (P.impl == 0) {
+        o = extend_job_wide<2, NARROW, true>(job, P, j);
+      } else {
+        o = extend_job_wide<2, NARROW, false>(job, P, j);
       }
     } else {
       o = extend_job_wide<C, NARROW>(job, P, j);

@@ -270,6 +270,10 @@ XD_FN uint64_t lane_span(int lo, int hi) {
   return lo > hi ? 0ull : ((~0ull >> (63 - hi)) & (~0ull << lo));
 }
 
+template <bool NARROW, int PAR>
+XD_FN bool wfinish2(WBand<2> &bd, WScalars &st, uint64_t m0, uint64_t m1, const JobView &jv,
+                    const Params &P);
+
 // Two registers (128 slots): the same step in straight-line form, both
 // registers always updated and clipped by their lane masks.
 template <bool NARROW, int PAR>
@@ -295,6 +299,16 @@ XD_FN bool wstep2(WBand<2> &bd, WScalars &st, int q, const JobView &jv, const Pa
   st.span_lo[PAR] = 0;
   st.span_hi[PAR] = 1;
   st.cells_blk += (uint32_t)(st.hi - st.lo + 1);
+  return wfinish2<NARROW, PAR>(bd, st, m0, m1, jv, P);
+}
+
+// The rest of a two-register anti-diagonal once its cells are computed and
+// pruned (survivor masks m0, m1 of the two registers): end test, best,
+// thresholds and the next range.
+template <bool NARROW, int PAR>
+XD_FN bool wfinish2(WBand<2> &bd, WScalars &st, uint64_t m0, uint64_t m1, const JobView &jv,
+                    const Params &P) {
+  const vint *cur = PAR ? bd.O : bd.E;
   if ((m0 | m1) == 0) return false;
   const int first = m0 ? ctz64(m0) : 64 + ctz64(m1);
   const int last = m1 ? 64 + last_bit64(m1) : last_bit64(m0);
@@ -424,9 +438,71 @@ XD_FN bool wrestore(WBand<C> &bd, WScalars &st, const Params &P, int32_t j) {
   return true;
 }
 
+// ---------------------------------------------------------------------------
+// Fast path of the two-register tier: a hand-scheduled loop (xd_w2_asm.h)
+// runs anti-diagonals while the band straddles the two registers, stays in
+// slots [2, 124] and the window lies inside the matrix.
+enum : int { kW2Step = 1, kW2Recenter = 2, kW2Leave = 3 };
+
+// Runs from anti-diagonal st.d (range st.lo .. st.hi, 2 <= lo <= 63 < 64 <=
+// hi <= 124; the window inside the matrix for the block of st.d).  Adds the
+// cells it computes to st.cells and keeps best, bi, bj, thr, bw current.
+// Returns
+//   kW2Step      anti-diagonal st.d computed and pruned, survivors m0 / m1
+//                with one of them empty; its end test, best, thresholds and
+//                next range still to do (wfinish2);
+//   kW2Recenter  st.d is the next anti-diagonal, st.lo .. st.hi its range,
+//                which reaches slots {0, 1} or {125, 126, 127};
+//   kW2Leave     st.d starts a block in which the window would leave the
+//                matrix; st.lo .. st.hi its range.
+template <bool NARROW, bool FWD>
+XD_FN int w2_loop(WBand<2> &bd, WScalars &st, const JobView &jv, const Params &P, uint64_t &m0,
+                  uint64_t &m1);
+
+// Returns 0 to continue with the C steps at st.d, 1 when the extension has
+// ended, 2 when the band has outgrown the tier.
+template <bool NARROW>
+XD_FN int w2_fast(WBand<2> &bd, WScalars &st, const JobView &jv, const Params &P) {
+  constexpr int S = 2 * kWave;
+  if (!NARROW || !P.unit_match || P.delta != 2) return 0;
+  for (;;) {
+    const int32_t e_end = ((st.d >> 1) & ~15) + 16;
+    if (S - 1 + e_end + st.h > jv.m || st.h < e_end - jv.n) return 0;   // near a read's end
+    const int width = st.hi - st.lo + 1;
+    if (width < 2 || width > S - 5) return 0;
+    if (st.lo < 2 || st.hi > S - 4 || st.lo > kWave - 1 || st.hi < kWave) {
+      if (!wrecenter<2>(bd, st)) return 2;
+      continue;                          // the window moved: test it again
+    }
+    uint64_t m0 = 0, m1 = 0;
+    const int rc = jv.dir > 0 ? w2_loop<NARROW, true>(bd, st, jv, P, m0, m1)
+                              : w2_loop<NARROW, false>(bd, st, jv, P, m0, m1);
+    st.span_lo[0] = st.span_lo[1] = 0;
+    st.span_hi[0] = st.span_hi[1] = 1;
+    st.w_lo = 1;                         // score words to be rebuilt by the C steps
+    st.w_hi = 0;
+    if (rc == kW2Step) {
+      const bool go = (st.d & 1) ? wfinish2<NARROW, 1>(bd, st, m0, m1, jv, P)
+                                 : wfinish2<NARROW, 0>(bd, st, m0, m1, jv, P);
+      if (!go) return 1;
+      continue;
+    }
+    // the pending range may lie in the next block, beyond a read's end: clip
+    // it to the matrix as the C step does
+    const int c1 = (st.d + 1) >> 1;
+    const int i_min = st.d - jv.n > 0 ? st.d - jv.n : 0;
+    const int smin = i_min - c1 - st.h, smax = jv.m - c1 - st.h;
+    if (st.lo < smin) st.lo = smin;
+    if (st.hi > smax) st.hi = smax;
+    if (st.d > jv.m + jv.n || st.lo > st.hi) return 1;
+    if (rc == kW2Recenter && !wrecenter<2>(bd, st)) return 2;
+  }
+}
+
 // Whole one-directional extension of job j, resumed from a narrower tier's
-// save when there is one.
-template <int C, bool NARROW>
+// save when there is one.  FAST (two registers only) enables the
+// hand-scheduled loop.
+template <int C, bool NARROW, bool FAST = false>
 XD_FN JobOut extend_job_wide(const Job &job, const Params &P, int32_t j) {
   constexpr int S = kWave * C;
   JobOut out;
@@ -473,6 +549,17 @@ XD_FN JobOut extend_job_wide(const Job &job, const Params &P, int32_t j) {
   int32_t e0 = e & ~15;
   bool ok = true;
   for (;;) {
+    if constexpr (FAST && C == 2) {
+      const int32_t d_before = st.d;
+      const int rc = w2_fast<NARROW>(bd, st, jv, P);
+      if (rc == 1) break;
+      if (rc == 2) { ok = false; break; }
+      if (st.d != d_before) {   // the loop ran (and left the score words to rebuild)
+        e = st.d >> 1;
+        odd = (st.d & 1) != 0;
+        e0 = e & ~15;
+      }
+    }
     if (!odd) {
       if (st.lo < 1 || st.hi > S - 2) {
         if (!wrecenter<C>(bd, st)) { ok = false; break; }

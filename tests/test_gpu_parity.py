@@ -351,3 +351,35 @@ def test_multi_wave_tier_from_the_start(ctx, xd):
     st = ctx.stats()
     assert st["jobs"][6] == 2 * bt.n, st
     assert_same(got, oracle_of(bt), "multi-wave tier")
+
+
+def _ending_pairs(seed, n=48):
+    """Pairs whose overlap stops partway: B copies A with 3% of each error
+    kind up to a cut and is unrelated after it, so X-drop ends inside the
+    reads with the band still wide (X 60-100)."""
+    from paper_2002_05200_amd import synth
+    rng = np.random.default_rng(np.random.SeedSequence(977, spawn_key=(seed,)))
+    a_l, b_l, pa_l, x_l = [], [], [], []
+    for _ in range(n):
+        la = int(rng.integers(1500, 6000))
+        cut = int(rng.integers(300, la - 300))
+        a = rng.integers(0, 4, la).astype(np.uint8)
+        b = np.concatenate([synth.mutate(rng, a[:cut], 0.03, 0.03, 0.03),
+                            rng.integers(0, 4, la - cut).astype(np.uint8)])
+        pa = int(rng.integers(0, max(1, min(cut, len(b)) - 17)))
+        b[pa:pa + 17] = a[pa:pa + 17]
+        a_l.append(a); b_l.append(b); pa_l.append(pa); x_l.append(int(rng.choice([60, 80, 100])))
+    return synth.from_pairs(a_l, b_l, pa_l, pa_l, x_l, name=f"ending[{seed}]")
+
+
+@pytest.mark.parametrize("impl", [0, 1])
+def test_two_register_tier_cases(ctx, xd, impl):
+    """The two-register tier's hand-scheduled loop and its C steps: bands of
+    X = 60-100 that end inside the reads (a register empties), long X = 100
+    requests (recentres, block boundaries, read ends), both directions."""
+    from paper_2002_05200_amd import synth
+    reqs = [r for r in (synth.make_request(i) for i in range(40)) if int(r.x[0]) == 100][:6]
+    bt = synth.concat([_ending_pairs(0), _ending_pairs(1)] + reqs, name="two-register")
+    ref = oracle_of(bt)
+    assert_same(run(ctx, xd, bt, impl=impl), ref, f"impl {impl}")
+    assert_same(run(ctx, xd, bt, impl=impl, min_tier=1), ref, f"impl {impl} from tier 1")
