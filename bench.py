@@ -10,8 +10,14 @@ the oracle counts them (every cell of every computed anti-diagonal range).
 `roofline` prices the dominant kernel against the INT32 VALU peak at 9
 algorithmic int32 operations per cell, with that kernel's duration taken from
 HIP events recorded by the library around it on the launch stream.
-`cpu_baseline` times the CPU oracle, single-threaded, on an evenly spread
-sample of the same workload.
+`sched_compare` runs the other scheduler (the plain one-wavefront-per-job
+grid against the persistent queue) on the same resident inputs;
+`host_buffers` times the host-memory entry point (allocation, PCIe copies
+both ways and the step) on the same reads.  `serving` is the
+continuous-batching server under Poisson arrivals at a fraction of its
+saturation rate, with a sweep over further loads.  `cpu_baseline` times the
+CPU oracle, single-threaded, on an evenly spread sample of the same workload,
+and once more with one process per host core.
 """
 from __future__ import annotations
 
@@ -64,14 +70,44 @@ def cpu_baseline(workload: str, budget_s: float, n_total: int) -> dict:
         n *= 2
     return {"value": round(cells / secs / 1e9, 4), "unit": "GCUPS", "cores": 1, "kind": "oracle",
             "sample": f"{used} pairs of the same workload spread evenly over it "
-                      f"({cells} cells, {secs:.1f} s, one thread)"}
+                      f"({cells} cells, {secs:.1f} s, one thread)",
+            "all_cores": cpu_all_cores(workload, n_total, used)}
+
+
+def _oracle_shard(args):
+    workload, n_total, start, stride, n = args
+    from oracle import oracle
+    from paper_2002_05200_amd import synth
+    bt = synth.make_batch(workload, n=n, start=start, stride=stride)
+    res, t = oracle.batch(bt, return_time=True)
+    return int(res["left_cells"].sum() + res["right_cells"].sum()), t
+
+
+def cpu_all_cores(workload: str, n_total: int, n_sample: int) -> dict:
+    """The same oracle, one process per host core, each on its own evenly
+    spread shard as large as the single-thread sample (fewer pairs when the
+    workload runs out); GCUPS = all cells / the slowest shard's time."""
+    from multiprocessing import get_context
+    procs = max(1, min(16, os.cpu_count() or 1))
+    per = max(1, min(n_sample, n_total // procs))
+    stride = max(1, n_total // (per * procs))
+    jobs = [(workload, n_total, p, stride * procs, per) for p in range(procs)]
+    with get_context("fork").Pool(procs) as pool:
+        out = pool.map(_oracle_shard, jobs)
+    cells = sum(c for c, _ in out)
+    slowest = max(t for _, t in out)
+    return {"value": round(cells / slowest / 1e9, 4), "unit": "GCUPS", "cores": procs,
+            "sample": f"{per * procs} pairs in {procs} shards ({cells} cells, slowest shard "
+                      f"{slowest:.1f} s)"}
 
 
 def serving_leg(n_distinct: int, n_requests: int, load: float, slots: int, max_batch: int,
-                graph: bool, workers: int) -> dict:
-    """Continuous-batching serving run: saturation throughput closed-loop, then
-    Poisson arrivals at load * saturation; latency from the scheduled arrival
-    to the completion the server's scheduler observed (same steady clock)."""
+                graph: bool, workers: int, sweep=(), sweep_requests: int = 0) -> dict:
+    """Continuous-batching serving run: saturation throughput closed-loop (whose
+    requests are also the warm-up), then Poisson arrivals at load * saturation;
+    latency from the scheduled arrival to the completion the server's
+    scheduler observed (same steady clock).  `sweep` repeats the open-loop run
+    at other loads with sweep_requests requests each."""
     import threading
     from multiprocessing import get_context
     from paper_2002_05200_amd import synth, xdrop
@@ -82,7 +118,6 @@ def serving_leg(n_distinct: int, n_requests: int, load: float, slots: int, max_b
     else:
         reqs = [synth.make_request(r) for r in range(n_distinct)]
     packed = [xdrop.PackedRequest(bt) for bt in reqs]
-    cells_of = None
     print(f"[bench] serving: {n_distinct} distinct requests generated in {time.time()-t0:.1f} s",
           file=sys.stderr, flush=True)
     srv = xdrop.Server(slots=slots, max_batch_pairs=max_batch, graph=int(graph),
@@ -99,46 +134,104 @@ def serving_leg(n_distinct: int, n_requests: int, load: float, slots: int, max_b
         t1 = time.perf_counter()
         closed(n_distinct)
         r_sat = n_distinct / (time.perf_counter() - t1)
-        rate = load * r_sat
-        arrivals = synth.poisson_arrivals(n_requests, rate)
-        tickets = [None] * n_requests
-        sched_ns = [0] * n_requests
-        lat = np.zeros(n_requests)
-        cells = np.zeros(n_requests)
-        done_ns = np.zeros(n_requests, np.int64)
-        ready = threading.Semaphore(0)
 
-        def poller():
+        def open_loop(load, n_requests, seed_key):
+            rate = load * r_sat
+            arrivals = synth.poisson_arrivals(n_requests, rate, seed_key)
+            tickets = [None] * n_requests
+            sched_ns = [0] * n_requests
+            lat = np.zeros(n_requests)
+            cells = np.zeros(n_requests)
+            done_ns = np.zeros(n_requests, np.int64)
+            ready = threading.Semaphore(0)
+
+            def poller():
+                for i in range(n_requests):
+                    ready.acquire()
+                    r, dn = srv.poll(tickets[i], packed[i % n_distinct].n, wait_ms=-1)
+                    lat[i] = (dn - sched_ns[i]) / 1e6
+                    done_ns[i] = dn
+                    cells[i] = int(r["left_cells"].sum() + r["right_cells"].sum())
+
+            th = threading.Thread(target=poller)
+            th.start()
+            start = time.monotonic_ns() + 2_000_000
             for i in range(n_requests):
-                ready.acquire()
-                r, dn = srv.poll(tickets[i], packed[i % n_distinct].n, wait_ms=-1)
-                lat[i] = (dn - sched_ns[i]) / 1e6
-                done_ns[i] = dn
-                cells[i] = int(r["left_cells"].sum() + r["right_cells"].sum())
+                sched_ns[i] = start + int(arrivals[i] * 1e9)
+                while time.monotonic_ns() < sched_ns[i]:
+                    pass
+                tickets[i] = srv.submit(packed[i % n_distinct])
+                ready.release()
+            th.join()
+            window = (done_ns.max() - start) / 1e9
+            return {"load": load, "requests": n_requests, "rate_requests_per_s": round(rate, 1),
+                    "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                    "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                    "gcups": round(float(cells.sum()) / window / 1e9, 2)}
 
-        th = threading.Thread(target=poller)
-        th.start()
-        start = time.monotonic_ns() + 2_000_000
-        for i in range(n_requests):
-            sched_ns[i] = start + int(arrivals[i] * 1e9)
-            while time.monotonic_ns() < sched_ns[i]:
-                pass
-            tickets[i] = srv.submit(packed[i % n_distinct])
-            ready.release()
-        th.join()
-        window = (done_ns.max() - start) / 1e9
+        main_run = open_loop(load, n_requests, 0)
+        print(f"[bench] serving at load {load}: {main_run}", file=sys.stderr, flush=True)
+        others = []
+        for k, ld in enumerate(sweep):
+            others.append(open_loop(ld, sweep_requests, k + 1))
+            print(f"[bench] serving at load {ld}: {others[-1]}", file=sys.stderr, flush=True)
         st = srv.stats()
     finally:
         srv.close()
-    return {"requests": n_requests, "distinct_requests": n_distinct,
-            "saturation_requests_per_s": round(r_sat, 1), "load": load,
-            "rate_requests_per_s": round(rate, 1),
-            "p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "gcups": round(float(cells.sum()) / window / 1e9, 2),
-            "slots": slots, "max_batch_pairs": max_batch, "graph": bool(graph),
-            "batches": st["batches"], "max_inflight": st["max_inflight"],
-            "workload": synth.WORKLOADS["serving"].describe}
+    out = {"requests": n_requests, "warmup_requests": min(200, n_distinct) + n_distinct,
+           "distinct_requests": n_distinct, "saturation_requests_per_s": round(r_sat, 1)}
+    out.update(main_run)
+    out.update({"slots": slots, "max_batch_pairs": max_batch, "graph": bool(graph),
+                "batches": st["batches"], "max_inflight": st["max_inflight"],
+                "load_sweep": others, "workload": synth.WORKLOADS["serving"].describe})
+    return out
+
+
+def sched_compare(ctx, db, stream, args, tuned, gcups, ref) -> dict:
+    """The other scheduler (plain one-wavefront-per-job grid, or the persistent
+    queue) on the same resident inputs, with identical results required."""
+    import torch
+    from paper_2002_05200_amd import xdrop
+    other = "persistent" if args.sched == "plain" else "plain"
+    code = xdrop.SCHED_PERSISTENT if other == "persistent" else xdrop.SCHED_PLAIN
+    o = xdrop.make_opts(sched=code, **tuned)
+    steps = max(2, args.steps // 5)
+    ctx.extend_device(db, stream=stream, opts=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.extend_device(db, stream=stream, opts=o)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res = db.results()
+    assert all(np.array_equal(res[f], ref[f]) for f in ref.dtype.names), \
+        f"{other} results differ from {args.sched}"
+    cells = int(res["left_cells"].sum() + res["right_cells"].sum())
+    mine = "persistent" if args.sched == "auto" else args.sched
+    return {mine: round(gcups, 2), other: round(cells * steps / el / 1e9, 2),
+            f"{other}_steps": steps, "results_identical": True}
+
+
+def host_buffers(ctx, db, args, tuned, cells_per_step, ref) -> dict:
+    """xdrop_extend_host on the same packed reads and pair records held in host
+    memory: device allocation, copies in over PCIe, the step, results back."""
+    from paper_2002_05200_amd import xdrop
+    sched = {"auto": xdrop.SCHED_AUTO, "plain": xdrop.SCHED_PLAIN,
+             "persistent": xdrop.SCHED_PERSISTENT}[args.sched]
+    o = xdrop.make_opts(sched=sched, **tuned)
+    ctx.extend_host_packed(db.a_words, db.b_words, db.pairs, db.scores, o)
+    times = []
+    for _ in range(2):
+        t0 = time.perf_counter()
+        out = ctx.extend_host_packed(db.a_words, db.b_words, db.pairs, db.scores, o)
+        times.append(time.perf_counter() - t0)
+    assert all(np.array_equal(out[f], ref[f]) for f in ref.dtype.names), "host path differs"
+    ms = min(times) * 1e3
+    mb_in = (db.a_words.nbytes + db.b_words.nbytes + db.pairs.nbytes) / 1e6
+    return {"api": "xdrop_extend_host", "ms_per_call": round(ms, 3),
+            "gcups": round(cells_per_step / (ms / 1e3) / 1e9, 2), "mb_in": round(mb_in, 1),
+            "mb_out": round(len(out) * out.dtype.itemsize / 1e6, 1),
+            "note": "pageable host buffers; includes device allocation and both copies"}
 
 
 def main():
@@ -151,8 +244,13 @@ def main():
     ap.add_argument("--sched", default="auto", choices=["auto", "plain", "persistent"])
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=4000,
-                    help="requests of the serving leg (0 = skip it)")
+    ap.add_argument("--serving-requests", type=int, default=20000,
+                    help="requests of the serving leg at --serving-load (0 = skip the leg)")
+    ap.add_argument("--serving-sweep", default="0.3,0.5,0.9",
+                    help="further loads (fractions of saturation) of the serving leg")
+    ap.add_argument("--serving-sweep-requests", type=int, default=4000)
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the other-scheduler and host-buffer legs")
     ap.add_argument("--serving-distinct", type=int, default=1000,
                     help="distinct generated requests the serving leg cycles through")
     ap.add_argument("--serving-load", type=float, default=0.7)
@@ -288,12 +386,17 @@ def main():
                          ["plan", "tier0", "tier1", "tier2", "tier3", "tier4", "tier5", "spill",
                           "combine"], stage_ms)}},
     }
+    if not args.no_compare:
+        line["sched_compare"] = sched_compare(ctx, db, stream, args, tuned, gcups, res2)
+        line["host_buffers"] = host_buffers(ctx, db, args, tuned, cells_per_step, res2)
     ctx.close()
     del db
     if args.serving_requests:
+        sweep = [float(v) for v in args.serving_sweep.split(",") if v.strip()]
         line["serving"] = serving_leg(args.serving_distinct, args.serving_requests,
                                       args.serving_load, args.serving_slots, args.serving_batch,
-                                      bool(args.serving_graph), min(16, os.cpu_count() or 1))
+                                      bool(args.serving_graph), min(16, os.cpu_count() or 1),
+                                      sweep, args.serving_sweep_requests)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget, n_pairs)
     print(json.dumps(line), flush=True)

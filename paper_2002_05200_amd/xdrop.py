@@ -231,11 +231,19 @@ class Context:
 
     def extend_host(self, bt, opts: Optional[Opts] = None) -> np.ndarray:
         """xdrop_extend_host: host arrays in, host results out."""
-        a, b, pr = pack_codes(bt.a), pack_codes(bt.b), make_pairs(bt)
-        out = np.zeros(bt.n, RESULT_DTYPE)
+        return self.extend_host_packed(pack_codes(bt.a), pack_codes(bt.b), make_pairs(bt),
+                                       bt.scores, opts)
+
+    def extend_host_packed(self, a_words: np.ndarray, b_words: np.ndarray, pairs: np.ndarray,
+                           scores: Sequence[int], opts: Optional[Opts] = None) -> np.ndarray:
+        """xdrop_extend_host on packed arenas and xd_pair records held on the host."""
+        a = np.ascontiguousarray(a_words, dtype=np.uint32)
+        b = np.ascontiguousarray(b_words, dtype=np.uint32)
+        pr = np.ascontiguousarray(pairs, dtype=PAIR_DTYPE)
+        out = np.zeros(len(pr), RESULT_DTYPE)
         _check(lib().xdrop_extend_host(
             self.h, a.ctypes.data_as(ctypes.c_void_p), len(a), b.ctypes.data_as(ctypes.c_void_p),
-            len(b), pr.ctypes.data_as(ctypes.c_void_p), bt.n, Scores(*bt.scores),
+            len(b), pr.ctypes.data_as(ctypes.c_void_p), len(pr), Scores(*scores),
             out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts) if opts is not None else None))
         return out
 
