@@ -104,6 +104,32 @@ XD_FN void wcell(vint *cur, const vint *prv, const vint *sw, int pos, int32_t th
   imp |= ballot(cur[R] > bw);
 }
 
+// The same cell update along a chain of registers that carries the rotated
+// neighbour register: even anti-diagonals walk the span upwards and odd ones
+// downwards, so each register is rotated once.  `carry` holds the rotation
+// of the register walked just before (-inf at the chain's start: that lane's
+// neighbour slot lies outside the previous anti-diagonal's survivors, and
+// every slot outside them holds -inf).
+// The improvement test is deferred: a running lane-wise maximum over the
+// chain is compared with bw once afterwards.
+template <int C, bool NARROW, int PAR, int R>
+XD_FN void wcell_chain(vint *cur, const vint *prv, const vint *sw, int pos, int32_t thr,
+                       vint &vmx, vint &carry, const Params &P) {
+  vint t;
+  if (PAR == 0) {   // slots s-1, s: lane 0 from the rotation of register R-1
+    const vint own = rot_prev(prv[R]);
+    t = select(lanes(1ull), carry, own);
+    carry = own;
+  } else {          // slots s, s+1: lane 63 from the rotation of register R+1
+    const vint own = rot_next(prv[R]);
+    t = select(lanes(1ull << 63), carry, own);
+    carry = own;
+  }
+  const vint v = vmax3(diag_term<NARROW>(cur[R], sw[R], pos, P), prv[R], t);
+  cur[R] = select(v >= thr, v, kNeg);
+  vmx = vmax(vmx, cur[R]);
+}
+
 // Clips register R, an edge of the span, to the range lanes in `mask`;
 // returns its surviving lanes.
 template <int R>
@@ -153,27 +179,79 @@ XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Par
     for (int r = 0; r < C; ++r)
       if ((r < rlo || r > rhi) && r >= plo && r <= phi) cur[r] = splat(kNeg);
   }
-  const int32_t thr = st.thr, bw = st.bw;
-  uint64_t imp = 0;
-  switch (rlo) {
-#define XD_SPAN_CASE(R)                                               \
-  case R:                                                             \
-    if constexpr (R < C) {                                            \
-      wcell<C, NARROW, PAR, R>(cur, prv, sw, pos, thr, bw, imp, P);   \
-      if (rhi == R) break;                                            \
-    }                                                                 \
-    [[fallthrough]];
-    XD_SPAN_CASE(0) XD_SPAN_CASE(1) XD_SPAN_CASE(2) XD_SPAN_CASE(3) XD_SPAN_CASE(4)
-    XD_SPAN_CASE(5) XD_SPAN_CASE(6) XD_SPAN_CASE(7) XD_SPAN_CASE(8) XD_SPAN_CASE(9)
-    XD_SPAN_CASE(10) XD_SPAN_CASE(11) XD_SPAN_CASE(12) XD_SPAN_CASE(13) XD_SPAN_CASE(14)
-    XD_SPAN_CASE(15) XD_SPAN_CASE(16) XD_SPAN_CASE(17) XD_SPAN_CASE(18) XD_SPAN_CASE(19)
-    XD_SPAN_CASE(20) XD_SPAN_CASE(21) XD_SPAN_CASE(22) XD_SPAN_CASE(23) XD_SPAN_CASE(24)
-    XD_SPAN_CASE(25) XD_SPAN_CASE(26) XD_SPAN_CASE(27) XD_SPAN_CASE(28) XD_SPAN_CASE(29)
-    XD_SPAN_CASE(30) XD_SPAN_CASE(31)
-#undef XD_SPAN_CASE
-    default:
-      break;
+  const int32_t thr = st.thr;
+  vint vmx = splat(kNeg);
+  // The chain's outer neighbour slot (below the range on even anti-diagonals,
+  // above it on odd ones) holds -inf unless the range was clipped to the
+  // matrix at that end; then its register's rotation is fetched.
+  vint carry = splat(kNeg);
+  {
+    const int c = (st.d + 1) >> 1;
+    const int i_min = st.d - jv.n > 0 ? st.d - jv.n : 0;
+    if (PAR == 0 ? (rlo > 0 && st.lo <= i_min - c - st.h)
+                 : (rhi < C - 1 && st.hi >= jv.m - c - st.h)) {
+      const int rn = PAR == 0 ? rlo - 1 : rhi + 1;
+      switch (rn) {
+#define XD_NEIGHBOUR(R)                                                 \
+  case R:                                                               \
+    if constexpr (R < C) carry = PAR == 0 ? rot_prev(prv[R]) : rot_next(prv[R]); \
+    break;
+        XD_NEIGHBOUR(0) XD_NEIGHBOUR(1) XD_NEIGHBOUR(2) XD_NEIGHBOUR(3) XD_NEIGHBOUR(4)
+        XD_NEIGHBOUR(5) XD_NEIGHBOUR(6) XD_NEIGHBOUR(7) XD_NEIGHBOUR(8) XD_NEIGHBOUR(9)
+        XD_NEIGHBOUR(10) XD_NEIGHBOUR(11) XD_NEIGHBOUR(12) XD_NEIGHBOUR(13) XD_NEIGHBOUR(14)
+        XD_NEIGHBOUR(15) XD_NEIGHBOUR(16) XD_NEIGHBOUR(17) XD_NEIGHBOUR(18) XD_NEIGHBOUR(19)
+        XD_NEIGHBOUR(20) XD_NEIGHBOUR(21) XD_NEIGHBOUR(22) XD_NEIGHBOUR(23) XD_NEIGHBOUR(24)
+        XD_NEIGHBOUR(25) XD_NEIGHBOUR(26) XD_NEIGHBOUR(27) XD_NEIGHBOUR(28) XD_NEIGHBOUR(29)
+        XD_NEIGHBOUR(30) XD_NEIGHBOUR(31)
+#undef XD_NEIGHBOUR
+        default:
+          break;
+      }
+    }
   }
+  if constexpr (PAR == 0) {   // upwards from rlo
+    switch (rlo) {
+#define XD_SPAN_UP(R)                                                          \
+  case R:                                                                      \
+    if constexpr (R < C) {                                                     \
+      wcell_chain<C, NARROW, 0, R>(cur, prv, sw, pos, thr, vmx, carry, P);     \
+      if (rhi == R) break;                                                     \
+    }                                                                          \
+    [[fallthrough]];
+      XD_SPAN_UP(0) XD_SPAN_UP(1) XD_SPAN_UP(2) XD_SPAN_UP(3) XD_SPAN_UP(4)
+      XD_SPAN_UP(5) XD_SPAN_UP(6) XD_SPAN_UP(7) XD_SPAN_UP(8) XD_SPAN_UP(9)
+      XD_SPAN_UP(10) XD_SPAN_UP(11) XD_SPAN_UP(12) XD_SPAN_UP(13) XD_SPAN_UP(14)
+      XD_SPAN_UP(15) XD_SPAN_UP(16) XD_SPAN_UP(17) XD_SPAN_UP(18) XD_SPAN_UP(19)
+      XD_SPAN_UP(20) XD_SPAN_UP(21) XD_SPAN_UP(22) XD_SPAN_UP(23) XD_SPAN_UP(24)
+      XD_SPAN_UP(25) XD_SPAN_UP(26) XD_SPAN_UP(27) XD_SPAN_UP(28) XD_SPAN_UP(29)
+      XD_SPAN_UP(30) XD_SPAN_UP(31)
+#undef XD_SPAN_UP
+      default:
+        break;
+    }
+  } else {                    // downwards from rhi
+    switch (rhi) {
+#define XD_SPAN_DOWN(R)                                                               \
+  case 31 - R:                                                                        \
+    if constexpr (31 - R < C) {                                                       \
+      wcell_chain<C, NARROW, 1, (31 - R < C ? 31 - R : 0)>(cur, prv, sw, pos, thr, vmx, \
+                                                            carry, P);                \
+      if (rlo == 31 - R) break;                                                       \
+    }                                                                                 \
+    [[fallthrough]];
+      XD_SPAN_DOWN(0) XD_SPAN_DOWN(1) XD_SPAN_DOWN(2) XD_SPAN_DOWN(3) XD_SPAN_DOWN(4)
+      XD_SPAN_DOWN(5) XD_SPAN_DOWN(6) XD_SPAN_DOWN(7) XD_SPAN_DOWN(8) XD_SPAN_DOWN(9)
+      XD_SPAN_DOWN(10) XD_SPAN_DOWN(11) XD_SPAN_DOWN(12) XD_SPAN_DOWN(13) XD_SPAN_DOWN(14)
+      XD_SPAN_DOWN(15) XD_SPAN_DOWN(16) XD_SPAN_DOWN(17) XD_SPAN_DOWN(18) XD_SPAN_DOWN(19)
+      XD_SPAN_DOWN(20) XD_SPAN_DOWN(21) XD_SPAN_DOWN(22) XD_SPAN_DOWN(23) XD_SPAN_DOWN(24)
+      XD_SPAN_DOWN(25) XD_SPAN_DOWN(26) XD_SPAN_DOWN(27) XD_SPAN_DOWN(28) XD_SPAN_DOWN(29)
+      XD_SPAN_DOWN(30) XD_SPAN_DOWN(31)
+#undef XD_SPAN_DOWN
+      default:
+        break;
+    }
+  }
+  uint64_t imp = ballot(vmx > st.bw);
   // clip the edge registers to the computed range
   const uint64_t lo_mask = ~0ull << (st.lo & 63);
   const uint64_t hi_mask = ~0ull >> (63 - (st.hi & 63));
@@ -209,6 +287,26 @@ XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Par
       if (last >= 0 || r < rlo || r >= rhi) continue;
       const uint64_t m = ballot(cur[r] != kNeg);
       if (m != 0) last = 64 * r + last_bit64(m);
+    }
+  }
+  if (imp != 0 && P.unit_match) {
+    // match = 1: best rises by exactly 1 and the new best cells are the
+    // lanes above bw, so the first register holding one (after clipping)
+    // gives both the confirmation and the best cell
+    int sbest = -1;
+#pragma unroll
+    for (int r = 0; r < C; ++r) {
+      if (sbest >= 0 || r < rlo || r > rhi) continue;
+      const uint64_t m = ballot(cur[r] > st.bw);
+      if (m != 0) sbest = 64 * r + ctz64(m);
+    }
+    imp = 0;
+    if (sbest >= 0) {
+      st.bw += 1;
+      st.thr += 1;
+      st.best += 1;
+      st.bi = sbest + ((st.d + 1) >> 1) + st.h;
+      st.bj = st.d - st.bi;
     }
   }
   if (imp != 0) {   // confirm on the clipped registers
