@@ -102,9 +102,10 @@ typedef struct {
     int32_t graph;        /* 1 = capture the launch sequence in a hipGraph on
                              the first call and replay it while every argument
                              stays the same; needs a non-NULL stream            */
-    int32_t multi_wave;   /* 1 = the tiers of 8, 16 and 32 cells per lane run
-                             four wavefronts per job (shorter anti-diagonal
-                             steps for very long jobs); 0 = one wavefront      */
+    int32_t multi_wave;   /* 1 / 2 = the tiers of 8, 16 and 32 cells per lane
+                             run four / two wavefronts per job (shorter
+                             anti-diagonal steps for very long jobs);
+                             0 = one wavefront; others: XD_EINVAL             */
 } xd_opts; /* 40 bytes */
 
 /* Statistics of the last xdrop_extend on a context.  Tier t in 0..5 runs C =

@@ -27,6 +27,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "xdrop.h"
@@ -362,7 +363,7 @@ xd_status ensure_capacity(xd_ctx *c, int64_t n_pairs) {
 
 template <int C, bool NARROW>
 hipError_t launch_tier(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_cu,
-                       int64_t max_jobs, int tier, const Params &P, bool multi_wave) {
+                       int64_t max_jobs, int tier, const Params &P, int multi_wave) {
   const int64_t stride = 2 * c->cap_pairs;
   TierQueue q;
   q.order = c->order;
@@ -372,14 +373,19 @@ hipError_t launch_tier(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_
   q.tier = tier;
   int32_t *head = persistent ? c->counters + kHead + tier : nullptr;
   if constexpr (C >= 8) {
-    if (multi_wave) {   // four wavefronts per job, C / 4 registers each
-      constexpr int NW = 4;
-      int64_t groups = persistent ? ((int64_t)c->num_cu * waves_per_cu + NW - 1) / NW : max_jobs;
-      if (groups < 1) groups = 1;
-      hipLaunchKernelGGL((k_extend_mw<NW, C / NW, NARROW>), dim3((unsigned)groups), dim3(64 * NW),
-                         0, s, c->jobs, q, head, c->outs, c->stats, P, q.next_esc,
-                         c->counters + kEsc + tier + 1);
-      return hipGetLastError();
+    if (multi_wave != 0) {   // NW wavefronts per job, C / NW registers each
+      auto launch_mw = [&](auto nw) {
+        constexpr int NW = decltype(nw)::value;
+        int64_t groups =
+            persistent ? ((int64_t)c->num_cu * waves_per_cu + NW - 1) / NW : max_jobs;
+        if (groups < 1) groups = 1;
+        hipLaunchKernelGGL((k_extend_mw<NW, C / NW, NARROW>), dim3((unsigned)groups),
+                           dim3(64 * NW), 0, s, c->jobs, q, head, c->outs, c->stats, P,
+                           q.next_esc, c->counters + kEsc + tier + 1);
+        return hipGetLastError();
+      };
+      return multi_wave == 2 ? launch_mw(std::integral_constant<int, 2>())
+                             : launch_mw(std::integral_constant<int, 4>());
     }
   }
   int64_t blocks;
@@ -396,7 +402,7 @@ hipError_t launch_tier(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_
 
 template <bool NARROW>
 hipError_t launch_tiers(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_cu,
-                        int64_t nj, const Params &P, bool prof, bool mw) {
+                        int64_t nj, const Params &P, bool prof, int mw) {
   // waves per CU suited to each tier's register footprint
   const int wpc[kTiers] = {32, 32, 24, 16, 8, 4};
   auto w = [&](int t) { return waves_per_cu > 0 ? waves_per_cu : wpc[t]; };
@@ -477,7 +483,7 @@ xd_status enqueue(xd_ctx *c, hipStream_t s, const Launch &L, bool prof) {
                      bin_off, bin_cursor, c->order);
   XD_HIP(hipGetLastError());
   if (prof) XD_HIP(hipEventRecord(c->ev[1], s));
-  const bool mw = o.multi_wave != 0;
+  const int mw = o.multi_wave;
   hipError_t e = narrow ? launch_tiers<true>(c, s, persistent, o.waves_per_cu, nj, P, prof, mw)
                         : launch_tiers<false>(c, s, persistent, o.waves_per_cu, nj, P, prof, mw);
   if (e != hipSuccess) return fail(XD_EDEVICE, std::string("k_extend: ") + hipGetErrorString(e));
@@ -610,7 +616,7 @@ xd_status xdrop_extend(xd_ctx *c, const uint32_t *d_a, uint64_t a_words, const u
   if (o.impl < 0 || o.impl > 1) return fail(XD_EINVAL, "xdrop_extend: impl out of range");
   if (o.long_job < 0 || o.long_tier_bias < 0 || o.long_tier_bias >= kTiers)
     return fail(XD_EINVAL, "xdrop_extend: long_job / long_tier_bias out of range");
-  if (o.multi_wave < 0 || o.multi_wave > 1)
+  if (o.multi_wave < 0 || o.multi_wave > 2)
     return fail(XD_EINVAL, "xdrop_extend: multi_wave out of range");
   if (o.waves_per_cu < 0 || o.waves_per_cu > 64)
     return fail(XD_EINVAL, "xdrop_extend: waves_per_cu out of range");

@@ -131,22 +131,71 @@ XD_FN bool mw_step(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w, int 
     const int32_t nb_below = w > 0 ? sh.edge[1 - PAR][w - 1][1] : kNeg;
     const int32_t nb_above = w < NW - 1 ? sh.edge[1 - PAR][w + 1][0] : kNeg;
     const int32_t thr = st.thr, bw = st.bw;
-    uint64_t imp = 0;
-    switch (rlo) {
-#define XD_MW_CASE(R)                                                                      \
-  case R:                                                                                  \
-    if constexpr (R < C) {                                                                 \
-      wcell<C, NARROW, PAR, R>(cur, prv, sw, pos, thr, bw, imp, P, nb_below, nb_above);    \
-      if (rhi == R) break;                                                                 \
-    }                                                                                      \
-    [[fallthrough]];
-      XD_MW_CASE(0) XD_MW_CASE(1) XD_MW_CASE(2) XD_MW_CASE(3) XD_MW_CASE(4) XD_MW_CASE(5)
-      XD_MW_CASE(6) XD_MW_CASE(7) XD_MW_CASE(8) XD_MW_CASE(9) XD_MW_CASE(10) XD_MW_CASE(11)
-      XD_MW_CASE(12) XD_MW_CASE(13) XD_MW_CASE(14) XD_MW_CASE(15)
-#undef XD_MW_CASE
-      default:
-        break;
+    // the chunk's registers as one chain (see wcell_chain): upwards on even
+    // anti-diagonals, downwards on odd ones; the chain's outer neighbour is
+    // the adjacent wave's posted edge when the chain starts at the chunk's
+    // edge, else -inf unless the range was clipped to the matrix there
+    vint carry = splat(kNeg);
+    {
+      const int c = (st.d + 1) >> 1;
+      const int i_min = st.d - jv.n > 0 ? st.d - jv.n : 0;
+      if (PAR == 0 && rlo == 0) {
+        carry = splat(nb_below);
+      } else if (PAR == 1 && rhi == C - 1) {
+        carry = splat(nb_above);
+      } else if (PAR == 0 ? st.lo <= i_min - c - st.h : st.hi >= jv.m - c - st.h) {
+        const int rn = PAR == 0 ? rlo - 1 : rhi + 1;
+        switch (rn) {
+#define XD_MW_NEIGHBOUR(R)                                                                  \
+  case R:                                                                                   \
+    if constexpr (R < C) carry = PAR == 0 ? rot_prev(prv[R]) : rot_next(prv[R]);           \
+    break;
+          XD_MW_NEIGHBOUR(0) XD_MW_NEIGHBOUR(1) XD_MW_NEIGHBOUR(2) XD_MW_NEIGHBOUR(3)
+          XD_MW_NEIGHBOUR(4) XD_MW_NEIGHBOUR(5) XD_MW_NEIGHBOUR(6) XD_MW_NEIGHBOUR(7)
+          XD_MW_NEIGHBOUR(8) XD_MW_NEIGHBOUR(9) XD_MW_NEIGHBOUR(10) XD_MW_NEIGHBOUR(11)
+          XD_MW_NEIGHBOUR(12) XD_MW_NEIGHBOUR(13) XD_MW_NEIGHBOUR(14) XD_MW_NEIGHBOUR(15)
+#undef XD_MW_NEIGHBOUR
+          default:
+            break;
+        }
+      }
     }
+    vint vmx = splat(kNeg);
+    if constexpr (PAR == 0) {
+      switch (rlo) {
+#define XD_MW_UP(R)                                                                          \
+  case R:                                                                                    \
+    if constexpr (R < C) {                                                                   \
+      wcell_chain<C, NARROW, 0, R>(cur, prv, sw, pos, thr, vmx, carry, P);                  \
+      if (rhi == R) break;                                                                   \
+    }                                                                                        \
+    [[fallthrough]];
+        XD_MW_UP(0) XD_MW_UP(1) XD_MW_UP(2) XD_MW_UP(3) XD_MW_UP(4) XD_MW_UP(5) XD_MW_UP(6)
+        XD_MW_UP(7) XD_MW_UP(8) XD_MW_UP(9) XD_MW_UP(10) XD_MW_UP(11) XD_MW_UP(12)
+        XD_MW_UP(13) XD_MW_UP(14) XD_MW_UP(15)
+#undef XD_MW_UP
+        default:
+          break;
+      }
+    } else {
+      switch (rhi) {
+#define XD_MW_DOWN(R)                                                                         \
+  case 15 - R:                                                                                \
+    if constexpr (15 - R < C) {                                                               \
+      wcell_chain<C, NARROW, 1, (15 - R < C ? 15 - R : 0)>(cur, prv, sw, pos, thr, vmx,      \
+                                                            carry, P);                       \
+      if (rlo == 15 - R) break;                                                               \
+    }                                                                                         \
+    [[fallthrough]];
+        XD_MW_DOWN(0) XD_MW_DOWN(1) XD_MW_DOWN(2) XD_MW_DOWN(3) XD_MW_DOWN(4) XD_MW_DOWN(5)
+        XD_MW_DOWN(6) XD_MW_DOWN(7) XD_MW_DOWN(8) XD_MW_DOWN(9) XD_MW_DOWN(10) XD_MW_DOWN(11)
+        XD_MW_DOWN(12) XD_MW_DOWN(13) XD_MW_DOWN(14) XD_MW_DOWN(15)
+#undef XD_MW_DOWN
+        default:
+          break;
+      }
+    }
+    const uint64_t imp = ballot(vmx > bw);
     const uint64_t lo_mask = ~0ull << (cl & 63);
     const uint64_t hi_mask = ~0ull >> (63 - (ch & 63));
     uint64_t live_lo, live_hi;
@@ -176,7 +225,17 @@ XD_FN bool mw_step(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w, int 
         if (m != 0) last = base + 64 * r + last_bit64(m);
       }
     }
-    if (imp != 0) {   // this chunk's best value above bw and its first slot
+    if (imp != 0 && P.unit_match) {   // best can rise by 1 only: one pass
+#pragma unroll
+      for (int r = 0; r < C; ++r) {
+        if (bests != 0x7fffffff || r < rlo || r > rhi) continue;
+        const uint64_t m = ballot(cur[r] > bw);
+        if (m != 0) {
+          bestv = bw + 1;
+          bests = base + 64 * r + ctz64(m);
+        }
+      }
+    } else if (imp != 0) {   // this chunk's best value above bw and its first slot
       int inc = 0;
       for (;;) {
         uint64_t more = 0;

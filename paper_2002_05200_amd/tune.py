@@ -6,7 +6,8 @@ The kernels' results never depend on these options, only their speed does:
   long_job start long_tier_bias lane-width tiers wider, so bands that will
   grow wide skip the narrow windows they would outgrow);
 - sort_jobs: longest-estimated-job-first order on or off;
-- multi_wave: four wavefronts per job in the widest single-job tiers.
+- multi_wave: four (1) or two (2) wavefronts per job in the widest
+  single-job tiers.
 
 `tune` times candidates on a sample batch already resident on the device
 (coordinate descent from the defaults, median of a few repetitions, timed
@@ -34,7 +35,7 @@ CANDIDATES: Dict[str, List[int]] = {
     "long_job": [2000, 10000, 40000],
     "waves_per_cu": [0, 8, 16, 24],
     "sort_jobs": [1, 0],
-    "multi_wave": [1],
+    "multi_wave": [1, 2],
 }
 DEFAULTS = {"sched": 0, "waves_per_cu": 0, "sort_jobs": 1, "long_job": 0, "long_tier_bias": 0,
             "multi_wave": 0}

@@ -219,7 +219,8 @@ def test_launch_options_do_not_change_results(ctx, xd):
     for kw in [dict(sort_jobs=0), dict(long_job=1000, long_tier_bias=2),
                dict(long_job=1, long_tier_bias=5), dict(waves_per_cu=4),
                dict(sched=1, long_job=500, long_tier_bias=1), dict(multi_wave=1),
-               dict(multi_wave=1, sched=1), dict(multi_wave=1, min_tier=3)]:
+               dict(multi_wave=1, sched=1), dict(multi_wave=1, min_tier=3),
+               dict(multi_wave=2), dict(multi_wave=2, min_tier=3)]:
         assert_same(run(ctx, xd, bt, **kw), ref, f"opts {kw}")
 
 
@@ -275,6 +276,7 @@ def test_escalated_jobs_resume_in_the_wider_tier(ctx, xd, scores):
     assert_same(got, oracle_of(bt), f"escalations {scores}")
     assert_same(run(ctx, xd, bt, impl=1), got, "escalations, C loops")
     assert_same(run(ctx, xd, bt, multi_wave=1), got, "escalations, four wavefronts per job")
+    assert_same(run(ctx, xd, bt, multi_wave=2), got, "escalations, two wavefronts per job")
 
 
 def asymmetric_cases(seed, n=150):
