@@ -403,8 +403,10 @@ hipError_t launch_tier(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_
 template <bool NARROW>
 hipError_t launch_tiers(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_cu,
                         int64_t nj, const Params &P, bool prof, int mw) {
-  // waves per CU suited to each tier's register footprint
-  const int wpc[kTiers] = {32, 32, 24, 16, 8, 4};
+  // waves per CU: each tier's resident limit from its register footprint
+  // (4 SIMDs x waves per SIMD: 7, 5, 7, 5, 3, 1 for C = 1 .. 32), rounded up
+  // for the narrow tiers, whose queues are long
+  const int wpc[kTiers] = {32, 32, 28, 20, 12, 4};
   auto w = [&](int t) { return waves_per_cu > 0 ? waves_per_cu : wpc[t]; };
   hipError_t e;
   auto mark = [&](int i) { return prof ? hipEventRecord(c->ev[i], s) : hipSuccess; };
