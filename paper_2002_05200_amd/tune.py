@@ -33,9 +33,9 @@ TABLE_PATH = os.path.join(HERE, "tune_table.json")
 CANDIDATES: Dict[str, List[int]] = {
     "long_tier_bias": [0, 1, 2, 3],
     "long_job": [2000, 10000, 40000],
+    "multi_wave": [1, 2],
     "waves_per_cu": [0, 8, 16, 24],
     "sort_jobs": [1, 0],
-    "multi_wave": [1, 2],
 }
 DEFAULTS = {"sched": 0, "waves_per_cu": 0, "sort_jobs": 1, "long_job": 0, "long_tier_bias": 0,
             "multi_wave": 0}
@@ -86,30 +86,39 @@ def time_opts(ctx, db, opts_kw: dict, reps: int = 3) -> float:
     return float(np.median(times))
 
 
-def tune(ctx, db, reps: int = 3, log=None) -> dict:
-    """Coordinate descent over CANDIDATES from DEFAULTS."""
+def tune(ctx, db, reps: int = 3, log=None, passes: int = 2) -> dict:
+    """Coordinate descent over CANDIDATES from DEFAULTS, repeated while a pass
+    improves (at most `passes` passes: the knobs interact, e.g. the grid size
+    that suits one wavefront per job differs from the multi-wave one)."""
     best = dict(DEFAULTS)
     best_ms = time_opts(ctx, db, best, reps)
     base_ms = best_ms
-    tried = [(dict(best), best_ms)]
-    for knob, values in CANDIDATES.items():
-        for v in values:
-            if best.get(knob) == v:
-                continue
-            cand = dict(best)
-            cand[knob] = v
-            if cand["long_tier_bias"] == 0 and knob == "long_job":
-                continue                      # the split does nothing without a bias
-            if cand["long_tier_bias"] > 0 and cand["long_job"] == 0:
-                cand["long_job"] = CANDIDATES["long_job"][0]
-            if log:
-                log(f"  timing {cand}")
-            ms = time_opts(ctx, db, cand, reps)
-            tried.append((dict(cand), ms))
-            if log:
-                log(f"  {cand} -> {ms:.2f} ms")
-            if ms < best_ms:
-                best, best_ms = cand, ms
+    tried = {tuple(sorted(best.items())): best_ms}
+    for _ in range(passes):
+        start = dict(best)
+        for knob, values in CANDIDATES.items():
+            for v in values:
+                if best.get(knob) == v:
+                    continue
+                cand = dict(best)
+                cand[knob] = v
+                if cand["long_tier_bias"] == 0 and knob == "long_job":
+                    continue                      # the split does nothing without a bias
+                if cand["long_tier_bias"] > 0 and cand["long_job"] == 0:
+                    cand["long_job"] = CANDIDATES["long_job"][0]
+                key = tuple(sorted(cand.items()))
+                if key in tried:
+                    continue
+                if log:
+                    log(f"  timing {cand}")
+                ms = time_opts(ctx, db, cand, reps)
+                tried[key] = ms
+                if log:
+                    log(f"  {cand} -> {ms:.2f} ms")
+                if ms < best_ms:
+                    best, best_ms = cand, ms
+        if best == start:
+            break
     return {"opts": best, "ms": round(best_ms, 3), "default_ms": round(base_ms, 3),
             "candidates": len(tried)}
 
