@@ -22,8 +22,9 @@
 //   s_ff1 / s_flbit / s_bfm                          trim: next range mask
 // An improvement of best costs 3 SALU + 1 VALU out of line; best itself is
 // not tracked in the loop but recovered from bw afterwards.
-// Block transition (every 32 anti-diagonals): 3 window shifts, 3 clamped
-// prefetch loads, 3 v_alignbit, 2 v_xor, 2-4 VALU per score word.
+// Block transition (every 32 anti-diagonals): 2 window shifts, 2 clamped
+// prefetch loads, 3 v_alignbit and a v_cndmask (one A window serves both
+// parities), 2 v_xor, 2-4 VALU per score word.
 //
 // Window edges: an even anti-diagonal may not use lane 0 (wave_shr leaves it
 // without a neighbour) and an odd one may not use lane 63.  Checking after
@@ -122,15 +123,23 @@ XD_FN Win make_win(const AsmView &v, vint off) {
   "v_mov_b32 %[lo" K "], %[nx" K "]\n\t"                            \
   "v_add_u32 %[idx" K "], -4, %[idx" K "]\n\t"
 
-#define XD_WORDS(SW, REV)                                           \
-  "v_alignbit_b32 %[x0], %[hi0], %[lo0], %[sh0]\n\t"                \
-  "v_alignbit_b32 %[x1], %[hi1], %[lo1], %[sh1]\n\t"                \
+// Score words of the next block.  One window of A serves both parities: the
+// other parity's bases start one base (two bits) further along the same two
+// words, which v_alignbit reaches for every lane except those whose window
+// starts at bit 30 (mask m30), where the shifted window is exactly `hi`.
+// XK is the word of the window kept in registers, XD the derived one.
+#define XD_WORDS1(SW, REV, XK, XD)                                  \
+  "v_alignbit_b32 %[" XK "], %[hi0], %[lo0], %[sh0]\n\t"            \
+  "v_alignbit_b32 %[" XD "], %[hi0], %[lo0], %[shd]\n\t"            \
+  "v_cndmask_b32_e64 %[" XD "], %[" XD "], %[hi0], %[m30]\n\t"       \
   "v_alignbit_b32 %[x2], %[hi2], %[lo2], %[sh2]\n\t"                \
   "v_xor_b32 %[x0], %[x0], %[x2]\n\t"                               \
   "v_xor_b32 %[x1], %[x1], %[x2]\n\t"                               \
   REV                                                               \
   SW("SE", "x0")                                                    \
   SW("SO", "x1")
+#define XD_WORDS_FWD(SW, REV) XD_WORDS1(SW, REV, "x0", "x1")
+#define XD_WORDS_BWD(SW, REV) XD_WORDS1(SW, REV, "x1", "x0")
 
 // Cell update and prune of one anti-diagonal (field P of the score word),
 // then its thresholds and survivor ends.  TAG names the step's exits:
@@ -270,13 +279,15 @@ template <bool NARROW, bool UNIT, bool FWD, bool D2>
 XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &jv,
                      const AsmView &av_a, const AsmView &av_b, const Params &P,
                      int32_t &words_e0) {
-  // windows of block e0: A for even and odd anti-diagonals, and B
+  // windows of block e0: A (the parity whose bases start lower in memory:
+  // even forwards, odd backwards; the other parity is derived) and B
   const vint s = lane_index();
   const vint i0 = s + (st.h + e0);
   const vint j0 = splat(e0 - st.h) - s;
-  Win w0 = make_win<FWD>(av_a, FWD ? i0 - 1 : splat(-14) - i0);
-  Win w1 = make_win<FWD>(av_a, FWD ? i0 + 0 : splat(-15) - i0);
+  Win w0 = make_win<FWD>(av_a, FWD ? i0 - 1 : splat(-15) - i0);
   Win w2 = make_win<FWD>(av_b, FWD ? j0 - 1 : splat(-14) - j0);
+  const vint shd = (w0.sh + 2) & 31;
+  const uint64_t m30 = ballot(w0.sh == 30);
   int32_t e0x2 = 2 * e0;
   // the window stays inside the matrix for blocks ending at or before e_lim
   int32_t e_lim = jv.m - (kWave - 1) - st.h;
@@ -294,11 +305,14 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
   const uint32_t *base_a = av_a.base, *base_b = av_b.base;
   int32_t par = st.par;
   int32_t bw = st.bw;
-  int32_t u, t, tv, x0, x1, x2, p0, p1, p2;
+  int32_t u, t, tv, x0, x1, x2, p0, p2;
   // score words of block e0 (the loop rebuilds them at each later block)
   {
-    vint xe = funnel_shr(w0.hi, w0.lo, w0.sh) ^ funnel_shr(w2.hi, w2.lo, w2.sh);
-    vint xo = funnel_shr(w1.hi, w1.lo, w1.sh) ^ funnel_shr(w2.hi, w2.lo, w2.sh);
+    const vint xk = funnel_shr(w0.hi, w0.lo, w0.sh);
+    const vint xd = select(lanes(m30), w0.hi, funnel_shr(w0.hi, w0.lo, shd));
+    const vint xb = funnel_shr(w2.hi, w2.lo, w2.sh);
+    vint xe = (FWD ? xk : xd) ^ xb;
+    vint xo = (FWD ? xd : xk) ^ xb;
     if (!FWD) { xe = bit_reverse(xe); xo = bit_reverse(xo); }
     bd.SE[0] = score_word<NARROW>(xe, P.pat);
     bd.SO[0] = score_word<NARROW>(xo, P.pat);
@@ -306,11 +320,10 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
   // The 32 anti-diagonals of a block are unrolled, so field offsets and
   // anti-diagonal numbers are immediates; entry jumps through a table of
   // branches indexed by the step within the block (pos + par).
-#define XD_ASM_BODY(DIAG, IMP, SW, SHIFTW, REV)                                       \
+#define XD_ASM_BODY(DIAG, IMP, SW, SHIFTW, REV, WORDS)                                \
   asm volatile(                                                                       \
       "s_nop 4\n\t"                                                                   \
       XD_PREFETCH("0", "hi_a", "base_a")                                              \
-      XD_PREFETCH("1", "hi_a", "base_a")                                              \
       XD_PREFETCH("2", "hi_b", "base_b")                                              \
       "s_add_i32 s42, %[pos], %[par]\n\t"                                             \
       "s_lshl_b32 s42, s42, 2\n\t"                                                    \
@@ -329,11 +342,10 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
       "s_cmp_gt_i32 %[e0x2], %[lim2]\n\t"                                             \
       "s_cbranch_scc1 .Lleave_%=\n\t"                                                  \
       "s_waitcnt vmcnt(0)\n\t"                                                        \
-      SHIFTW("0") SHIFTW("1") SHIFTW("2")                                             \
+      SHIFTW("0") SHIFTW("2")                                                         \
       XD_PREFETCH("0", "hi_a", "base_a")                                              \
-      XD_PREFETCH("1", "hi_a", "base_a")                                              \
       XD_PREFETCH("2", "hi_b", "base_b")                                              \
-      XD_WORDS(SW, REV)                                                               \
+      WORDS(SW, REV)                                                                  \
       "s_branch .Le0_%=\n"                                                             \
       XD_ALL_STUBS(IMP)                                                               \
       ".Ldone_%=:\n\t"                                                                 \
@@ -352,15 +364,15 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
       : [E] "+v"(bd.E[0].x), [O] "+v"(bd.O[0].x), [cnt] "+v"(cnt.x), [bw] "+v"(bw),   \
         [SE] "+v"(bd.SE[0].x), [SO] "+v"(bd.SO[0].x),                                 \
         [lo0] "+v"(w0.lo.x), [hi0] "+v"(w0.hi.x), [nx0] "+v"(w0.nx.x), [idx0] "+v"(w0.idx.x), \
-        [lo1] "+v"(w1.lo.x), [hi1] "+v"(w1.hi.x), [nx1] "+v"(w1.nx.x), [idx1] "+v"(w1.idx.x), \
         [lo2] "+v"(w2.lo.x), [hi2] "+v"(w2.hi.x), [nx2] "+v"(w2.nx.x), [idx2] "+v"(w2.idx.x), \
         [u] "=&v"(u), [t] "=&v"(t), [tv] "=&v"(tv), [x0] "=&v"(x0), [x1] "=&v"(x1),   \
-        [x2] "=&v"(x2), [p0] "=&v"(p0), [p1] "=&v"(p1), [p2] "=&v"(p2),               \
+        [x2] "=&v"(x2), [p0] "=&v"(p0), [p2] "=&v"(p2),               \
         [thr] "+s"(st.thr), [bs] "+s"(bs), [bpos] "+s"(bpos),                         \
         [par] "+s"(par), [pos] "+s"(pos), [e0x2] "+s"(e0x2), [range] "+s"(st.range),  \
         [live] "+s"(live), [a] "+s"(a), [f] "+s"(f), [tmp] "+s"(tmp), [inc] "+s"(inc), \
         [status] "+s"(status)                                                         \
-      : [sh0] "v"(w0.sh.x), [sh1] "v"(w1.sh.x), [sh2] "v"(w2.sh.x), [base] "s"(P.base), \
+      : [sh0] "v"(w0.sh.x), [shd] "v"(shd.x), [m30] "s"(m30), [sh2] "v"(w2.sh.x),     \
+        [base] "s"(P.base),                                                           \
         [delta] "s"(P.delta), [ng] "s"(P.neg_gap), [ng1] "s"(ng1), [lim2] "s"(lim2),   \
         [edge] "s"(edge),                                                             \
         [k55] "s"(k55), [pat] "s"(P.pat), [hi_a] "s"(hi_a), [hi_b] "s"(hi_b),          \
@@ -369,23 +381,23 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
 #define XD_REV_NONE ""
 #define XD_REV_BOTH "v_bfrev_b32 %[x0], %[x0]\n\tv_bfrev_b32 %[x1], %[x1]\n\t"
   if (D2) {   // match = 1 and match - mismatch = 2 (e.g. +1/-1/-1)
-    if (FWD) { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_UNIT, XD_SW_D2, XD_SHIFT_FWD, XD_REV_NONE); }
-    else { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_UNIT, XD_SW_D2, XD_SHIFT_BWD, XD_REV_BOTH); }
+    if (FWD) { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_UNIT, XD_SW_D2, XD_SHIFT_FWD, XD_REV_NONE, XD_WORDS_FWD); }
+    else { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_UNIT, XD_SW_D2, XD_SHIFT_BWD, XD_REV_BOTH, XD_WORDS_BWD); }
   } else if (FWD) {
     if (NARROW) {
-      if (UNIT) { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_UNIT, XD_SW_NARROW, XD_SHIFT_FWD, XD_REV_NONE); }
-      else { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_LOOP, XD_SW_NARROW, XD_SHIFT_FWD, XD_REV_NONE); }
+      if (UNIT) { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_UNIT, XD_SW_NARROW, XD_SHIFT_FWD, XD_REV_NONE, XD_WORDS_FWD); }
+      else { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_LOOP, XD_SW_NARROW, XD_SHIFT_FWD, XD_REV_NONE, XD_WORDS_FWD); }
     } else {
-      if (UNIT) { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMP_UNIT, XD_SW_WIDE, XD_SHIFT_FWD, XD_REV_NONE); }
-      else { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMP_LOOP, XD_SW_WIDE, XD_SHIFT_FWD, XD_REV_NONE); }
+      if (UNIT) { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMP_UNIT, XD_SW_WIDE, XD_SHIFT_FWD, XD_REV_NONE, XD_WORDS_FWD); }
+      else { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMP_LOOP, XD_SW_WIDE, XD_SHIFT_FWD, XD_REV_NONE, XD_WORDS_FWD); }
     }
   } else {
     if (NARROW) {
-      if (UNIT) { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_UNIT, XD_SW_NARROW, XD_SHIFT_BWD, XD_REV_BOTH); }
-      else { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_LOOP, XD_SW_NARROW, XD_SHIFT_BWD, XD_REV_BOTH); }
+      if (UNIT) { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_UNIT, XD_SW_NARROW, XD_SHIFT_BWD, XD_REV_BOTH, XD_WORDS_BWD); }
+      else { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_LOOP, XD_SW_NARROW, XD_SHIFT_BWD, XD_REV_BOTH, XD_WORDS_BWD); }
     } else {
-      if (UNIT) { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMP_UNIT, XD_SW_WIDE, XD_SHIFT_BWD, XD_REV_BOTH); }
-      else { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMP_LOOP, XD_SW_WIDE, XD_SHIFT_BWD, XD_REV_BOTH); }
+      if (UNIT) { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMP_UNIT, XD_SW_WIDE, XD_SHIFT_BWD, XD_REV_BOTH, XD_WORDS_BWD); }
+      else { XD_ASM_BODY(XD_DIAG_WIDE, XD_IMP_LOOP, XD_SW_WIDE, XD_SHIFT_BWD, XD_REV_BOTH, XD_WORDS_BWD); }
     }
   }
 #undef XD_REV_NONE
