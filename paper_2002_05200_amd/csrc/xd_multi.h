@@ -161,7 +161,18 @@ XD_FN bool mw_step(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w, int 
       }
     }
     vint vmx = splat(kNeg);
-    if constexpr (PAR == 0) {
+    bool chained = false;
+#ifndef XD_EMULATION
+    if constexpr (NARROW) {
+      if (P.impl == 0) {   // the same chain as generated assembly
+        WChain<C, PAR>::run(cur, prv, sw, uniform(pos), uniform(thr), uniform(P.base),
+                            uniform(rlo), uniform(rhi), carry, vmx);
+        chained = true;
+      }
+    }
+#endif
+    if (chained) {
+    } else if constexpr (PAR == 0) {
       switch (rlo) {
 #define XD_MW_UP(R)                                                                          \
   case R:                                                                                    \

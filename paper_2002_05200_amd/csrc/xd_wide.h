@@ -19,6 +19,9 @@
 #pragma once
 
 #include "xd_extend.h"
+#ifndef XD_EMULATION
+#include "xd_wchain_asm.h"
+#endif
 
 namespace xd {
 
@@ -209,7 +212,18 @@ XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Par
       }
     }
   }
-  if constexpr (PAR == 0) {   // upwards from rlo
+  bool chained = false;
+#ifndef XD_EMULATION
+  if constexpr (NARROW) {
+    if (P.impl == 0) {   // the same chain as generated assembly
+      WChain<C, PAR>::run(cur, prv, sw, uniform(pos), uniform(thr), uniform(P.base),
+                          uniform(rlo), uniform(rhi), carry, vmx);
+      chained = true;
+    }
+  }
+#endif
+  if (chained) {
+  } else if constexpr (PAR == 0) {   // upwards from rlo
     switch (rlo) {
 #define XD_SPAN_UP(R)                                                          \
   case R:                                                                      \
