@@ -211,6 +211,50 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job *__restrict__ jobs,
   }
 }
 
+// Orders the jobs escalated into `tier` by the anti-diagonals they have left
+// (m + n less the one they resume at), longest first, into `out`: a counting
+// sort in the planning's cost buckets by one workgroup.  The tier then starts
+// the longest remainders first, as planning orders whole jobs (longest
+// processing time first), instead of in the order the narrower tier happened
+// to give them up.  The order within a bucket is unspecified; no result
+// depends on it.
+constexpr int kSortBlock = 1024;
+__global__ __launch_bounds__(kSortBlock) void k_esc_sort(const Job *__restrict__ jobs,
+                                                         const int32_t *__restrict__ in,
+                                                         int32_t *__restrict__ out,
+                                                         const int32_t *__restrict__ counters,
+                                                         int tier, Params P) {
+  __shared__ int32_t start[kCostBuckets];
+  const int32_t n = counters[kEsc + tier];
+  for (int b = threadIdx.x; b < kCostBuckets; b += blockDim.x) start[b] = 0;
+  __syncthreads();
+  auto bin = [&](int32_t j) {
+    const Job jb = jobs[j];
+    int32_t d = 0;
+    if (P.save_pool) {
+      const int32_t off = P.job_save[j];
+      if (off >= 0) d = P.save_pool[off + kSvD];
+    }
+    const int32_t rem = jb.m + jb.n - d;
+    return kCostBuckets - 1 - cost_bucket((uint32_t)(rem > 0 ? rem : 0));
+  };
+  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&start[bin(in[i])], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {   // counts -> first positions
+    int32_t acc = 0;
+    for (int b = 0; b < kCostBuckets; ++b) {
+      const int32_t k = start[b];
+      start[b] = acc;
+      acc += k;
+    }
+  }
+  __syncthreads();
+  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const int32_t j = in[i];
+    out[atomicAdd(&start[bin(j)], 1)] = j;
+  }
+}
+
 __global__ void k_combine(const xd_pair *__restrict__ pairs, int64_t n_pairs,
                           const int32_t *__restrict__ pair_status, const JobOut *__restrict__ outs,
                           const uint32_t *__restrict__ A, const uint32_t *__restrict__ B,
@@ -280,6 +324,7 @@ struct xd_ctx {
   int32_t *bins = nullptr;       // kBins counts, kBins cursors, kBins offsets
   int32_t *order = nullptr;
   int32_t *esc = nullptr;        // kLists + 1 lists of 2 * cap_pairs entries: escalations
+  int32_t *esc_sorted = nullptr; // one more: a tier's escalations, longest remainder first
                                  // into each tier, then the spill tier's second pass
   int32_t *counters = nullptr;   // kCounters
   unsigned long long *stats = nullptr;  // kStats
@@ -313,7 +358,7 @@ xd_status ensure_capacity(xd_ctx *c, int64_t n_pairs) {
   const size_t o_jsave = off; off = align_up(off + sizeof(int32_t) * nj);
   const size_t o_bins = off; off = align_up(off + sizeof(int32_t) * 3 * kBins);
   const size_t o_order = off; off = align_up(off + sizeof(int32_t) * nj);
-  const size_t o_esc = off; off = align_up(off + sizeof(int32_t) * nj * (kLists + 1));
+  const size_t o_esc = off; off = align_up(off + sizeof(int32_t) * nj * (kLists + 2));
   const size_t o_cnt = off; off = align_up(off + sizeof(int32_t) * kCounters);
   const size_t o_stats = off; off = align_up(off + sizeof(unsigned long long) * kStats);
   const size_t o_dummy = off; off = align_up(off + 64);
@@ -353,6 +398,7 @@ xd_status ensure_capacity(xd_ctx *c, int64_t n_pairs) {
   c->bins = (int32_t *)(b + o_bins);
   c->order = (int32_t *)(b + o_order);
   c->esc = (int32_t *)(b + o_esc);
+  c->esc_sorted = c->esc + (kLists + 1) * nj;
   c->counters = (int32_t *)(b + o_cnt);
   c->stats = (unsigned long long *)(b + o_stats);
   c->dummy = (uint32_t *)(b + o_dummy);
@@ -372,6 +418,13 @@ hipError_t launch_tier(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_
   q.next_esc = c->esc + (tier + 1) * stride;
   q.tier = tier;
   int32_t *head = persistent ? c->counters + kHead + tier : nullptr;
+  if (tier > 0) {   // escalated jobs, longest remainder first
+    hipLaunchKernelGGL(k_esc_sort, dim3(1), dim3(kSortBlock), 0, s, c->jobs, q.esc,
+                       c->esc_sorted, c->counters, tier, P);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    q.esc = c->esc_sorted;
+  }
   if constexpr (C >= 8) {
     if (multi_wave != 0) {   // NW wavefronts per job, C / NW registers each
       auto launch_mw = [&](auto nw) {
@@ -492,10 +545,13 @@ xd_status enqueue(xd_ctx *c, hipStream_t s, const Launch &L, bool prof) {
   {   // bands wider than one wavefront: a workgroup per job, then global memory
     TierQueue q;
     q.order = c->order;
-    q.esc = c->esc + kTiers * stride;
     q.counters = c->counters;
     q.next_esc = nullptr;
     q.tier = kTiers;
+    hipLaunchKernelGGL(k_esc_sort, dim3(1), dim3(kSortBlock), 0, s, c->jobs,
+                       c->esc + kTiers * stride, c->esc_sorted, c->counters, kTiers, P);
+    XD_HIP(hipGetLastError());
+    q.esc = c->esc_sorted;
     int32_t *huge_list = c->esc + kLists * stride;
     if (narrow)
       hipLaunchKernelGGL((k_extend_mw<16, 8, true>), dim3((unsigned)c->num_cu), dim3(64 * 16), 0, s,

@@ -4,7 +4,7 @@
 // the latter in logarithmic cost buckets (four per octave), by a counting
 // sort.  Tier t works through its segment of that order, then through the
 // jobs escalated into it from tier t - 1 (their band outgrew the narrower
-// window).
+// window), those ordered by the anti-diagonals they have left.
 #pragma once
 
 #include <hip/hip_runtime.h>
