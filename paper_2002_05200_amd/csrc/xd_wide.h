@@ -523,18 +523,18 @@ XD_FN bool wrestore(WBand<C> &bd, WScalars &st, const Params &P, int32_t j) {
   const int32_t off = P.job_save[j];
   if (off < 0) return false;
   const int32_t *sv = P.save_pool + off;
-  const int32_t cs = sv[kSvC];
+  const int32_t cs = uniform(sv[kSvC]);
   constexpr int S = kWave * C;
   if (cs >= C) return false;
   const int32_t ss = kWave * cs;
   const int32_t shift = (S - ss) / 2;
-  st.d = sv[kSvD];
-  st.lo = sv[kSvLo] + shift;
-  st.hi = sv[kSvHi] + shift;
-  st.h = sv[kSvH] - shift;
-  st.best = sv[kSvBest]; st.bi = sv[kSvBi]; st.bj = sv[kSvBj];
-  st.bw = sv[kSvBw]; st.thr = sv[kSvThr];
-  st.cells = (uint64_t)(uint32_t)sv[kSvCellsLo] | ((uint64_t)(uint32_t)sv[kSvCellsHi] << 32);
+  st.d = uniform(sv[kSvD]);
+  st.lo = uniform(sv[kSvLo]) + shift;
+  st.hi = uniform(sv[kSvHi]) + shift;
+  st.h = uniform(sv[kSvH]) - shift;
+  st.best = uniform(sv[kSvBest]); st.bi = uniform(sv[kSvBi]); st.bj = uniform(sv[kSvBj]);
+  st.bw = uniform(sv[kSvBw]); st.thr = uniform(sv[kSvThr]);
+  st.cells = (uint64_t)(uint32_t)uniform(sv[kSvCellsLo]) | ((uint64_t)(uint32_t)uniform(sv[kSvCellsHi]) << 32);
   st.cells_blk = 0;
   const vint l = lane_index();
 #pragma unroll
