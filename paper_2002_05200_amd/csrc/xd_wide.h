@@ -84,37 +84,16 @@ XD_FN void wbuild(WBand<C> &bd, WScalars &st, int32_t e0, int32_t r0, int32_t r1
   st.w_hi = r1;
 }
 
-// Cell update of register R of the span (no range clipping; see wstep).
-// nb_below / nb_above: the previous anti-diagonal's value in the slot just
-// below register 0 / just above register C-1 (-inf at the window's edges; a
-// neighbouring wave's edge slot in the multi-wave tier).
-template <int C, bool NARROW, int PAR, int R>
-XD_FN void wcell(vint *cur, const vint *prv, const vint *sw, int pos, int32_t thr, int32_t bw,
-                 uint64_t &imp, const Params &P, int32_t nb_below = kNeg,
-                 int32_t nb_above = kNeg) {
-  vint t;
-  if (PAR == 0) {   // even d: predecessors in slots s-1 and s
-    const vint own = rot_prev(prv[R]);
-    const vint below = R > 0 ? rot_prev(prv[R > 0 ? R - 1 : 0]) : splat(nb_below);
-    t = select(lanes(1ull), below, own);
-  } else {          // odd d: predecessors in slots s and s+1
-    const vint own = rot_next(prv[R]);
-    const vint above = R < C - 1 ? rot_next(prv[R < C - 1 ? R + 1 : R]) : splat(nb_above);
-    t = select(lanes(1ull << 63), above, own);
-  }
-  const vint v = vmax3(diag_term<NARROW>(cur[R], sw[R], pos, P), prv[R], t);
-  cur[R] = select(v >= thr, v, kNeg);
-  imp |= ballot(cur[R] > bw);
-}
-
-// The same cell update along a chain of registers that carries the rotated
-// neighbour register: even anti-diagonals walk the span upwards and odd ones
-// downwards, so each register is rotated once.  `carry` holds the rotation
-// of the register walked just before (-inf at the chain's start: that lane's
-// neighbour slot lies outside the previous anti-diagonal's survivors, and
-// every slot outside them holds -inf).
-// The improvement test is deferred: a running lane-wise maximum over the
-// chain is compared with bw once afterwards.
+// Cell update of register R of the span (no range clipping; see wstep),
+// along a chain of registers that carries the rotated neighbour register:
+// even anti-diagonals walk the span upwards and odd ones downwards, so each
+// register is rotated once.  `carry` holds the rotation of the register
+// walked just before; at the chain's start it is -inf (that lane's neighbour
+// slot lies outside the previous anti-diagonal's survivors, and every slot
+// outside them holds -inf) unless the range was clipped to the matrix there,
+// or is the adjacent wave's edge value in the multi-wave tier.  The
+// improvement test is deferred: a running lane-wise maximum over the chain
+// is compared with bw once afterwards.
 template <int C, bool NARROW, int PAR, int R>
 XD_FN void wcell_chain(vint *cur, const vint *prv, const vint *sw, int pos, int32_t thr,
                        vint &vmx, vint &carry, const Params &P) {
