@@ -1,6 +1,6 @@
 // xd_wide.h -- one X-drop extension per wavefront for bands wider than one
-// register: C registers per lane, the S = 64 C diagonal slots interleaved
-// across registers (slot s lives in lane s mod 64 of register s / 64).
+// register: C registers per lane holding the S = 64 C diagonal slots in runs
+// of 64 (slot s lives in lane s mod 64 of register s / 64).
 //
 // Same arithmetic as xd_extend.h (Section III-A recurrence in the gap-free W
 // form, pruning against the best of the previous anti-diagonals, next range
