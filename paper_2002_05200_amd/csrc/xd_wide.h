@@ -286,12 +286,41 @@ XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Par
     // match = 1: best rises by exactly 1 and the new best cells are the
     // lanes above bw, so the first register holding one (after clipping)
     // gives both the confirmation and the best cell
+    // (for up to 16 registers a fall-through run entered at rlo that stops
+    // at the first hit; the 32-register tier measured faster with the
+    // unrolled loop, whose code its register allocation handles better)
     int sbest = -1;
+    const int32_t bw0 = st.bw;
+    if constexpr (C >= 32) {
 #pragma unroll
-    for (int r = 0; r < C; ++r) {
-      if (sbest >= 0 || r < rlo || r > rhi) continue;
-      const uint64_t m = ballot(cur[r] > st.bw);
-      if (m != 0) sbest = 64 * r + ctz64(m);
+      for (int r = 0; r < C; ++r) {
+        if (sbest >= 0 || r < rlo || r > rhi) continue;
+        const uint64_t m = ballot(cur[r] > bw0);
+        if (m != 0) sbest = 64 * r + ctz64(m);
+      }
+    } else switch (rlo) {
+#define XD_FIRST_BEST(R)                                         \
+  case R:                                                        \
+    if constexpr (R < C) {                                       \
+      const uint64_t m = ballot(cur[R] > bw0);                   \
+      if (m != 0) {                                              \
+        sbest = 64 * R + ctz64(m);                               \
+        break;                                                   \
+      }                                                          \
+      if (rhi == R) break;                                       \
+    }                                                            \
+    [[fallthrough]];
+      XD_FIRST_BEST(0) XD_FIRST_BEST(1) XD_FIRST_BEST(2) XD_FIRST_BEST(3) XD_FIRST_BEST(4)
+      XD_FIRST_BEST(5) XD_FIRST_BEST(6) XD_FIRST_BEST(7) XD_FIRST_BEST(8) XD_FIRST_BEST(9)
+      XD_FIRST_BEST(10) XD_FIRST_BEST(11) XD_FIRST_BEST(12) XD_FIRST_BEST(13)
+      XD_FIRST_BEST(14) XD_FIRST_BEST(15) XD_FIRST_BEST(16) XD_FIRST_BEST(17)
+      XD_FIRST_BEST(18) XD_FIRST_BEST(19) XD_FIRST_BEST(20) XD_FIRST_BEST(21)
+      XD_FIRST_BEST(22) XD_FIRST_BEST(23) XD_FIRST_BEST(24) XD_FIRST_BEST(25)
+      XD_FIRST_BEST(26) XD_FIRST_BEST(27) XD_FIRST_BEST(28) XD_FIRST_BEST(29)
+      XD_FIRST_BEST(30) XD_FIRST_BEST(31)
+#undef XD_FIRST_BEST
+      default:
+        break;
     }
     imp = 0;
     if (sbest >= 0) {
