@@ -553,14 +553,17 @@ xd_status enqueue(xd_ctx *c, hipStream_t s, const Launch &L, bool prof) {
     XD_HIP(hipGetLastError());
     q.esc = c->esc_sorted;
     int32_t *huge_list = c->esc + kLists * stride;
+    // 8,192 slots: 8 wavefronts of 16 registers (measured faster than 16 of 8:
+    // fewer waves take part in each anti-diagonal's barrier and reduction)
+    constexpr int kHugeNW = 8, kHugeC = 16;
     if (narrow)
-      hipLaunchKernelGGL((k_extend_mw<16, 8, true>), dim3((unsigned)c->num_cu), dim3(64 * 16), 0, s,
-                         c->jobs, q, c->counters + kHead + kTiers, c->outs, c->stats, P,
-                         huge_list, c->counters + kHugeCount);
+      hipLaunchKernelGGL((k_extend_mw<kHugeNW, kHugeC, true>), dim3((unsigned)c->num_cu),
+                         dim3(64 * kHugeNW), 0, s, c->jobs, q, c->counters + kHead + kTiers,
+                         c->outs, c->stats, P, huge_list, c->counters + kHugeCount);
     else
-      hipLaunchKernelGGL((k_extend_mw<16, 8, false>), dim3((unsigned)c->num_cu), dim3(64 * 16), 0, s,
-                         c->jobs, q, c->counters + kHead + kTiers, c->outs, c->stats, P,
-                         huge_list, c->counters + kHugeCount);
+      hipLaunchKernelGGL((k_extend_mw<kHugeNW, kHugeC, false>), dim3((unsigned)c->num_cu),
+                         dim3(64 * kHugeNW), 0, s, c->jobs, q, c->counters + kHead + kTiers,
+                         c->outs, c->stats, P, huge_list, c->counters + kHugeCount);
     XD_HIP(hipGetLastError());
     if (spill_launch(&c->spill, s, c->jobs, q, c->counters + kHugeHead, huge_list,
                      c->counters + kHugeCount, c->outs, c->stats, P) != XD_OK)

@@ -2,8 +2,8 @@
 // wider than one wavefront's registers hold (more than 2,046 cells).
 //
 // NW wavefronts each own a chunk of C registers (64 C slots, in runs of 64
-// consecutive slots per register as in xd_wide.h), so the
-// window is (64 * C * NW) = 64 C NW diagonal slots.  Per anti-diagonal
+// consecutive slots per register as in xd_wide.h), so the window is 64 C NW
+// diagonal slots.  Per anti-diagonal
 // every wave updates the part of the computed range that falls in its chunk
 // with the single-wave step, clips its edge registers, and posts to LDS
 //   * its chunk's first and last slot values (the neighbours the adjacent
