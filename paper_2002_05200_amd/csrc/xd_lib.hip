@@ -191,8 +191,10 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job *__restrict__ jobs,
       } else {
         o = extend_job_wide<2, NARROW, false>(job, P, j);
       }
+    } else if (NARROW && P.impl == 0) {
+      o = extend_job_wide<C, NARROW, true>(job, P, j);
     } else {
-      o = extend_job_wide<C, NARROW>(job, P, j);
+      o = extend_job_wide<C, NARROW, false>(job, P, j);
     }
     if (lane_id() == 0) {
       if (o.status == kJobWider) {

@@ -104,7 +104,7 @@ XD_FN void mw_post_edges(const WBand<C> &bd, MwShared<NW, C> &sh, int w) {
 }
 
 // Anti-diagonal st.d (parity PAR).  Returns false once the extension ended.
-template <int NW, int C, bool NARROW, int PAR>
+template <int NW, int C, bool NARROW, int PAR, bool ASM>
 XD_FN bool mw_step(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w, int q,
                    const JobView &jv, const Params &P) {
   vint *cur = PAR ? bd.O : bd.E;
@@ -161,19 +161,28 @@ XD_FN bool mw_step(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w, int 
       }
     }
     vint vmx = splat(kNeg);
-    bool chained = false;
+    uint64_t live_lo, live_hi;
 #ifndef XD_EMULATION
-    if constexpr (NARROW) {
-      if (P.impl == 0) {   // the same chain as generated assembly
-        WChain<C, PAR>::run(cur, prv, sw, uniform(pos), uniform(thr), uniform(P.base),
-                            uniform(rlo), uniform(rhi), carry, vmx);
-        chained = true;
-      }
-    }
+    if constexpr (ASM && NARROW) {
+      // the same chain as generated assembly, with the chunk's edge
+      // registers clipped inside it
+      const int ucl = uniform(cl), uch = uniform(ch);
+      const int urlo = uniform(rlo), urhi = uniform(rhi);
+      const uint64_t lo_mask = ~0ull << (ucl & 63);
+      const uint64_t hi_mask = ~0ull >> (63 - (uch & 63));
+      const uint64_t mf =
+          urlo == urhi ? (lo_mask & hi_mask) : (PAR == 0 ? lo_mask : hi_mask);
+      const uint64_t ml = PAR == 0 ? hi_mask : lo_mask;
+      uint64_t lf, ll;
+      WChain<C, PAR>::run(cur, prv, sw, uniform(pos), uniform(thr), uniform(P.base), urlo,
+                          urhi, carry, vmx, mf, ml, lf, ll);
+      live_lo = PAR == 0 ? lf : ll;
+      live_hi = PAR == 0 ? ll : lf;
+    } else
 #endif
-    if (chained) {
-    } else if constexpr (PAR == 0) {
-      switch (rlo) {
+    {
+      if constexpr (PAR == 0) {
+        switch (rlo) {
 #define XD_MW_UP(R)                                                                          \
   case R:                                                                                    \
     if constexpr (R < C) {                                                                   \
@@ -181,15 +190,15 @@ XD_FN bool mw_step(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w, int 
       if (rhi == R) break;                                                                   \
     }                                                                                        \
     [[fallthrough]];
-        XD_MW_UP(0) XD_MW_UP(1) XD_MW_UP(2) XD_MW_UP(3) XD_MW_UP(4) XD_MW_UP(5) XD_MW_UP(6)
-        XD_MW_UP(7) XD_MW_UP(8) XD_MW_UP(9) XD_MW_UP(10) XD_MW_UP(11) XD_MW_UP(12)
-        XD_MW_UP(13) XD_MW_UP(14) XD_MW_UP(15)
+          XD_MW_UP(0) XD_MW_UP(1) XD_MW_UP(2) XD_MW_UP(3) XD_MW_UP(4) XD_MW_UP(5) XD_MW_UP(6)
+          XD_MW_UP(7) XD_MW_UP(8) XD_MW_UP(9) XD_MW_UP(10) XD_MW_UP(11) XD_MW_UP(12)
+          XD_MW_UP(13) XD_MW_UP(14) XD_MW_UP(15)
 #undef XD_MW_UP
-        default:
-          break;
-      }
-    } else {
-      switch (rhi) {
+          default:
+            break;
+        }
+      } else {
+        switch (rhi) {
 #define XD_MW_DOWN(R)                                                                         \
   case 15 - R:                                                                                \
     if constexpr (15 - R < C) {                                                               \
@@ -198,24 +207,24 @@ XD_FN bool mw_step(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w, int 
       if (rlo == 15 - R) break;                                                               \
     }                                                                                         \
     [[fallthrough]];
-        XD_MW_DOWN(0) XD_MW_DOWN(1) XD_MW_DOWN(2) XD_MW_DOWN(3) XD_MW_DOWN(4) XD_MW_DOWN(5)
-        XD_MW_DOWN(6) XD_MW_DOWN(7) XD_MW_DOWN(8) XD_MW_DOWN(9) XD_MW_DOWN(10) XD_MW_DOWN(11)
-        XD_MW_DOWN(12) XD_MW_DOWN(13) XD_MW_DOWN(14) XD_MW_DOWN(15)
+          XD_MW_DOWN(0) XD_MW_DOWN(1) XD_MW_DOWN(2) XD_MW_DOWN(3) XD_MW_DOWN(4) XD_MW_DOWN(5)
+          XD_MW_DOWN(6) XD_MW_DOWN(7) XD_MW_DOWN(8) XD_MW_DOWN(9) XD_MW_DOWN(10) XD_MW_DOWN(11)
+          XD_MW_DOWN(12) XD_MW_DOWN(13) XD_MW_DOWN(14) XD_MW_DOWN(15)
 #undef XD_MW_DOWN
-        default:
-          break;
+          default:
+            break;
+        }
+      }
+      const uint64_t lo_mask = ~0ull << (cl & 63);
+      const uint64_t hi_mask = ~0ull >> (63 - (ch & 63));
+      if (rlo == rhi) {
+        live_lo = live_hi = wclip_at<C>(cur, rlo, lo_mask & hi_mask);
+      } else {
+        live_lo = wclip_at<C>(cur, rlo, lo_mask);
+        live_hi = wclip_at<C>(cur, rhi, hi_mask);
       }
     }
     const uint64_t imp = ballot(vmx > bw);
-    const uint64_t lo_mask = ~0ull << (cl & 63);
-    const uint64_t hi_mask = ~0ull >> (63 - (ch & 63));
-    uint64_t live_lo, live_hi;
-    if (rlo == rhi) {
-      live_lo = live_hi = wclip_at<C>(cur, rlo, lo_mask & hi_mask);
-    } else {
-      live_lo = wclip_at<C>(cur, rlo, lo_mask);
-      live_hi = wclip_at<C>(cur, rhi, hi_mask);
-    }
     if (live_lo != 0) {
       first = base + 64 * rlo + ctz64(live_lo);
     } else {
@@ -425,7 +434,7 @@ XD_FN void mw_save(const WBand<C> &bd, const MwScalars &st, MwShared<NW, C> &sh,
 
 // Whole extension of job j by the workgroup.  kJobWider when the band
 // outgrows the window.
-template <int NW, int C, bool NARROW>
+template <int NW, int C, bool NARROW, bool ASM>
 XD_FN JobOut mw_extend(const Job &job, const Params &P, int32_t j, MwShared<NW, C> &sh, int w) {
   JobOut out;
   out.best = 0; out.bi = 0; out.bj = 0; out.status = kJobOk; out.cells = 0;
@@ -481,13 +490,13 @@ XD_FN JobOut mw_extend(const Job &job, const Params &P, int32_t j, MwShared<NW, 
         st.w_lo = 1;
         st.w_hi = 0;
       }
-      if (!mw_step<NW, C, NARROW, 0>(bd, st, sh, w, e - e0, jv, P)) break;   // d = 2e
+      if (!mw_step<NW, C, NARROW, 0, ASM>(bd, st, sh, w, e - e0, jv, P)) break;   // d = 2e
     }
     odd = false;
     if (st.lo < 1 || st.hi > (64 * C * NW) - 2) {
       if (!mw_recenter<NW, C>(bd, st, sh, w)) { ok = false; break; }
     }
-    if (!mw_step<NW, C, NARROW, 1>(bd, st, sh, w, e - e0, jv, P)) break;     // d = 2e + 1
+    if (!mw_step<NW, C, NARROW, 1, ASM>(bd, st, sh, w, e - e0, jv, P)) break;     // d = 2e + 1
     ++e;
   }
   if (!ok) {
@@ -528,7 +537,9 @@ __global__ __launch_bounds__(64 * NW) void k_extend_mw(const Job *__restrict__ j
     if (widx >= count) break;
     const int32_t j = tier_job(q, widx, n_init, n_esc);
     const Job job = jobs[j];
-    const JobOut o = mw_extend<NW, C, NARROW>(job, P, j, sh, (int)(threadIdx.x >> 6));
+    const int w = (int)(threadIdx.x >> 6);
+    const JobOut o = NARROW && P.impl == 0 ? mw_extend<NW, C, NARROW, true>(job, P, j, sh, w)
+                                           : mw_extend<NW, C, NARROW, false>(job, P, j, sh, w);
     if (threadIdx.x == 0) {
       if (o.status == kJobWider) {
         overflow[atomicAdd(overflow_count, 1)] = j;

@@ -148,7 +148,7 @@ XD_FN uint64_t wclip_at(vint *cur, int r, uint64_t mask) {
 // clipping is applied afterwards to the two edge registers only.  Lanes
 // outside the range in those registers may briefly hold values above best,
 // so an improvement seen during the update is confirmed after clipping.
-template <int C, bool NARROW, int PAR>
+template <int C, bool NARROW, int PAR, bool ASM>
 XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Params &P) {
   vint *cur = PAR ? bd.O : bd.E;          // d - 2 on entry, d on exit
   const vint *prv = PAR ? bd.E : bd.O;    // d - 1
@@ -191,39 +191,46 @@ XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Par
       }
     }
   }
-  bool chained = false;
+  const uint64_t lo_mask = ~0ull << (st.lo & 63);
+  const uint64_t hi_mask = ~0ull >> (63 - (st.hi & 63));
+  uint64_t live_lo, live_hi;
 #ifndef XD_EMULATION
-  if constexpr (NARROW) {
-    if (P.impl == 0) {   // the same chain as generated assembly
-      WChain<C, PAR>::run(cur, prv, sw, uniform(pos), uniform(thr), uniform(P.base),
-                          uniform(rlo), uniform(rhi), carry, vmx);
-      chained = true;
-    }
-  }
+  if constexpr (ASM && NARROW) {
+    // the same chain as generated assembly, with the edge registers clipped
+    // to the range inside it (the entry register is rlo going up, rhi going
+    // down)
+    const uint64_t mf = rlo == rhi ? (lo_mask & hi_mask) : (PAR == 0 ? lo_mask : hi_mask);
+    const uint64_t ml = PAR == 0 ? hi_mask : lo_mask;
+    uint64_t lf, ll;
+    WChain<C, PAR>::run(cur, prv, sw, uniform(pos), uniform(thr), uniform(P.base),
+                        uniform(rlo), uniform(rhi), carry, vmx, mf, ml, lf, ll);
+    live_lo = PAR == 0 ? lf : ll;
+    live_hi = PAR == 0 ? ll : lf;
+  } else
 #endif
-  if (chained) {
-  } else if constexpr (PAR == 0) {   // upwards from rlo
-    switch (rlo) {
+  {
+    if constexpr (PAR == 0) {   // upwards from rlo
+      switch (rlo) {
 #define XD_SPAN_UP(R)                                                          \
   case R:                                                                      \
     if constexpr (R < C) {                                                     \
       wcell_chain<C, NARROW, 0, R>(cur, prv, sw, pos, thr, vmx, carry, P);     \
       if (rhi == R) break;                                                     \
     }                                                                          \
-    [[fallthrough]];
-      XD_SPAN_UP(0) XD_SPAN_UP(1) XD_SPAN_UP(2) XD_SPAN_UP(3) XD_SPAN_UP(4)
-      XD_SPAN_UP(5) XD_SPAN_UP(6) XD_SPAN_UP(7) XD_SPAN_UP(8) XD_SPAN_UP(9)
-      XD_SPAN_UP(10) XD_SPAN_UP(11) XD_SPAN_UP(12) XD_SPAN_UP(13) XD_SPAN_UP(14)
-      XD_SPAN_UP(15) XD_SPAN_UP(16) XD_SPAN_UP(17) XD_SPAN_UP(18) XD_SPAN_UP(19)
-      XD_SPAN_UP(20) XD_SPAN_UP(21) XD_SPAN_UP(22) XD_SPAN_UP(23) XD_SPAN_UP(24)
-      XD_SPAN_UP(25) XD_SPAN_UP(26) XD_SPAN_UP(27) XD_SPAN_UP(28) XD_SPAN_UP(29)
-      XD_SPAN_UP(30) XD_SPAN_UP(31)
+      [[fallthrough]];
+        XD_SPAN_UP(0) XD_SPAN_UP(1) XD_SPAN_UP(2) XD_SPAN_UP(3) XD_SPAN_UP(4)
+        XD_SPAN_UP(5) XD_SPAN_UP(6) XD_SPAN_UP(7) XD_SPAN_UP(8) XD_SPAN_UP(9)
+        XD_SPAN_UP(10) XD_SPAN_UP(11) XD_SPAN_UP(12) XD_SPAN_UP(13) XD_SPAN_UP(14)
+        XD_SPAN_UP(15) XD_SPAN_UP(16) XD_SPAN_UP(17) XD_SPAN_UP(18) XD_SPAN_UP(19)
+        XD_SPAN_UP(20) XD_SPAN_UP(21) XD_SPAN_UP(22) XD_SPAN_UP(23) XD_SPAN_UP(24)
+        XD_SPAN_UP(25) XD_SPAN_UP(26) XD_SPAN_UP(27) XD_SPAN_UP(28) XD_SPAN_UP(29)
+        XD_SPAN_UP(30) XD_SPAN_UP(31)
 #undef XD_SPAN_UP
-      default:
-        break;
-    }
-  } else {                    // downwards from rhi
-    switch (rhi) {
+        default:
+          break;
+      }
+    } else {                    // downwards from rhi
+      switch (rhi) {
 #define XD_SPAN_DOWN(R)                                                               \
   case 31 - R:                                                                        \
     if constexpr (31 - R < C) {                                                       \
@@ -231,30 +238,30 @@ XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Par
                                                             carry, P);                \
       if (rlo == 31 - R) break;                                                       \
     }                                                                                 \
-    [[fallthrough]];
-      XD_SPAN_DOWN(0) XD_SPAN_DOWN(1) XD_SPAN_DOWN(2) XD_SPAN_DOWN(3) XD_SPAN_DOWN(4)
-      XD_SPAN_DOWN(5) XD_SPAN_DOWN(6) XD_SPAN_DOWN(7) XD_SPAN_DOWN(8) XD_SPAN_DOWN(9)
-      XD_SPAN_DOWN(10) XD_SPAN_DOWN(11) XD_SPAN_DOWN(12) XD_SPAN_DOWN(13) XD_SPAN_DOWN(14)
-      XD_SPAN_DOWN(15) XD_SPAN_DOWN(16) XD_SPAN_DOWN(17) XD_SPAN_DOWN(18) XD_SPAN_DOWN(19)
-      XD_SPAN_DOWN(20) XD_SPAN_DOWN(21) XD_SPAN_DOWN(22) XD_SPAN_DOWN(23) XD_SPAN_DOWN(24)
-      XD_SPAN_DOWN(25) XD_SPAN_DOWN(26) XD_SPAN_DOWN(27) XD_SPAN_DOWN(28) XD_SPAN_DOWN(29)
-      XD_SPAN_DOWN(30) XD_SPAN_DOWN(31)
+      [[fallthrough]];
+        XD_SPAN_DOWN(0) XD_SPAN_DOWN(1) XD_SPAN_DOWN(2) XD_SPAN_DOWN(3) XD_SPAN_DOWN(4)
+        XD_SPAN_DOWN(5) XD_SPAN_DOWN(6) XD_SPAN_DOWN(7) XD_SPAN_DOWN(8) XD_SPAN_DOWN(9)
+        XD_SPAN_DOWN(10) XD_SPAN_DOWN(11) XD_SPAN_DOWN(12) XD_SPAN_DOWN(13) XD_SPAN_DOWN(14)
+        XD_SPAN_DOWN(15) XD_SPAN_DOWN(16) XD_SPAN_DOWN(17) XD_SPAN_DOWN(18) XD_SPAN_DOWN(19)
+        XD_SPAN_DOWN(20) XD_SPAN_DOWN(21) XD_SPAN_DOWN(22) XD_SPAN_DOWN(23) XD_SPAN_DOWN(24)
+        XD_SPAN_DOWN(25) XD_SPAN_DOWN(26) XD_SPAN_DOWN(27) XD_SPAN_DOWN(28) XD_SPAN_DOWN(29)
+        XD_SPAN_DOWN(30) XD_SPAN_DOWN(31)
 #undef XD_SPAN_DOWN
-      default:
-        break;
+        default:
+          break;
+      }
+    }
+    // clip the edge registers to the computed range
+    if (rlo == rhi) {
+      live_lo = live_hi = wclip_at<C>(cur, rlo, lo_mask & hi_mask);
+    } else {
+      live_lo = wclip_at<C>(cur, rlo, lo_mask);
+      live_hi = wclip_at<C>(cur, rhi, hi_mask);
     }
   }
+  // (after the assembly chain the maximum saw clipped registers only, so an
+  // improvement it shows is already confirmed)
   uint64_t imp = ballot(vmx > st.bw);
-  // clip the edge registers to the computed range
-  const uint64_t lo_mask = ~0ull << (st.lo & 63);
-  const uint64_t hi_mask = ~0ull >> (63 - (st.hi & 63));
-  uint64_t live_lo, live_hi;
-  if (rlo == rhi) {
-    live_lo = live_hi = wclip_at<C>(cur, rlo, lo_mask & hi_mask);
-  } else {
-    live_lo = wclip_at<C>(cur, rlo, lo_mask);
-    live_hi = wclip_at<C>(cur, rhi, hi_mask);
-  }
   st.span_lo[PAR] = rlo;
   st.span_hi[PAR] = rhi;
   st.cells_blk += (uint32_t)(st.hi - st.lo + 1);
@@ -331,7 +338,7 @@ XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Par
       st.bj = st.d - st.bi;
     }
   }
-  if (imp != 0) {   // confirm on the clipped registers
+  if (!(ASM && NARROW) && imp != 0) {   // confirm on the clipped registers
     imp = 0;
 #pragma unroll
     for (int r = 0; r < C; ++r)
@@ -620,8 +627,9 @@ XD_FN int w2_fast(WBand<2> &bd, WScalars &st, const JobView &jv, const Params &P
 }
 
 // Whole one-directional extension of job j, resumed from a narrower tier's
-// save when there is one.  FAST (two registers only) enables the
-// hand-scheduled loop.
+// save when there is one.  FAST selects the assembly: the hand-scheduled
+// loop for two registers, the generated chain with built-in edge clipping
+// for more (narrow score fields only; else FAST changes nothing).
 template <int C, bool NARROW, bool FAST = false>
 XD_FN JobOut extend_job_wide(const Job &job, const Params &P, int32_t j) {
   constexpr int S = kWave * C;
@@ -695,7 +703,7 @@ XD_FN JobOut extend_job_wide(const Job &job, const Params &P, int32_t j) {
         wbuild<C, NARROW>(bd, st, e0, (st.lo >> 6) - 1, (st.hi >> 6) + 1, jv, P);
       bool go;
       if constexpr (C == 2) go = wstep2<NARROW, 0>(bd, st, e - e0, jv, P);
-      else go = wstep<C, NARROW, 0>(bd, st, e - e0, jv, P);
+      else go = wstep<C, NARROW, 0, FAST>(bd, st, e - e0, jv, P);
       if (!go) break;                                           // d = 2e
     }
     odd = false;
@@ -706,7 +714,7 @@ XD_FN JobOut extend_job_wide(const Job &job, const Params &P, int32_t j) {
       wbuild<C, NARROW>(bd, st, e0, (st.lo >> 6) - 1, (st.hi >> 6) + 1, jv, P);
     bool go;
     if constexpr (C == 2) go = wstep2<NARROW, 1>(bd, st, e - e0, jv, P);
-    else go = wstep<C, NARROW, 1>(bd, st, e - e0, jv, P);
+    else go = wstep<C, NARROW, 1, FAST>(bd, st, e - e0, jv, P);
     if (!go) break;                                             // d = 2e + 1
     ++e;
   }

@@ -27,15 +27,59 @@ def test_every_register_count_and_parity_is_generated():
             assert f"WChain<{c}, {par}>::run" in text
 
 
-def test_chain_order_and_end_tests():
+def _blocks(lines):
+    """Label -> the instructions under it, in order of appearance."""
+    out, cur = [], None
+    for ln in lines.split("\n"):
+        m = re.search(r'"\.L([hrl])(\d+)_%=:', ln)
+        if m:
+            cur = (m.group(1), int(m.group(2)), [])
+            out.append(cur)
+        elif '".Lend_%=:' in ln:
+            cur = None
+        elif cur is not None:
+            cur[2].append(ln)
+    return out
+
+
+def test_chain_order_end_tests_and_clipping():
     gen = _gen()
     for c in (4, 32):
         for par in (0, 1):
-            lines = "\n".join(gen.function(c, par))
-            regs = [int(r) for r in re.findall(r"v_max3_i32 %\[c(\d+)\]", lines)]
-            assert regs == (list(range(c)) if par == 0 else list(range(c - 1, -1, -1)))
-            # each block ends the chain when it reaches the span's other end
-            stops = [int(r) for r in re.findall(r"s_cmp_eq_u32 %\[stop\], (\d+)", lines)]
-            assert stops == regs
-            # neighbour rotation: right for even anti-diagonals, left for odd
-            assert lines.count("wave_ror:1" if par == 0 else "wave_rol:1") == c
+            text = "\n".join(gen.function(c, par))
+            reg = (lambda k: k) if par == 0 else (lambda k: c - 1 - k)
+            blocks = _blocks(text)
+            kinds = [(kind, k) for kind, k, _ in blocks]
+            # a head per entry position, then the fall-through run from
+            # position 1, then a tail per position that can end the chain
+            assert kinds == ([("h", k) for k in range(c)] + [("r", k) for k in range(1, c)]
+                             + [("l", k) for k in range(1, c)])
+            for kind, k, body in blocks:
+                code = "\n".join(body)
+                r = reg(k)
+                if kind in "hr":
+                    assert re.findall(r"v_max3_i32 %\[c(\d+)\]", code) == [str(r)]
+                    # the block ends the chain when it reaches the span's other end
+                    assert re.findall(r"s_cmp_eq_u32 %\[stop\], (\d+)", code) == [str(r)]
+                    # neighbour rotation: right for even anti-diagonals, left for odd
+                    assert code.count("wave_ror:1" if par == 0 else "wave_rol:1") == 1
+                    # the X-drop test comes two instructions before its use as a mask
+                    ins = [b.strip().strip('"').split()[0] for b in body]
+                    i_cmp = ins.index("v_cmp_le_i32")
+                    i_use = ins.index("v_cndmask_b32_e32")
+                    assert i_use - i_cmp >= 3
+                if kind == "h":
+                    # the entry register is clipped to mf and its survivors kept
+                    assert "s_and_b64 vcc, vcc, %[mf]" in code and "s_mov_b64 %[lf], vcc" in code
+                    assert code.index("%[mf]") < code.index("v_cndmask_b32_e32")
+                    nxt = f".Lr{k + 1}_%=" if k + 1 < c else ".Lend_%="
+                    assert body[-1].strip().startswith(f'"s_branch {nxt}')
+                if kind == "r":
+                    assert f"s_cbranch_scc1 .Ll{k}_%=" in code and "%[mf]" not in code
+                    assert "%[ml]" not in code
+                if kind == "l":
+                    # the last register is clipped to ml before -inf and the maximum
+                    assert code.index("s_and_b64 vcc, vcc, %[ml]") < code.index("v_cndmask")
+                    assert f"%[c{r}]" in code
+            # the last register's survivors are what VCC holds at the end
+            assert text.rstrip().count('"s_mov_b64 %[ll], vcc') == 1
