@@ -27,8 +27,14 @@ the test with the last register's mask.  So cells outside the range come out
 edge registers' survivor masks come back without another pass.
 
 The rotation of each block alternates between two registers, so the block
-after it finds it as its neighbour without a copy.  Run from the repository
-root: python paper_2002_05200_amd/csrc/gen_wchain.py
+after it finds it as its neighbour without a copy.
+
+WFirst<C>::run is the search for the first (lowest) slot of the span whose
+cell exceeds a value, used when best can rise by exactly one: a table of
+branches enters at the span's lowest register, and each register is one
+compare and two branches.
+
+Run from the repository root: python paper_2002_05200_amd/csrc/gen_wchain.py
 """
 import os
 
@@ -151,6 +157,61 @@ def function(C, par):
     return lines
 
 
+def first_function(C):
+    """WFirst<C>::run: slot (64 r + lane) of the first cell above `bw` in
+    registers rlo .. rhi, or -1."""
+    lines = [
+        f"template <>",
+        f"XD_MEMBER int32_t WFirst<{C}>::run(const vint *cur, int32_t bw, int32_t rlo, int32_t rhi) {{",
+        f"  int32_t slot;",
+        f"  asm volatile(",
+        f'      "s_lshl_b32 s42, %[rlo], 2\\n\\t"',
+        f'      "s_getpc_b64 s[40:41]\\n"',
+        f'      ".Lb_%=:\\n\\t"',
+        f'      "s_add_u32 s40, s40, s42\\n\\t"',
+        f'      "s_addc_u32 s41, s41, 0\\n\\t"',
+        f'      "s_add_u32 s40, s40, .Lt_%=-.Lb_%=\\n\\t"',
+        f'      "s_addc_u32 s41, s41, 0\\n\\t"',
+        f'      "s_nop 0\\n\\t"',
+        f'      "s_setpc_b64 s[40:41]\\n"',
+        f'      ".Lt_%=:\\n\\t"',
+    ]
+    for r in range(C):
+        lines.append(f'      "s_branch .Lq{r}_%=\\n\\t"')
+    for r in range(C):
+        lines += [
+            f'      ".Lq{r}_%=:\\n\\t"',
+            f'      "v_cmp_lt_i32_e32 vcc, %[bw], %[c{r}]\\n\\t"',
+            f'      "s_cbranch_vccnz .Lf{r}_%=\\n\\t"',
+            f'      "s_cmp_eq_u32 %[rhi], {r}\\n\\t"',
+            f'      "s_cbranch_scc1 .Lnone_%=\\n\\t"',
+        ]
+    lines += [
+        '      ".Lnone_%=:\\n\\t"',
+        '      "s_mov_b32 %[slot], -1\\n\\t"',
+        '      "s_branch .Lend_%=\\n\\t"',
+    ]
+    for r in range(C):
+        lines += [
+            f'      ".Lf{r}_%=:\\n\\t"',
+            '      "s_ff1_i32_b64 %[slot], vcc\\n\\t"',
+            f'      "s_add_i32 %[slot], %[slot], {64 * r}\\n\\t"',
+            '      "s_branch .Lend_%=\\n\\t"',
+        ]
+    ins = ", ".join(f'[c{r}] "v"(cur[{r}].x)' for r in range(C))
+    lines += [
+        '      ".Lend_%=:\\n"',
+        '      : [slot] "=&s"(slot)',
+        f"      : {ins},",
+        '        [bw] "s"(bw), [rlo] "s"(rlo), [rhi] "s"(rhi)',
+        '      : "vcc", "scc", "s40", "s41", "s42");',
+        "  return slot;",
+        "}",
+        "",
+    ]
+    return lines
+
+
 def render() -> str:
     """The header's text."""
     out = [
@@ -166,6 +227,9 @@ def render() -> str:
         "// rlo == rhi; mf then holds both clips).  `carry` is the outer neighbour",
         "// rotation of the chain's first register.  Reads only registers; writes",
         "// only cur[rlo..rhi].",
+        "//",
+        "// WFirst<C>::run returns the first slot (64 r + lane) of registers",
+        "// rlo..rhi whose cell exceeds bw, or -1 when none does.",
         "#pragma once",
         "",
         '#include "xd_wave.h"',
@@ -180,10 +244,16 @@ def render() -> str:
         "                            uint64_t &lf, uint64_t &ll);",
         "};",
         "",
+        "template <int C>",
+        "struct WFirst {",
+        "  XD_MEMBER static int32_t run(const vint *cur, int32_t bw, int32_t rlo, int32_t rhi);",
+        "};",
+        "",
     ]
     for C in CS:
         for par in (0, 1):
             out += function(C, par)
+        out += first_function(C)
     out += ["}  // namespace xd", ""]
     return "\n".join(out)
 

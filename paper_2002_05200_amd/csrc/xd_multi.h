@@ -246,13 +246,24 @@ XD_FN bool mw_step(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w, int 
       }
     }
     if (imp != 0 && P.unit_match) {   // best can rise by 1 only: one pass
-#pragma unroll
-      for (int r = 0; r < C; ++r) {
-        if (bests != 0x7fffffff || r < rlo || r > rhi) continue;
-        const uint64_t m = ballot(cur[r] > bw);
-        if (m != 0) {
+#ifndef XD_EMULATION
+      if constexpr (ASM && NARROW) {
+        const int32_t sb = WFirst<C>::run(cur, uniform(bw), uniform(rlo), uniform(rhi));
+        if (sb >= 0) {
           bestv = bw + 1;
-          bests = base + 64 * r + ctz64(m);
+          bests = base + sb;
+        }
+      } else
+#endif
+      {
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+          if (bests != 0x7fffffff || r < rlo || r > rhi) continue;
+          const uint64_t m = ballot(cur[r] > bw);
+          if (m != 0) {
+            bestv = bw + 1;
+            bests = base + 64 * r + ctz64(m);
+          }
         }
       }
     } else if (imp != 0) {   // this chunk's best value above bw and its first slot

@@ -298,6 +298,11 @@ XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Par
     // unrolled loop, whose code its register allocation handles better)
     int sbest = -1;
     const int32_t bw0 = st.bw;
+#ifndef XD_EMULATION
+    if constexpr (ASM && NARROW) {
+      sbest = WFirst<C>::run(cur, uniform(bw0), uniform(rlo), uniform(rhi));
+    } else
+#endif
     if constexpr (C >= 32) {
 #pragma unroll
       for (int r = 0; r < C; ++r) {
