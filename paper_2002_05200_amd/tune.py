@@ -30,11 +30,14 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE_PATH = os.path.join(HERE, "tune_table.json")
 
-CANDIDATES: Dict[str, List[int]] = {
+# A knob named "a+b" sets several options together.  The persistent grid size
+# that suits one wavefront per job differs from the multi-wave one (a
+# four-wavefront job needs a grid large enough that the longest jobs, not the
+# queue, set the end), so those two are searched jointly.
+CANDIDATES: Dict[str, list] = {
     "long_tier_bias": [0, 1, 2, 3],
     "long_job": [2000, 10000, 40000],
-    "multi_wave": [1, 2],
-    "waves_per_cu": [0, 8, 16, 24],
+    "multi_wave+waves_per_cu": [(m, w) for m in (0, 1, 2) for w in (0, 8, 16, 24)],
     "sort_jobs": [1, 0],
 }
 DEFAULTS = {"sched": 0, "waves_per_cu": 0, "sort_jobs": 1, "long_job": 0, "long_tier_bias": 0,
@@ -86,22 +89,31 @@ def time_opts(ctx, db, opts_kw: dict, reps: int = 3) -> float:
     return float(np.median(times))
 
 
-def tune(ctx, db, reps: int = 3, log=None, passes: int = 2) -> dict:
+def _set(opts: dict, knob: str, value) -> dict:
+    """Copy of opts with the knob (one option, or "a+b" several) set to value."""
+    out = dict(opts)
+    names = knob.split("+")
+    for n, v in zip(names, value if len(names) > 1 else (value,)):
+        out[n] = v
+    return out
+
+
+def tune(ctx, db, reps: int = 3, log=None, passes: int = 2, timer=None) -> dict:
     """Coordinate descent over CANDIDATES from DEFAULTS, repeated while a pass
-    improves (at most `passes` passes: the knobs interact, e.g. the grid size
-    that suits one wavefront per job differs from the multi-wave one)."""
+    improves (at most `passes` passes: the knobs interact).  `timer(opts)`
+    replaces the GPU timing (for tests)."""
+    timer = timer or (lambda o: time_opts(ctx, db, o, reps))
     best = dict(DEFAULTS)
-    best_ms = time_opts(ctx, db, best, reps)
+    best_ms = timer(best)
     base_ms = best_ms
     tried = {tuple(sorted(best.items())): best_ms}
     for _ in range(passes):
         start = dict(best)
         for knob, values in CANDIDATES.items():
             for v in values:
-                if best.get(knob) == v:
+                cand = _set(best, knob, v)
+                if cand == best:
                     continue
-                cand = dict(best)
-                cand[knob] = v
                 if cand["long_tier_bias"] == 0 and knob == "long_job":
                     continue                      # the split does nothing without a bias
                 if cand["long_tier_bias"] > 0 and cand["long_job"] == 0:
@@ -111,7 +123,7 @@ def tune(ctx, db, reps: int = 3, log=None, passes: int = 2) -> dict:
                     continue
                 if log:
                     log(f"  timing {cand}")
-                ms = time_opts(ctx, db, cand, reps)
+                ms = timer(cand)
                 tried[key] = ms
                 if log:
                     log(f"  {cand} -> {ms:.2f} ms")

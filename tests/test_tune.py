@@ -29,3 +29,20 @@ def test_shipped_table_is_well_formed():
         assert set(e["opts"]) <= {"sched", "waves_per_cu", "sort_jobs", "long_job", "long_tier_bias",
                                   "multi_wave"}
         assert e["ms"] <= e["default_ms"]
+
+
+def test_search_finds_grid_and_multi_wave_together():
+    """A job-latency-bound workload: four wavefronts per job only pay off with
+    a large persistent grid; one knob at a time would stop at two wavefronts."""
+    from paper_2002_05200_amd import tune
+
+    def timer(o):
+        if o["long_tier_bias"] or o["sort_jobs"] == 0:
+            return 3000.0
+        return {0: {0: 2045.0}, 1: {0: 2126.0, 16: 1834.0, 24: 1850.0},
+                2: {0: 2030.0}}[o["multi_wave"]].get(o["waves_per_cu"], 2100.0)
+
+    res = tune.tune(None, None, timer=timer)
+    assert res["opts"]["multi_wave"] == 1 and res["opts"]["waves_per_cu"] == 16
+    assert res["ms"] == 1834.0 and res["default_ms"] == 2045.0
+    assert res["opts"]["long_job"] == 0 and res["opts"]["sort_jobs"] == 1
