@@ -144,10 +144,14 @@ XD_FN uint64_t wclip_at(vint *cur, int r, uint64_t mask) {
 // prepares st for d + 1.  Returns false once the extension has ended.
 //
 // The span's registers rlo .. rhi are updated in one fall-through sequence
-// entered at rlo (a jump table), each followed by a test for rhi; range
-// clipping is applied afterwards to the two edge registers only.  Lanes
-// outside the range in those registers may briefly hold values above best,
-// so an improvement seen during the update is confirmed after clipping.
+// entered at its first register (a jump table), each followed by a test for
+// its last.  In the C version range clipping is applied afterwards to the
+// two edge registers only; lanes outside the range in those registers may
+// briefly hold values above best, so an improvement seen during the update
+// is confirmed after clipping.  The assembly version (ASM, narrow score
+// fields) clips the edge registers inside the chain, so its running maximum
+// needs no confirmation, and finds the first best cell with a generated
+// scan too.
 template <int C, bool NARROW, int PAR, bool ASM>
 XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Params &P) {
   vint *cur = PAR ? bd.O : bd.E;          // d - 2 on entry, d on exit
