@@ -83,3 +83,23 @@ def test_chain_order_end_tests_and_clipping():
                     assert f"%[c{r}]" in code
             # the last register's survivors are what VCC holds at the end
             assert text.rstrip().count('"s_mov_b64 %[ll], vcc') == 1
+
+
+def test_first_best_scan_shape():
+    """WFirst<C>: entered at rlo through a table, each register is one
+    compare of bw < cell and a branch to its own found-stub, then the end
+    test against rhi; a found-stub returns the lowest set lane + 64 r."""
+    gen = _gen()
+    for c in (4, 16):
+        text = "\n".join(gen.first_function(c))
+        table = re.findall(r'"s_branch \.Lq(\d+)_%=', text)
+        assert [int(x) for x in table] == list(range(c))
+        scans = re.findall(r"v_cmp_lt_i32_e32 vcc, %\[bw\], %\[c(\d+)\]", text)
+        assert [int(x) for x in scans] == list(range(c))
+        assert [int(x) for x in re.findall(r"s_cbranch_vccnz \.Lf(\d+)_%=", text)] == list(range(c))
+        assert [int(x) for x in re.findall(r"s_cmp_eq_u32 %\[rhi\], (\d+)", text)] == list(range(c))
+        offs = [int(x) for x in re.findall(r"s_add_i32 %\[slot\], %\[slot\], (\d+)", text)]
+        assert offs == [64 * r for r in range(c)]
+        assert text.count("s_ff1_i32_b64 %[slot], vcc") == c
+        # no register found: -1
+        assert '"s_mov_b32 %[slot], -1' in text
