@@ -52,7 +52,26 @@ def profiled_traffic(kernel_tag: str, workload: str):
     return int(fields["TRAFFIC_BYTES"]), os.path.relpath(path, ROOT)
 
 
-def cpu_baseline(workload: str, budget_s: float, n_total: int) -> dict:
+def host_cpu() -> dict:
+    """The host the CPU baseline ran on: logical CPUs, those this process may
+    use, and the CPU model."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
+
+
+def cpu_baseline(workload: str, budget_s: float, n_total: int, gpu_results=None) -> dict:
     from oracle import oracle
     from paper_2002_05200_amd import synth
     # grow an evenly spread sample until the oracle has run for about budget_s
@@ -71,7 +90,12 @@ def cpu_baseline(workload: str, budget_s: float, n_total: int) -> dict:
     return {"value": round(cells / secs / 1e9, 4), "unit": "GCUPS", "cores": 1, "kind": "oracle",
             "sample": f"{used} pairs of the same workload spread evenly over it "
                       f"({cells} cells, {secs:.1f} s, one thread)",
-            "all_cores": cpu_all_cores(workload, n_total, used)}
+            "host": host_cpu(),
+            "all_cores": cpu_all_cores(workload, n_total, used, gpu_results)}
+
+
+RESULT_FIELDS = ["score", "left_score", "right_score", "seed_score", "a_begin", "a_end",
+                 "b_begin", "b_end", "left_cells", "right_cells", "status"]
 
 
 def _oracle_shard(args):
@@ -80,25 +104,38 @@ def _oracle_shard(args):
     from paper_2002_05200_amd import synth
     bt = synth.make_batch(workload, n=n, start=start, stride=stride)
     res, t = oracle.batch(bt, return_time=True)
-    return int(res["left_cells"].sum() + res["right_cells"].sum()), t
+    idx = start + stride * np.arange(n, dtype=np.int64)
+    fields = np.stack([res[f] for f in RESULT_FIELDS], axis=1)
+    return int(res["left_cells"].sum() + res["right_cells"].sum()), t, idx, fields
 
 
-def cpu_all_cores(workload: str, n_total: int, n_sample: int) -> dict:
-    """The same oracle, one process per host core, each on its own evenly
-    spread shard as large as the single-thread sample (fewer pairs when the
-    workload runs out); GCUPS = all cells / the slowest shard's time."""
+def cpu_all_cores(workload: str, n_total: int, n_sample: int, gpu_results=None) -> dict:
+    """The same oracle, one process per usable host CPU (at most 16), each on
+    its own evenly spread shard as large as the single-thread sample (fewer
+    pairs when the workload runs out); GCUPS = all cells / the slowest shard's
+    time.  When the shards cover pairs of the timed GPU run, every integer
+    result field of those pairs is compared with the GPU's."""
     from multiprocessing import get_context
-    procs = max(1, min(16, os.cpu_count() or 1))
+    procs = max(1, min(16, host_cpu()["usable_cpus"]))
     per = max(1, min(n_sample, n_total // procs))
     stride = max(1, n_total // (per * procs))
     jobs = [(workload, n_total, p, stride * procs, per) for p in range(procs)]
     with get_context("fork").Pool(procs) as pool:
         out = pool.map(_oracle_shard, jobs)
-    cells = sum(c for c, _ in out)
-    slowest = max(t for _, t in out)
-    return {"value": round(cells / slowest / 1e9, 4), "unit": "GCUPS", "cores": procs,
-            "sample": f"{per * procs} pairs in {procs} shards ({cells} cells, slowest shard "
-                      f"{slowest:.1f} s)"}
+    cells = sum(o[0] for o in out)
+    slowest = max(o[1] for o in out)
+    rec = {"value": round(cells / slowest / 1e9, 4), "unit": "GCUPS", "cores": procs,
+           "sample": f"{per * procs} pairs in {procs} shards ({cells} cells, slowest shard "
+                     f"{slowest:.1f} s)"}
+    if gpu_results is not None:
+        idx = np.concatenate([o[2] for o in out])
+        ref = np.concatenate([o[3] for o in out])
+        got = np.stack([gpu_results[f][idx].astype(np.int64) for f in RESULT_FIELDS], axis=1)
+        bad = np.nonzero((got != ref).any(axis=1))[0]
+        rec["gpu_parity"] = {"pairs_compared": int(len(idx)), "fields": len(RESULT_FIELDS),
+                             "mismatched_pairs": int(len(bad)),
+                             "first_mismatches": idx[bad[:5]].tolist()}
+    return rec
 
 
 def serving_leg(n_distinct: int, n_requests: int, load: float, slots: int, max_batch: int,
@@ -398,7 +435,13 @@ def main():
                                       bool(args.serving_graph), min(16, os.cpu_count() or 1),
                                       sweep, args.serving_sweep_requests)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget, n_pairs)
+        line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget, n_pairs, res2)
+        gp = line["cpu_baseline"]["all_cores"].get("gpu_parity")
+        if gp is not None:
+            line["oracle_parity"] = {"pairs_compared": gp["pairs_compared"],
+                                     "of_pairs": n_pairs, "mismatched_pairs": gp["mismatched_pairs"],
+                                     "how": "every integer result field of the timed run against "
+                                            "the all-core oracle leg's results"}
     print(json.dumps(line), flush=True)
 
 

@@ -106,7 +106,16 @@ typedef struct {
                              run four / two wavefronts per job (shorter
                              anti-diagonal steps for very long jobs);
                              0 = one wavefront; others: XD_EINVAL             */
-} xd_opts; /* 40 bytes */
+    int32_t max_save_slots; /* 0 = automatic; N > 0 = at most N escalation
+                             saves per call.  A job whose band outgrows its
+                             window stores its state in a save slot and the
+                             next tier resumes from it; once the slots run
+                             out, further escalating jobs start over in the
+                             wider tier (same results, more work: see
+                             xd_stats.restarted).  For tests and for callers
+                             that cap memory                                   */
+    int32_t reserved;     /* must be 0                                          */
+} xd_opts; /* 48 bytes */
 
 /* Statistics of the last xdrop_extend on a context.  Tier t in 0..5 runs C =
  * 2^t cells per lane (a window of 64*C diagonals); tier 6 keeps the band in
@@ -115,6 +124,10 @@ typedef struct {
     uint64_t jobs[7];      /* jobs finished at each tier                        */
     uint64_t cells[7];     /* cells computed by the jobs finished at each tier  */
     uint64_t escalated[7]; /* jobs whose band outgrew the tier's window          */
+    uint64_t restarted[7]; /* of those, jobs that found no free save slot (or
+                              outgrew the widest save) and start over in the
+                              next tier                                        */
+    uint64_t wasted_cells[7]; /* cells the restarted jobs had computed here   */
     float stage_ms[9];     /* plan, tiers 0..5, tier 6, combine (profile only)  */
     int32_t profiled;      /* 1 when stage_ms is valid                          */
 } xd_stats;
@@ -133,9 +146,17 @@ xd_status xd_pack_codes(const uint8_t *codes, size_t n, uint32_t *words,
                         uint64_t base_off);
 
 /* Context on HIP device `device`: kernels, internal scratch (job lists, tier
- * queues) grown on demand.  mem_budget caps the scratch (0 = no cap). */
+ * queues, global-memory band buffers, escalation saves) grown on demand.
+ * mem_budget caps all of it (0 = no cap): under a budget the global-memory
+ * band holds fewer cells per anti-diagonal (at least 16,388; wider bands give
+ * XD_ENOMEM per pair) and fewer escalation saves are kept (jobs then start
+ * over in the wider tier), and a call whose job scratch alone does not fit
+ * returns XD_ENOMEM. */
 xd_status xd_ctx_create(int device, size_t mem_budget, xd_ctx **out);
 void xd_ctx_destroy(xd_ctx *ctx);
+
+/* Device bytes the context holds now (scratch, band buffers, saves). */
+xd_status xd_ctx_memory(const xd_ctx *ctx, uint64_t *bytes);
 
 /*
  * Batched X-drop extension of n_pairs pairs, enqueued on `stream` (a
@@ -194,7 +215,7 @@ typedef struct {
                                  (0 = 1 GiB); each slot holds an equal share       */
     xd_opts extend_opts;      /* launch options of every batch (graph and
                                  profile are set by the server)                     */
-} xd_server_opts; /* 64 bytes */
+} xd_server_opts; /* 72 bytes */
 
 /* One request: host buffers, read by xd_server_submit before it returns. */
 typedef struct {

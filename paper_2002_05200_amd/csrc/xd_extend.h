@@ -362,14 +362,17 @@ XD_FN JobOut extend_job_w1(const Job &job, const Params &P, int32_t j) {
       const int width = st.hi - st.lo + 1;
       if (width > kWave - 2) {   // the next tier resumes from here
         int32_t *sv = save_reserve(P, j, kWave);
+        const uint64_t cells = st.cells + lane_sum(cnt);
         if (sv) {
           save_scalars(sv, 2 * st.e + st.par, st.lo, st.hi, st.h, st.best, st.bi, st.bj, st.bw,
-                       st.thr, 1, st.cells + lane_sum(cnt));
+                       st.thr, 1, cells);
           store_vec(sv + kSaveHdr, lane_index(), bd.E[0]);
           store_vec(sv + kSaveHdr + kWave, lane_index(), bd.O[0]);
           save_publish(P, j, sv);
         }
         out.status = kJobWider;
+        out.bi = sv ? 1 : 0;
+        out.cells = cells;
         return out;
       }
       const int dl = st.lo - (kWave - width) / 2;

@@ -24,6 +24,9 @@ struct Job {
 // Job status values (internal).
 enum : int32_t { kJobOk = 0, kJobWider = 100 };
 
+// A finished job's result.  With status kJobWider (the band outgrew the
+// window) bi is 1 when the state was saved for the next tier, 0 when the job
+// starts over there, and cells holds the cells computed so far.
 struct JobOut {
   int32_t best, bi, bj, status;
   uint64_t cells;

@@ -201,6 +201,10 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job *__restrict__ jobs,
         const int32_t at = atomicAdd((int32_t *)&q.counters[kEsc + q.tier + 1], 1);
         q.next_esc[at] = j;
         atomicAdd(&stats[2 * kLists + q.tier], 1ull);
+        if (o.bi == 0) {
+          atomicAdd(&stats[kRestart + q.tier], 1ull);
+          atomicAdd(&stats[kWasted + q.tier], (unsigned long long)o.cells);
+        }
       } else {
         outs[j] = o;
         record_done(stats, q.tier, o.cells);
@@ -347,10 +351,23 @@ namespace {
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Escalation saves: one slot per job at most, 16 GiB at most, and under a
+// memory budget at most a quarter of it.
+constexpr uint64_t kSaveSlotBytes = sizeof(int32_t) * kSaveSlotWords;
+constexpr uint64_t kSavePoolMax = 16ull << 30;
+
+// Device memory of a context: job scratch, the global-memory band buffers
+// and the escalation save pool.  Under a budget (mem_budget > 0) the band
+// buffers take at most an eighth of it (fewer cells per anti-diagonal) and
+// the save pool what is left, at most a quarter; the total never exceeds the
+// budget.
 xd_status ensure_capacity(xd_ctx *c, int64_t n_pairs) {
   if (n_pairs <= c->cap_pairs && c->scratch.ptr) return XD_OK;
   int64_t cap = std::max<int64_t>(n_pairs, 1024);
   if (c->cap_pairs > 0) cap = std::max<int64_t>(cap, c->cap_pairs * 3 / 2);
+  if (c->budget && cap > n_pairs) {   // growth headroom only while it fits
+    cap = std::max<int64_t>(n_pairs, 1);
+  }
   const int64_t nj = 2 * cap;
   size_t off = 0;
   const size_t o_jobs = off; off = align_up(off + sizeof(Job) * nj);
@@ -364,23 +381,33 @@ xd_status ensure_capacity(xd_ctx *c, int64_t n_pairs) {
   const size_t o_cnt = off; off = align_up(off + sizeof(int32_t) * kCounters);
   const size_t o_stats = off; off = align_up(off + sizeof(unsigned long long) * kStats);
   const size_t o_dummy = off; off = align_up(off + 64);
-  if (c->budget && off > c->budget)
-    return fail(XD_ENOMEM, "scratch for " + std::to_string(n_pairs) + " pairs exceeds the budget");
+  int64_t spill_cap = c->spill.huge ? c->spill.cap : kHugeCap;
+  uint64_t pool_max = kSavePoolMax;
+  if (c->budget) {
+    if (!c->spill.huge) {
+      const int64_t fit = (int64_t)(c->budget / 8 / spill_bytes(1));
+      spill_cap = std::max<int64_t>(kHugeCapMin, std::min<int64_t>(kHugeCap, fit));
+    }
+    const uint64_t fixed = off + spill_bytes(spill_cap);
+    if (fixed > c->budget)
+      return fail(XD_ENOMEM, "scratch for " + std::to_string(n_pairs) + " pairs exceeds the budget");
+    pool_max = std::min<uint64_t>(c->budget / 4, c->budget - fixed);
+  }
   if (c->scratch.ptr) {
     XD_HIP(hipDeviceSynchronize());
     XD_HIP(hipFree(c->scratch.ptr));
     c->scratch.ptr = nullptr;
+    c->scratch.bytes = 0;
   }
   void *p = nullptr;
   if (hipMalloc(&p, off) != hipSuccess) return fail(XD_ENOMEM, "hipMalloc of job scratch failed");
   c->scratch.ptr = p;
   c->scratch.bytes = off;
-  if (!c->spill.huge && spill_alloc(&c->spill) != XD_OK)
+  if (!c->spill.huge && spill_alloc(&c->spill, spill_cap) != XD_OK)
     return fail(XD_ENOMEM, "hipMalloc of the global-memory band buffers failed");
-  {   // escalation saves: one slot per job, at most 2 GiB
-    const uint64_t max_slots = (2ull << 30) / (sizeof(int32_t) * kSaveSlotWords);
-    const uint64_t want = std::min<uint64_t>((uint64_t)nj, max_slots);
-    if (want > c->save_slots) {
+  {   // escalation saves
+    const uint64_t want = std::min<uint64_t>((uint64_t)nj, pool_max / kSaveSlotBytes);
+    if (want > c->save_slots || (c->budget && c->save_slots > want)) {
       if (c->save_pool) XD_HIP(hipFree(c->save_pool));
       c->save_pool = nullptr;
       c->save_slots = 0;
@@ -517,6 +544,8 @@ xd_status enqueue(xd_ctx *c, hipStream_t s, const Launch &L, bool prof) {
   P.unit_match = sc.match == 1;
   P.save_pool = c->save_pool;
   P.save_cap = c->save_slots;
+  if (o.max_save_slots > 0 && (uint64_t)o.max_save_slots < P.save_cap)
+    P.save_cap = (uint64_t)o.max_save_slots;
   P.save_top = c->stats + kSaveTop;
   P.job_save = c->job_save;
   const bool narrow = P.delta <= 3;
@@ -639,6 +668,13 @@ xd_status xd_ctx_create(int device, size_t mem_budget, xd_ctx **out) {
   return XD_OK;
 }
 
+xd_status xd_ctx_memory(const xd_ctx *c, uint64_t *bytes) {
+  if (!c || !bytes) return fail(XD_EINVAL, "xd_ctx_memory: null pointer");
+  *bytes = (uint64_t)c->scratch.bytes + (c->spill.huge ? spill_bytes(c->spill.cap) : 0) +
+           c->save_slots * kSaveSlotBytes;
+  return XD_OK;
+}
+
 void xd_ctx_destroy(xd_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
@@ -683,6 +719,8 @@ xd_status xdrop_extend(xd_ctx *c, const uint32_t *d_a, uint64_t a_words, const u
     return fail(XD_EINVAL, "xdrop_extend: multi_wave out of range");
   if (o.waves_per_cu < 0 || o.waves_per_cu > 64)
     return fail(XD_EINVAL, "xdrop_extend: waves_per_cu out of range");
+  if (o.max_save_slots < 0 || o.reserved != 0)
+    return fail(XD_EINVAL, "xdrop_extend: max_save_slots negative or reserved field set");
   const bool graph = o.graph != 0;
   if (graph && o.profile) return fail(XD_EINVAL, "xdrop_extend: graph and profile together");
   if (graph && !stream) return fail(XD_EINVAL, "xdrop_extend: graph mode needs a non-NULL stream");
@@ -804,6 +842,8 @@ xd_status xd_last_stats(xd_ctx *c, xd_stats *out) {
     out->jobs[t] = h[t];
     out->cells[t] = h[kLists + t];
     out->escalated[t] = h[2 * kLists + t];
+    out->restarted[t] = h[kRestart + t];
+    out->wasted_cells[t] = h[kWasted + t];
   }
   if (c->profiled) {
     for (int i = 0; i < 9; ++i) XD_HIP(hipEventElapsedTime(&out->stage_ms[i], c->ev[i], c->ev[i + 1]));

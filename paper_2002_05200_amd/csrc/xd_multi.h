@@ -416,9 +416,9 @@ XD_FN bool mw_restore(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w, c
 
 // Stores the workgroup's state in the job's save slot (slot order, C field =
 // slots / 64) for the next, wider tier; nothing when the window is wider than
-// a save slot holds or the pool is full.
+// a save slot holds or the pool is full.  Returns whether it saved.
 template <int NW, int C>
-XD_FN void mw_save(const WBand<C> &bd, const MwScalars &st, MwShared<NW, C> &sh, int w,
+XD_FN bool mw_save(const WBand<C> &bd, const MwScalars &st, MwShared<NW, C> &sh, int w,
                    const Params &P, int32_t j) {
   constexpr int S = 64 * C * NW;
   if (w == 0) {
@@ -441,6 +441,7 @@ XD_FN void mw_save(const WBand<C> &bd, const MwScalars &st, MwShared<NW, C> &sh,
   }
   __syncthreads();
   if (w == 0 && off >= 0) save_publish(P, j, P.save_pool + off);
+  return off >= 0;
 }
 
 // Whole extension of job j by the workgroup.  kJobWider when the band
@@ -511,8 +512,9 @@ XD_FN JobOut mw_extend(const Job &job, const Params &P, int32_t j, MwShared<NW, 
     ++e;
   }
   if (!ok) {
-    mw_save<NW, C>(bd, st, sh, w, P, j);
+    out.bi = mw_save<NW, C>(bd, st, sh, w, P, j) ? 1 : 0;
     out.status = kJobWider;
+    out.cells = st.cells + st.cells_blk;
     return out;
   }
   out.best = st.best;
@@ -555,6 +557,10 @@ __global__ __launch_bounds__(64 * NW) void k_extend_mw(const Job *__restrict__ j
       if (o.status == kJobWider) {
         overflow[atomicAdd(overflow_count, 1)] = j;
         atomicAdd(&stats[2 * kLists + q.tier], 1ull);
+        if (o.bi == 0) {
+          atomicAdd(&stats[kRestart + q.tier], 1ull);
+          atomicAdd(&stats[kWasted + q.tier], (unsigned long long)o.cells);
+        }
       } else {
         outs[j] = o;
         atomicAdd(&stats[q.tier], 1ull);

@@ -22,9 +22,13 @@ constexpr int kInit = 0, kEsc = kLists, kHead = 2 * kLists, kOff = 3 * kLists;
 constexpr int kHugeCount = 4 * kLists, kHugeHead = 4 * kLists + 1;
 constexpr int kCounters = 4 * kLists + 2;
 // Device statistics (uint64): jobs finished, cells of those jobs, escalations;
-// then the bump pointer of the escalation save pool.
+// the bump pointer of the escalation save pool; escalations that found no
+// save slot (the job starts over in the next tier) and the cells they had
+// computed.
 constexpr int kSaveTop = 3 * kLists;
-constexpr int kStats = 3 * kLists + 1;
+constexpr int kRestart = 3 * kLists + 1;
+constexpr int kWasted = 4 * kLists + 1;
+constexpr int kStats = 5 * kLists + 1;
 
 // Counting-sort bins: kCostBuckets per tier, longest jobs in the lowest bin.
 constexpr int kCostBuckets = 128;

@@ -19,13 +19,19 @@ namespace xd {
 
 constexpr int kSpillThreads = 256;
 // Jobs whose band outgrows the multi-wave tier's window start over here:
-// kHugeSlots workgroups with room for kHugeCap cells per anti-diagonal.
+// kHugeSlots workgroups with room for `cap` cells per anti-diagonal (kHugeCap
+// unless a memory budget asks for less); a job whose band is wider still
+// fails with XD_ENOMEM.
 constexpr int kHugeSlots = 8;
 constexpr int64_t kHugeCap = (1 << 20) + 4;
+constexpr int64_t kHugeCapMin = (1 << 14) + 4;
 
 struct SpillScratch {
-  int32_t *huge = nullptr;   // kHugeSlots * 3 * kHugeCap
+  int32_t *huge = nullptr;   // kHugeSlots * 3 * cap
+  int64_t cap = 0;
 };
+
+inline uint64_t spill_bytes(int64_t cap) { return sizeof(int32_t) * 3 * (uint64_t)cap * kHugeSlots; }
 
 // Where a spill pass takes its jobs from: a tier queue, or a plain list.
 struct SpillSource {
@@ -155,12 +161,12 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(const Job *__restrict__
   }
 }
 
-inline xd_status spill_alloc(SpillScratch *sp) {
+inline xd_status spill_alloc(SpillScratch *sp, int64_t cap) {
   if (!sp->huge) {
     void *p = nullptr;
-    if (hipMalloc(&p, sizeof(int32_t) * 3 * kHugeCap * kHugeSlots) != hipSuccess)
-      return XD_ENOMEM;
+    if (hipMalloc(&p, spill_bytes(cap)) != hipSuccess) return XD_ENOMEM;
     sp->huge = (int32_t *)p;
+    sp->cap = cap;
   }
   return XD_OK;
 }
@@ -177,7 +183,7 @@ inline xd_status spill_launch(SpillScratch *sp, hipStream_t s, const Job *jobs,
   b.list_count = list_count;
   b.overflow = nullptr;
   b.overflow_count = nullptr;
-  b.cap = kHugeCap;
+  b.cap = sp->cap;
   hipLaunchKernelGGL(k_spill, dim3(kHugeSlots), dim3(kSpillThreads), 0, s, jobs, b, head, outs,
                      stats, P, sp->huge);
   return hipGetLastError() == hipSuccess ? XD_OK : XD_EDEVICE;
@@ -186,6 +192,7 @@ inline xd_status spill_launch(SpillScratch *sp, hipStream_t s, const Job *jobs,
 inline void spill_free(SpillScratch *sp) {
   if (sp->huge) (void)hipFree(sp->huge);
   sp->huge = nullptr;
+  sp->cap = 0;
 }
 
 }  // namespace xd

@@ -524,11 +524,12 @@ XD_FN bool wrecenter(WBand<C> &bd, WScalars &st) {
   return true;
 }
 
+// Returns false when no save slot was free (the job then starts over).
 template <int C>
-XD_FN void wsave(const WBand<C> &bd, const WScalars &st, const Params &P, int32_t j) {
+XD_FN bool wsave(const WBand<C> &bd, const WScalars &st, const Params &P, int32_t j) {
   constexpr int S = kWave * C;
   int32_t *sv = save_reserve(P, j, S);
-  if (!sv) return;
+  if (!sv) return false;
   save_scalars(sv, st.d, st.lo, st.hi, st.h, st.best, st.bi, st.bj, st.bw, st.thr, C,
                st.cells + st.cells_blk);
   const vint l = lane_index();
@@ -538,6 +539,7 @@ XD_FN void wsave(const WBand<C> &bd, const WScalars &st, const Params &P, int32_
     store_vec(sv + kSaveHdr + S, l + 64 * r, bd.O[r]);
   }
   save_publish(P, j, sv);
+  return true;
 }
 
 // Restores a narrower tier's save (slot order) into the middle of the window.
@@ -728,8 +730,9 @@ XD_FN JobOut extend_job_wide(const Job &job, const Params &P, int32_t j) {
     ++e;
   }
   if (!ok) {
-    wsave<C>(bd, st, P, j);
+    out.bi = wsave<C>(bd, st, P, j) ? 1 : 0;
     out.status = kJobWider;
+    out.cells = st.cells + st.cells_blk;
     return out;
   }
   out.best = st.best;

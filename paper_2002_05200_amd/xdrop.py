@@ -42,12 +42,14 @@ class Opts(ctypes.Structure):
                 ("waves_per_cu", ctypes.c_int32), ("sort_jobs", ctypes.c_int32),
                 ("long_job", ctypes.c_int32), ("long_tier_bias", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("impl", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("multi_wave", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("multi_wave", ctypes.c_int32),
+                ("max_save_slots", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("jobs", ctypes.c_uint64 * 7), ("cells", ctypes.c_uint64 * 7),
-                ("escalated", ctypes.c_uint64 * 7), ("stage_ms", ctypes.c_float * 9),
+                ("escalated", ctypes.c_uint64 * 7), ("restarted", ctypes.c_uint64 * 7),
+                ("wasted_cells", ctypes.c_uint64 * 7), ("stage_ms", ctypes.c_float * 9),
                 ("profiled", ctypes.c_int32)]
 
 
@@ -95,6 +97,8 @@ def lib() -> ctypes.CDLL:
         L.xd_ctx_create.restype = i32
         L.xd_ctx_destroy.argtypes = [p]
         L.xd_ctx_destroy.restype = None
+        L.xd_ctx_memory.argtypes = [p, ctypes.POINTER(u64)]
+        L.xd_ctx_memory.restype = i32
         L.xdrop_extend.argtypes = [p, p, u64, p, u64, p, sz, Scores, p, p, p]
         L.xdrop_extend.restype = i32
         L.xdrop_extend_host.argtypes = [p, p, u64, p, u64, p, sz, Scores, p, p]
@@ -183,11 +187,13 @@ class DeviceBatch:
 
 def make_opts(sched: int = SCHED_AUTO, min_tier: int = 0, waves_per_cu: int = 0,
               sort_jobs: int = 1, long_job: int = 0, long_tier_bias: int = 0,
-              profile: int = 0, impl: int = 0, graph: int = 0, multi_wave: int = 0) -> Opts:
+              profile: int = 0, impl: int = 0, graph: int = 0, multi_wave: int = 0,
+              max_save_slots: int = 0) -> Opts:
     o = Opts()
     o.sched, o.min_tier, o.waves_per_cu = sched, min_tier, waves_per_cu
     o.sort_jobs, o.long_job, o.long_tier_bias = sort_jobs, long_job, long_tier_bias
     o.profile, o.impl, o.graph, o.multi_wave = profile, impl, graph, multi_wave
+    o.max_save_slots = max_save_slots
     return o
 
 
@@ -247,13 +253,21 @@ class Context:
             out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts) if opts is not None else None))
         return out
 
+    def memory(self) -> int:
+        """xd_ctx_memory: device bytes the context holds."""
+        b = ctypes.c_uint64()
+        _check(lib().xd_ctx_memory(self.h, ctypes.byref(b)))
+        return b.value
+
     def stats(self) -> dict:
-        """xd_last_stats: per-tier jobs / cells / escalations, stage times."""
+        """xd_last_stats: per-tier jobs / cells / escalations / restarts, stage times."""
         st = Stats()
         _check(lib().xd_last_stats(self.h, ctypes.byref(st)))
         out = {"jobs": np.array(list(st.jobs), np.int64),
                "cells": np.array(list(st.cells), np.int64),
-               "escalated": np.array(list(st.escalated), np.int64)}
+               "escalated": np.array(list(st.escalated), np.int64),
+               "restarted": np.array(list(st.restarted), np.int64),
+               "wasted_cells": np.array(list(st.wasted_cells), np.int64)}
         if st.profiled:
             out["stage_ms"] = np.array(list(st.stage_ms), np.float64)
         return out

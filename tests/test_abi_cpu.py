@@ -93,16 +93,45 @@ def test_null_context_is_rejected_without_touching_a_device(L):
     L.xd_ctx_destroy(None)
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's structs have the sizes and field offsets a C compiler
+    gives the header's structs."""
+    import subprocess
     from paper_2002_05200_amd import xdrop
+    structs = {"xd_pair": None, "xd_result": None, "xd_opts": xdrop.Opts,
+               "xd_stats": xdrop.Stats, "xd_server_opts": xdrop.ServerOpts,
+               "xd_request": xdrop.Request, "xd_server_stats": xdrop.ServerStats}
+    fields = {"xd_opts": [f for f, _ in xdrop.Opts._fields_],
+              "xd_stats": [f for f, _ in xdrop.Stats._fields_],
+              "xd_server_opts": [f for f, _ in xdrop.ServerOpts._fields_],
+              "xd_pair": list(xdrop.PAIR_DTYPE.names),
+              "xd_result": list(xdrop.RESULT_DTYPE.names)}
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "xdrop.h"', "int main(void) {"]
+    for s in structs:
+        src.append(f'printf("{s} %zu\\n", sizeof({s}));')
+        for f in fields.get(s, []):
+            src.append(f'printf("{s}.{f} %zu\\n", offsetof({s}, {f}));')
+    src.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", f"-I{os.path.dirname(HEADER)}", str(c), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    assert int(got["xd_pair"]) == xdrop.PAIR_DTYPE.itemsize == 40
+    assert int(got["xd_result"]) == xdrop.RESULT_DTYPE.itemsize == 56
+    for name, dt in (("xd_pair", xdrop.PAIR_DTYPE), ("xd_result", xdrop.RESULT_DTYPE)):
+        for f in dt.names:
+            assert int(got[f"{name}.{f}"]) == dt.fields[f][1], (name, f)
+    for s, cls in structs.items():
+        if cls is None:
+            continue
+        assert int(got[s]) == ctypes.sizeof(cls), s
+        for f in fields.get(s, []):
+            assert int(got[f"{s}.{f}"]) == getattr(cls, f).offset, (s, f)
     text = open(HEADER).read()
-    assert "/* 40 bytes */" in text and xdrop.PAIR_DTYPE.itemsize == 40
-    assert "/* 56 bytes */" in text and xdrop.RESULT_DTYPE.itemsize == 56
-    assert "/* 40 bytes */" in text and ctypes.sizeof(xdrop.Opts) == 40
-    assert ctypes.sizeof(xdrop.Stats) == 3 * 7 * 8 + 9 * 4 + 4
-    assert "} xd_server_opts; /* 64 bytes */" in text and ctypes.sizeof(xdrop.ServerOpts) == 64
-    assert "} xd_request; /* 56 bytes */" in text and ctypes.sizeof(xdrop.Request) == 56
-    assert ctypes.sizeof(xdrop.ServerStats) == 6 * 8
+    assert "} xd_opts; /* 48 bytes */" in text and int(got["xd_opts"]) == 48
+    assert "} xd_server_opts; /* 72 bytes */" in text and int(got["xd_server_opts"]) == 72
+    assert "} xd_request; /* 56 bytes */" in text and int(got["xd_request"]) == 56
 
 
 def test_server_rejects_null_arguments_without_a_device(L):

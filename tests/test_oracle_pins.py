@@ -67,10 +67,11 @@ def _strings(alpha, max_len):
 
 
 def test_p2_full_matrix_exhaustive_binary():
-    strs = list(_strings(2, 4))
+    """Every pair of reads over a two-letter alphabet of length 0..6, X 0..8."""
+    strs = list(_strings(2, 6))
     for a in strs:
         for b in strs:
-            for x in range(0, 7):
+            for x in range(0, 9):
                 got = ext(a, b, (1, -1, -1), x)
                 ref = brute.xdrop_full(a, b, 1, -1, -1, x)
                 assert (got["best"], got["bi"], got["bj"], got["cells"]) == (
@@ -81,7 +82,7 @@ def test_p2_full_matrix_exhaustive_binary():
 def test_p2_full_matrix_random(sc):
     r = rng(2)
     for _ in range(60):
-        m, n = int(r.integers(0, 31)), int(r.integers(0, 31))
+        m, n = int(r.integers(0, 65)), int(r.integers(0, 65))
         a = list(r.integers(0, 4, m))
         if r.random() < 0.6 and m:
             # a noisy copy keeps the band alive for long
