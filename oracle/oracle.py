@@ -59,6 +59,13 @@ def lib():
         L.ox_pair.restype = ctypes.c_int
         L.ox_batch.argtypes = [p, p, p, p, p, p, p, p, p, i64, i64, i64, i64, i64, p]
         L.ox_batch.restype = ctypes.c_double
+        L.ox_extend_matrix.argtypes = [p, i64, p, i64, p, i64, i64,
+                                       ctypes.POINTER(_Ext), ctypes.POINTER(_Trace)]
+        L.ox_extend_matrix.restype = ctypes.c_int
+        L.ox_pair_matrix.argtypes = [p, i64, p, i64, i64, i64, i64, p, i64, i64, p]
+        L.ox_pair_matrix.restype = ctypes.c_int
+        L.ox_batch_matrix.argtypes = [p, p, p, p, p, p, p, p, p, i64, i64, p, i64, p]
+        L.ox_batch_matrix.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -87,6 +94,60 @@ def extend(a, b, match=1, mismatch=-1, gap=-1, x=10, trace: bool = False):
     if trace:
         res["trace"] = {f: v[: tr.n].copy() for f, v in bufs.items()}
     return res
+
+
+def _table(matrix) -> np.ndarray:
+    t = np.ascontiguousarray(np.asarray(matrix, dtype=np.int64).reshape(16))
+    return t
+
+
+def extend_matrix(a, b, matrix, gap=-1, x=10, trace: bool = False):
+    """One extension under a 4 x 4 substitution table (matrix[p][q] scores
+    base p of a against base q of b).  Returns a dict."""
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    b = np.ascontiguousarray(b, dtype=np.uint8)
+    tbl = _table(matrix)
+    out = _Ext()
+    tr = None
+    bufs = None
+    if trace:
+        cap = len(a) + len(b) + 1
+        bufs = {f: np.zeros(cap, np.int64) for f in ("lo", "hi", "la", "lb", "best", "vmax")}
+        tr = _Trace(cap, 0, *[bufs[f].ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+                              for f in ("lo", "hi", "la", "lb", "best", "vmax")])
+    rc = lib().ox_extend_matrix(_ptr(a), len(a), _ptr(b), len(b), _ptr(tbl), gap, x,
+                                ctypes.byref(out), ctypes.byref(tr) if tr is not None else None)
+    if rc:
+        raise ValueError("ox_extend_matrix rejected its arguments")
+    res = {f: int(getattr(out, f)) for f in ("best", "bi", "bj", "cells", "ndiag", "wmax")}
+    if trace:
+        res["trace"] = {f: v[: tr.n].copy() for f, v in bufs.items()}
+    return res
+
+
+def pair_matrix(a, b, a_seed, b_seed, matrix, k=17, gap=-1, x=10) -> dict:
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    b = np.ascontiguousarray(b, dtype=np.uint8)
+    out = np.zeros(1, PAIR_DTYPE)
+    lib().ox_pair_matrix(_ptr(a), len(a), _ptr(b), len(b), a_seed, b_seed, k, _ptr(_table(matrix)),
+                         gap, x, _ptr(out))
+    return {f: int(out[f][0]) for f in PAIR_FIELDS}
+
+
+def batch_matrix(bt, matrix, gap, return_time: bool = False):
+    """Oracle results for a generator batch under a substitution table."""
+    n = bt.n
+    out = np.zeros(n, PAIR_DTYPE)
+    arr = lambda v, dt: np.ascontiguousarray(v, dtype=dt)
+    a = arr(bt.a, np.uint8) if len(bt.a) else np.zeros(1, np.uint8)
+    b = arr(bt.b, np.uint8) if len(bt.b) else np.zeros(1, np.uint8)
+    keep = [arr(bt.a_off, np.int64), arr(bt.a_len, np.int64), arr(bt.b_off, np.int64),
+            arr(bt.b_len, np.int64), arr(bt.a_seed, np.int64), arr(bt.b_seed, np.int64),
+            arr(bt.x, np.int32)]
+    tbl = _table(matrix)
+    secs = lib().ox_batch_matrix(_ptr(a), _ptr(b), *[_ptr(v) for v in keep], n, bt.k, _ptr(tbl),
+                                 gap, _ptr(out))
+    return (out, secs) if return_time else out
 
 
 def pair(a, b, a_seed, b_seed, k=17, match=1, mismatch=-1, gap=-1, x=10) -> dict:

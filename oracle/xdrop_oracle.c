@@ -7,8 +7,11 @@
  * X-drop is a heuristic, so this oracle is the algorithm itself, step by step,
  * in the paper's order:
  *   - problem statement and cell recurrence (Section III-A): S(i,j) takes the
- *     best of the diagonal predecessor plus match/mismatch and the two
- *     neighbours plus the (negative) gap score;
+ *     best of the diagonal predecessor plus the substitution score of
+ *     (a_i, b_j) and the two neighbours plus the (negative) gap score; the
+ *     paper's match/mismatch choice is the table with `match` on its
+ *     diagonal, and any 4 x 4 table is accepted (Section VIII names other
+ *     scoring schemes as future work);
  *   - X-drop rule (Section III-A): a cell scoring below best - X becomes -inf
  *     and is never used again; best is updated once per anti-diagonal, after
  *     the whole anti-diagonal is computed (Section IV-A);
@@ -52,9 +55,9 @@ static int64_t cell(const antidiag *ad, int64_t i) {
 static int64_t max2(int64_t p, int64_t q) { return p > q ? p : q; }
 static int64_t min2(int64_t p, int64_t q) { return p < q ? p : q; }
 
-int ox_extend(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
-              int64_t match, int64_t mismatch, int64_t gap, int64_t x,
-              ox_ext *out, ox_trace *trace) {
+int ox_extend_matrix(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
+                     const int64_t score[16], int64_t gap, int64_t x,
+                     ox_ext *out, ox_trace *trace) {
     if (m < 0 || n < 0 || x < 0 || x > (INT64_C(1) << 62) || !out) return 1;
     memset(out, 0, sizeof(*out));
     if (trace) trace->n = 0;
@@ -92,7 +95,7 @@ int ox_extend(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
             if (i >= 1 && j >= 1) {                     /* (i-1, j-1) */
                 p = cell(two_back, i - 1);
                 if (p != OX_NEG) {
-                    int64_t s = (a[i - 1] == b[j - 1]) ? match : mismatch;
+                    int64_t s = score[4 * a[i - 1] + b[j - 1]];
                     v = max2(v, p + s);
                 }
             }
@@ -142,10 +145,25 @@ int ox_extend(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
     return 0;
 }
 
-int ox_pair(const uint8_t *a, int64_t len_a, const uint8_t *b, int64_t len_b,
-            int64_t a_seed, int64_t b_seed, int64_t k,
-            int64_t match, int64_t mismatch, int64_t gap, int64_t x,
-            ox_pair_result *out) {
+/* Match/mismatch scoring is the substitution table with `match` on its
+ * diagonal and `mismatch` everywhere else. */
+static void linear_table(int64_t match, int64_t mismatch, int64_t score[16]) {
+    for (int p = 0; p < 4; p++)
+        for (int q = 0; q < 4; q++) score[4 * p + q] = (p == q) ? match : mismatch;
+}
+
+int ox_extend(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
+              int64_t match, int64_t mismatch, int64_t gap, int64_t x,
+              ox_ext *out, ox_trace *trace) {
+    int64_t score[16];
+    linear_table(match, mismatch, score);
+    return ox_extend_matrix(a, m, b, n, score, gap, x, out, trace);
+}
+
+int ox_pair_matrix(const uint8_t *a, int64_t len_a, const uint8_t *b, int64_t len_b,
+                   int64_t a_seed, int64_t b_seed, int64_t k,
+                   const int64_t score[16], int64_t gap, int64_t x,
+                   ox_pair_result *out) {
     memset(out, 0, sizeof(*out));
     if (k < 0 || x < 0 || a_seed < 0 || b_seed < 0 || a_seed + k > len_a ||
         b_seed + k > len_b) {
@@ -154,20 +172,20 @@ int ox_pair(const uint8_t *a, int64_t len_a, const uint8_t *b, int64_t len_b,
     }
     /* Right extension: the suffixes after the seed, read forward. */
     ox_ext right, left;
-    int rc = ox_extend(a + a_seed + k, len_a - a_seed - k, b + b_seed + k,
-                       len_b - b_seed - k, match, mismatch, gap, x, &right, NULL);
+    int rc = ox_extend_matrix(a + a_seed + k, len_a - a_seed - k, b + b_seed + k,
+                              len_b - b_seed - k, score, gap, x, &right, NULL);
     /* Left extension: the prefixes before the seed, reversed. */
     uint8_t *ra = (uint8_t *)malloc((size_t)(a_seed > 0 ? a_seed : 1));
     uint8_t *rb = (uint8_t *)malloc((size_t)(b_seed > 0 ? b_seed : 1));
     for (int64_t t = 0; t < a_seed; t++) ra[t] = a[a_seed - 1 - t];
     for (int64_t t = 0; t < b_seed; t++) rb[t] = b[b_seed - 1 - t];
-    rc |= ox_extend(ra, a_seed, rb, b_seed, match, mismatch, gap, x, &left, NULL);
+    rc |= ox_extend_matrix(ra, a_seed, rb, b_seed, score, gap, x, &left, NULL);
     free(ra); free(rb);
     if (rc) { out->status = 1; return 1; }
 
     int64_t seed_score = 0;
     for (int64_t t = 0; t < k; t++)
-        seed_score += (a[a_seed + t] == b[b_seed + t]) ? match : mismatch;
+        seed_score += score[4 * a[a_seed + t] + b[b_seed + t]];
 
     out->left_score = left.best;
     out->right_score = right.best;
@@ -183,6 +201,31 @@ int ox_pair(const uint8_t *a, int64_t len_a, const uint8_t *b, int64_t len_b,
     out->right_bi = right.bi; out->right_bj = right.bj;
     out->status = 0;
     return 0;
+}
+
+int ox_pair(const uint8_t *a, int64_t len_a, const uint8_t *b, int64_t len_b,
+            int64_t a_seed, int64_t b_seed, int64_t k,
+            int64_t match, int64_t mismatch, int64_t gap, int64_t x,
+            ox_pair_result *out) {
+    int64_t score[16];
+    linear_table(match, mismatch, score);
+    return ox_pair_matrix(a, len_a, b, len_b, a_seed, b_seed, k, score, gap, x, out);
+}
+
+double ox_batch_matrix(const uint8_t *arena_a, const uint8_t *arena_b,
+                       const int64_t *a_off, const int64_t *a_len,
+                       const int64_t *b_off, const int64_t *b_len,
+                       const int64_t *a_seed, const int64_t *b_seed, const int32_t *x,
+                       int64_t n_pairs, int64_t k, const int64_t score[16], int64_t gap,
+                       ox_pair_result *out) {
+    struct timespec t0, t1;
+    clock_gettime(CLOCK_MONOTONIC, &t0);
+    for (int64_t p = 0; p < n_pairs; p++) {
+        ox_pair_matrix(arena_a + a_off[p], a_len[p], arena_b + b_off[p], b_len[p],
+                       a_seed[p], b_seed[p], k, score, gap, x[p], &out[p]);
+    }
+    clock_gettime(CLOCK_MONOTONIC, &t1);
+    return (double)(t1.tv_sec - t0.tv_sec) + 1e-9 * (double)(t1.tv_nsec - t0.tv_nsec);
 }
 
 double ox_batch(const uint8_t *arena_a, const uint8_t *arena_b,

@@ -50,10 +50,25 @@ typedef struct {
 /* -inf: a flag value, never used in arithmetic. */
 #define OX_NEG INT64_MIN
 
-/* One extension of a[0..m) against b[0..n).  Returns 0, or 1 on bad arguments. */
+/* One extension of a[0..m) against b[0..n) under a substitution table:
+ * aligning base p of A with base q of B scores score[4 * p + q] (Section
+ * III-A with the match/mismatch choice generalised to a table, as Section
+ * VIII proposes for other alphabets).  Returns 0, or 1 on bad arguments. */
+int ox_extend_matrix(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
+                     const int64_t score[16], int64_t gap, int64_t x,
+                     ox_ext *out, ox_trace *trace);
+
+/* Match/mismatch scoring: the table with `match` on its diagonal. */
 int ox_extend(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
               int64_t match, int64_t mismatch, int64_t gap, int64_t x,
               ox_ext *out, ox_trace *trace);
+
+/* Left and right extension of one seeded pair, combined (seed score summed
+ * from the table). */
+int ox_pair_matrix(const uint8_t *a, int64_t len_a, const uint8_t *b, int64_t len_b,
+                   int64_t a_seed, int64_t b_seed, int64_t k,
+                   const int64_t score[16], int64_t gap, int64_t x,
+                   ox_pair_result *out);
 
 /* Left and right extension of one seeded pair, combined. */
 int ox_pair(const uint8_t *a, int64_t len_a, const uint8_t *b, int64_t len_b,
@@ -69,6 +84,13 @@ double ox_batch(const uint8_t *arena_a, const uint8_t *arena_b,
                 const int64_t *a_seed, const int64_t *b_seed, const int32_t *x,
                 int64_t n_pairs, int64_t k, int64_t match, int64_t mismatch,
                 int64_t gap, ox_pair_result *out);
+
+double ox_batch_matrix(const uint8_t *arena_a, const uint8_t *arena_b,
+                       const int64_t *a_off, const int64_t *a_len,
+                       const int64_t *b_off, const int64_t *b_len,
+                       const int64_t *a_seed, const int64_t *b_seed, const int32_t *x,
+                       int64_t n_pairs, int64_t k, const int64_t score[16], int64_t gap,
+                       ox_pair_result *out);
 
 #ifdef __cplusplus
 }

@@ -9,18 +9,22 @@ Python's ``-math.inf`` and each anti-diagonal's range found by scanning the
 matrix.  It shares no code or data structure with the C oracle's rolling
 anti-diagonals, so agreement pins the oracle's bookkeeping.
 
-Both are pure-Python loops for tiny inputs.
+Both are pure-Python loops for tiny inputs.  Either takes match/mismatch
+scores or, with ``table``, a 4 x 4 substitution table (table[x][y] scores
+base x of a against base y of b).
 """
 import math
 
 NEG_INF = -math.inf
 
 
-def score(x, y, match, mismatch):
+def score(x, y, match, mismatch, table=None):
+    if table is not None:
+        return table[x][y]
     return match if x == y else mismatch
 
 
-def full_dp(a, b, match=1, mismatch=-1, gap=-1):
+def full_dp(a, b, match=1, mismatch=-1, gap=-1, table=None):
     m, n = len(a), len(b)
     S = [[0] * (n + 1) for _ in range(m + 1)]
     for i in range(m + 1):
@@ -29,7 +33,7 @@ def full_dp(a, b, match=1, mismatch=-1, gap=-1):
                 continue
             cands = []
             if i > 0 and j > 0:
-                cands.append(S[i - 1][j - 1] + score(a[i - 1], b[j - 1], match, mismatch))
+                cands.append(S[i - 1][j - 1] + score(a[i - 1], b[j - 1], match, mismatch, table))
             if i > 0:
                 cands.append(S[i - 1][j] + gap)
             if j > 0:
@@ -47,7 +51,7 @@ def full_dp(a, b, match=1, mismatch=-1, gap=-1):
     return {"best": best, "bi": bi, "bj": bj, "cells": (m + 1) * (n + 1) - 1, "S": S}
 
 
-def xdrop_full(a, b, match=1, mismatch=-1, gap=-1, x=10):
+def xdrop_full(a, b, match=1, mismatch=-1, gap=-1, x=10, table=None):
     m, n = len(a), len(b)
     S = [[NEG_INF] * (n + 1) for _ in range(m + 1)]
     S[0][0] = 0
@@ -66,7 +70,7 @@ def xdrop_full(a, b, match=1, mismatch=-1, gap=-1, x=10):
             j = d - i
             v = NEG_INF
             if i > 0 and j > 0:
-                v = max(v, S[i - 1][j - 1] + score(a[i - 1], b[j - 1], match, mismatch))
+                v = max(v, S[i - 1][j - 1] + score(a[i - 1], b[j - 1], match, mismatch, table))
             if i > 0:
                 v = max(v, S[i - 1][j] + gap)
             if j > 0:
