@@ -94,6 +94,34 @@ def cpu_baseline(workload: str, budget_s: float, n_total: int, gpu_results=None)
             "all_cores": cpu_all_cores(workload, n_total, used, gpu_results)}
 
 
+def eq1_ceiling(workload: str, n_total: int, tier: int, n_sample: int = 400) -> dict:
+    """Adapted lane-occupancy ceiling (Section VII, Eq. 1) of one tier: the
+    oracle traces the computed range of every anti-diagonal of an evenly
+    spread sample of pairs (both extensions of each), and each anti-diagonal
+    is priced at the lanes the tier that computes it issues."""
+    from oracle import oracle
+    from paper_2002_05200_amd import ceiling, synth
+    n = min(n_sample, n_total)
+    stride = max(1, n_total // n)
+    bt = synth.make_batch(workload, n=n, start=0, stride=stride)
+    m_, mm, g = bt.scores
+    jobs = []
+    for p in range(bt.n):
+        a, b = bt.pair(p)
+        pa, pb, k, x = int(bt.a_seed[p]), int(bt.b_seed[p]), bt.k, int(bt.x[p])
+        for ea, eb in ((a[:pa][::-1], b[:pb][::-1]), (a[pa + k:], b[pb + k:])):
+            tr = oracle.extend(ea, eb, m_, mm, g, x=x, trace=True)["trace"]
+            jobs.append(((tr["hi"] - tr["lo"] + 1).tolist(),
+                         ceiling.initial_tier(len(ea), len(eb), x)))
+    c = ceiling.ceiling(jobs, only_tier=tier)
+    return {"frac": round(c["work_weighted"], 4), "eq1_mean": round(c["eq1_mean"], 4),
+            "tier": tier, "anti_diagonals": c["anti_diagonals"],
+            "sample": f"{bt.n} pairs spread evenly over the workload (both extensions), "
+                      f"widths from the oracle's per-anti-diagonal trace",
+            "lanes_model": "64 lanes per anti-diagonal with one register, 128 with two, "
+                           "the spanned registers with more"}
+
+
 RESULT_FIELDS = ["score", "left_score", "right_score", "seed_score", "a_begin", "a_end",
                  "b_begin", "b_end", "left_cells", "right_cells", "status"]
 
@@ -436,6 +464,11 @@ def main():
                                       sweep, args.serving_sweep_requests)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget, n_pairs, res2)
+        if dom < 6:
+            ce = eq1_ceiling(args.workload, n_pairs, dom)
+            ce["achieved_over_ceiling"] = round(line["roofline"]["frac"] / ce["frac"], 4) \
+                if ce["frac"] else None
+            line["roofline"]["eq1_ceiling"] = ce
         gp = line["cpu_baseline"]["all_cores"].get("gpu_parity")
         if gp is not None:
             line["oracle_parity"] = {"pairs_compared": gp["pairs_compared"],

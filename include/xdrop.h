@@ -177,6 +177,27 @@ xd_status xdrop_extend(xd_ctx *ctx, const uint32_t *d_a, uint64_t a_words,
                        const xd_pair *d_pairs, size_t n_pairs, xd_scores scores,
                        xd_result *d_out, void *stream, const xd_opts *opts);
 
+/*
+ * The same batched extension with the diagonal step scored by a 4 x 4
+ * substitution table instead of match/mismatch (Section III-A's recurrence
+ * with the scoring generalised, as Section VIII proposes): aligning base p of
+ * A with base q of B (codes A=0 C=1 G=2 T=3) adds matrix[4*p + q]; gaps add
+ * `gap`.  matrix is a host array of 16 entries in [-2^20, 2^20], row-major by
+ * the base of A; gap in [-2^20, 0].  seed_score sums the table over the seed.
+ * Everything else -- pairs, results, seed split, readings, asynchrony,
+ * per-pair errors -- is as in xdrop_extend; the int32 guard uses the table's
+ * largest magnitude for both the match and the mismatch term.  Options: only
+ * sched, waves_per_cu and sort_jobs apply (graph, profile, multi_wave,
+ * min_tier and long_job give XD_EINVAL).  Bands up to 62 cells run one
+ * wavefront per job in registers; wider ones start over in the
+ * global-memory tier.
+ */
+xd_status xdrop_extend_matrix(xd_ctx *ctx, const uint32_t *d_a, uint64_t a_words,
+                              const uint32_t *d_b, uint64_t b_words,
+                              const xd_pair *d_pairs, size_t n_pairs,
+                              const int32_t *matrix, int32_t gap,
+                              xd_result *d_out, void *stream, const xd_opts *opts);
+
 /* Synchronous convenience: host arenas, pairs and results; copies in, runs
  * xdrop_extend on an internal stream, copies out. */
 xd_status xdrop_extend_host(xd_ctx *ctx, const uint32_t *a, uint64_t a_words,

@@ -51,6 +51,10 @@ struct Params {
   unsigned long long save_cap;     // pool size in save slots
   unsigned long long *save_top;    // next free slot (cleared per call)
   int32_t *job_save;               // per job: word offset of its slot, or -1
+  // Substitution table (xdrop_extend_matrix): lut[4 p + q] scores base p of
+  // A against base q of B; has_lut = 0 for match/mismatch scoring.
+  int32_t has_lut;
+  int32_t lut[16];
 };
 
 // Layout of one save: a header, then the W values of the latest even and odd

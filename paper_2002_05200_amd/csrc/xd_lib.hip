@@ -40,14 +40,17 @@
 #include "xd_wide.h"
 #include "xd_w2_asm.h"
 #include "xd_multi.h"
+#include "xd_matrix.h"
 
 namespace xd {
 
 constexpr int kBlock = 256;                 // 4 wavefronts, each its own job
 constexpr int kWavesPerBlock = kBlock / kWave;
 
-__global__ void k_reset(int32_t *counters, unsigned long long *stats, int32_t *bins) {
+__global__ void k_reset(int32_t *counters, unsigned long long *stats, int32_t *bins,
+                        uint32_t *dummy) {
   for (int i = threadIdx.x; i < 2 * kBins; i += blockDim.x) bins[i] = 0;   // counts, cursors
+  if (threadIdx.x < 16) dummy[threadIdx.x] = 0;   // the zero words of empty arenas
   if (threadIdx.x < kCounters) counters[threadIdx.x] = 0;
   if (threadIdx.x < kStats) stats[threadIdx.x] = 0;
 }
@@ -69,7 +72,7 @@ constexpr int kPlanBlock = 256;   // pairs per block of k_plan / k_scatter
 __global__ __launch_bounds__(kPlanBlock) void k_plan(
     const xd_pair *__restrict__ pairs, int64_t n_pairs, int64_t a_words, int64_t b_words,
     int32_t match, int32_t mismatch, int32_t gap, int32_t min_tier, int32_t by_cost,
-    int32_t long_job, int32_t long_bias, Job *__restrict__ jobs,
+    int32_t long_job, int32_t long_bias, int32_t max_tier, Job *__restrict__ jobs,
     int32_t *__restrict__ pair_status, int32_t *__restrict__ bin_of,
     int32_t *__restrict__ bin_count, int32_t *__restrict__ job_save) {
   __shared__ int32_t hist[kBins];
@@ -91,6 +94,8 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan(
     }
     if (tl < min_tier) tl = min_tier;
     if (tr < min_tier) tr = min_tier;
+    if (tl > max_tier) tl = max_tier;
+    if (tr > max_tier) tr = max_tier;
     const int32_t bl = job_bin(l, tl, by_cost != 0), br = job_bin(r, tr, by_cost != 0);
     bin_of[2 * p] = bl;
     bin_of[2 * p + 1] = br;
@@ -264,7 +269,8 @@ __global__ __launch_bounds__(kSortBlock) void k_esc_sort(const Job *__restrict__
 __global__ void k_combine(const xd_pair *__restrict__ pairs, int64_t n_pairs,
                           const int32_t *__restrict__ pair_status, const JobOut *__restrict__ outs,
                           const uint32_t *__restrict__ A, const uint32_t *__restrict__ B,
-                          int32_t match, int32_t mismatch, xd_result *__restrict__ res) {
+                          int32_t match, int32_t mismatch, Params P,
+                          xd_result *__restrict__ res) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_pairs) return;
   const xd_pair pr = pairs[p];
@@ -275,7 +281,7 @@ __global__ void k_combine(const xd_pair *__restrict__ pairs, int64_t n_pairs,
       const uint64_t ga = pr.a_off + pr.a_seed + t, gb = pr.b_off + pr.b_seed + t;
       const uint32_t ca = (A[ga >> 4] >> (2 * (ga & 15))) & 3u;
       const uint32_t cb = (B[gb >> 4] >> (2 * (gb & 15))) & 3u;
-      seed += (ca == cb) ? match : mismatch;
+      seed += P.has_lut ? P.lut[(ca << 2) | cb] : ((ca == cb) ? match : mismatch);
     }
   }
   xd_result out;
@@ -292,10 +298,17 @@ using namespace xd;
 
 namespace {
 
-thread_local std::string g_err;
+// Last error message of this thread, in a fixed buffer so that reporting an
+// error allocates nothing.
+thread_local char g_err[512];
 
-xd_status fail(xd_status s, const std::string &msg) {
-  g_err = msg;
+xd_status fail(xd_status s, const char *msg) {
+  std::snprintf(g_err, sizeof(g_err), "%s", msg);
+  return s;
+}
+xd_status fail(xd_status s, const std::string &msg) { return fail(s, msg.c_str()); }
+xd_status failw(xd_status s, const char *who, const char *msg) {
+  std::snprintf(g_err, sizeof(g_err), "%s: %s", who, msg);
   return s;
 }
 
@@ -306,27 +319,24 @@ xd_status fail(xd_status s, const std::string &msg) {
       return fail(XD_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_));   \
   } while (0)
 
-struct Scratch {
+struct HeapBlock {
   void *ptr = nullptr;
   size_t bytes = 0;
 };
 
-}  // namespace
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
-struct xd_ctx {
-  int device = 0;
-  size_t budget = 0;
-  int num_cu = 0;
-  Scratch scratch;
+// Device buffers of one call, carved from one block: per job the descriptor,
+// result, counting-sort bin and save-slot index; per pair the status; the
+// sort bins, the sorted order, the escalation lists, counters and statistics;
+// plus the escalation save pool and the global-memory band buffers.
+struct Bufs {
   int64_t cap_pairs = 0;
-  // carved from scratch
   Job *jobs = nullptr;
   JobOut *outs = nullptr;
   int32_t *pair_status = nullptr;
   int32_t *bin_of = nullptr;     // counting-sort bin of every job
   int32_t *job_save = nullptr;   // escalation save slot of every job (-1: none)
-  int32_t *save_pool = nullptr;  // escalation saves (separate allocation)
-  uint64_t save_slots = 0;
   int32_t *bins = nullptr;       // kBins counts, kBins cursors, kBins offsets
   int32_t *order = nullptr;
   int32_t *esc = nullptr;        // kLists + 1 lists of 2 * cap_pairs entries: escalations
@@ -334,11 +344,50 @@ struct xd_ctx {
                                  // into each tier, then the spill tier's second pass
   int32_t *counters = nullptr;   // kCounters
   unsigned long long *stats = nullptr;  // kStats
-  uint32_t *dummy = nullptr;     // one zero word for empty arenas
+  uint32_t *dummy = nullptr;     // one zero word for empty arenas (cleared by k_reset)
+  int32_t *save_pool = nullptr;  // escalation saves
+  uint64_t save_slots = 0;
+  SpillScratch spill;
+};
+
+// Lays the per-job buffers for cap_pairs pairs out from `base` (nullptr: only
+// measure); returns the bytes they take.
+size_t carve_jobs(Bufs &B, char *base, int64_t cap) {
+  const int64_t nj = 2 * cap;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return base ? base + at : nullptr;
+  };
+  B.cap_pairs = cap;
+  B.jobs = (Job *)take(sizeof(Job) * nj);
+  B.outs = (JobOut *)take(sizeof(JobOut) * nj);
+  B.pair_status = (int32_t *)take(sizeof(int32_t) * cap);
+  B.bin_of = (int32_t *)take(sizeof(int32_t) * nj);
+  B.job_save = (int32_t *)take(sizeof(int32_t) * nj);
+  B.bins = (int32_t *)take(sizeof(int32_t) * 3 * kBins);
+  B.order = (int32_t *)take(sizeof(int32_t) * nj);
+  B.esc = (int32_t *)take(sizeof(int32_t) * nj * (kLists + 2));
+  B.esc_sorted = B.esc ? B.esc + (kLists + 1) * nj : nullptr;
+  B.counters = (int32_t *)take(sizeof(int32_t) * kCounters);
+  B.stats = (unsigned long long *)take(sizeof(unsigned long long) * kStats);
+  B.dummy = (uint32_t *)take(64);
+  return off;
+}
+
+}  // namespace
+
+struct xd_ctx {
+  int device = 0;
+  size_t budget = 0;
+  int num_cu = 0;
+  HeapBlock heap;                  // the per-job buffers of `b`
+  Bufs b;                        // this context's own buffers
+  const Bufs *last = nullptr;    // buffers of the last call (statistics)
   hipEvent_t ev[10] = {};        // stage boundaries when profiling
   bool have_events = false;
   bool profiled = false;
-  SpillScratch spill;
   hipStream_t own_stream = nullptr;
   // graph of the last graph-mode call and the arguments it was captured for
   hipGraph_t graph = nullptr;
@@ -348,8 +397,6 @@ struct xd_ctx {
 };
 
 namespace {
-
-size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Escalation saves: one slot per job at most, 16 GiB at most, and under a
 // memory budget at most a quarter of it.
@@ -362,29 +409,20 @@ constexpr uint64_t kSavePoolMax = 16ull << 30;
 // the save pool what is left, at most a quarter; the total never exceeds the
 // budget.
 xd_status ensure_capacity(xd_ctx *c, int64_t n_pairs) {
-  if (n_pairs <= c->cap_pairs && c->scratch.ptr) return XD_OK;
+  Bufs &B = c->b;
+  if (n_pairs <= B.cap_pairs && c->heap.ptr) return XD_OK;
   int64_t cap = std::max<int64_t>(n_pairs, 1024);
-  if (c->cap_pairs > 0) cap = std::max<int64_t>(cap, c->cap_pairs * 3 / 2);
-  if (c->budget && cap > n_pairs) {   // growth headroom only while it fits
+  if (B.cap_pairs > 0) cap = std::max<int64_t>(cap, B.cap_pairs * 3 / 2);
+  if (c->budget && cap > n_pairs) {   // no growth headroom under a budget
     cap = std::max<int64_t>(n_pairs, 1);
   }
   const int64_t nj = 2 * cap;
-  size_t off = 0;
-  const size_t o_jobs = off; off = align_up(off + sizeof(Job) * nj);
-  const size_t o_outs = off; off = align_up(off + sizeof(JobOut) * nj);
-  const size_t o_stat = off; off = align_up(off + sizeof(int32_t) * cap);
-  const size_t o_binof = off; off = align_up(off + sizeof(int32_t) * nj);
-  const size_t o_jsave = off; off = align_up(off + sizeof(int32_t) * nj);
-  const size_t o_bins = off; off = align_up(off + sizeof(int32_t) * 3 * kBins);
-  const size_t o_order = off; off = align_up(off + sizeof(int32_t) * nj);
-  const size_t o_esc = off; off = align_up(off + sizeof(int32_t) * nj * (kLists + 2));
-  const size_t o_cnt = off; off = align_up(off + sizeof(int32_t) * kCounters);
-  const size_t o_stats = off; off = align_up(off + sizeof(unsigned long long) * kStats);
-  const size_t o_dummy = off; off = align_up(off + 64);
-  int64_t spill_cap = c->spill.huge ? c->spill.cap : kHugeCap;
+  Bufs probe;
+  const size_t off = carve_jobs(probe, nullptr, cap);
+  int64_t spill_cap = B.spill.huge ? B.spill.cap : kHugeCap;
   uint64_t pool_max = kSavePoolMax;
   if (c->budget) {
-    if (!c->spill.huge) {
+    if (!B.spill.huge) {
       const int64_t fit = (int64_t)(c->budget / 8 / spill_bytes(1));
       spill_cap = std::max<int64_t>(kHugeCapMin, std::min<int64_t>(kHugeCap, fit));
     }
@@ -393,66 +431,53 @@ xd_status ensure_capacity(xd_ctx *c, int64_t n_pairs) {
       return fail(XD_ENOMEM, "scratch for " + std::to_string(n_pairs) + " pairs exceeds the budget");
     pool_max = std::min<uint64_t>(c->budget / 4, c->budget - fixed);
   }
-  if (c->scratch.ptr) {
+  if (c->heap.ptr) {
     XD_HIP(hipDeviceSynchronize());
-    XD_HIP(hipFree(c->scratch.ptr));
-    c->scratch.ptr = nullptr;
-    c->scratch.bytes = 0;
+    XD_HIP(hipFree(c->heap.ptr));
+    c->heap.ptr = nullptr;
+    c->heap.bytes = 0;
+    B.cap_pairs = 0;
   }
   void *p = nullptr;
   if (hipMalloc(&p, off) != hipSuccess) return fail(XD_ENOMEM, "hipMalloc of job scratch failed");
-  c->scratch.ptr = p;
-  c->scratch.bytes = off;
-  if (!c->spill.huge && spill_alloc(&c->spill, spill_cap) != XD_OK)
+  c->heap.ptr = p;
+  c->heap.bytes = off;
+  if (!B.spill.huge && spill_alloc(&B.spill, spill_cap) != XD_OK)
     return fail(XD_ENOMEM, "hipMalloc of the global-memory band buffers failed");
   {   // escalation saves
     const uint64_t want = std::min<uint64_t>((uint64_t)nj, pool_max / kSaveSlotBytes);
-    if (want > c->save_slots || (c->budget && c->save_slots > want)) {
-      if (c->save_pool) XD_HIP(hipFree(c->save_pool));
-      c->save_pool = nullptr;
-      c->save_slots = 0;
+    if (want > B.save_slots || (c->budget && B.save_slots > want)) {
+      if (B.save_pool) XD_HIP(hipFree(B.save_pool));
+      B.save_pool = nullptr;
+      B.save_slots = 0;
       void *sp = nullptr;
-      if (hipMalloc(&sp, sizeof(int32_t) * kSaveSlotWords * want) == hipSuccess) {
-        c->save_pool = (int32_t *)sp;
-        c->save_slots = want;
+      if (hipMalloc(&sp, kSaveSlotBytes * want) == hipSuccess) {
+        B.save_pool = (int32_t *)sp;
+        B.save_slots = want;
       }   // else: escalated jobs restart from scratch
     }
   }
-  char *b = (char *)p;
-  c->jobs = (Job *)(b + o_jobs);
-  c->outs = (JobOut *)(b + o_outs);
-  c->pair_status = (int32_t *)(b + o_stat);
-  c->bin_of = (int32_t *)(b + o_binof);
-  c->job_save = (int32_t *)(b + o_jsave);
-  c->bins = (int32_t *)(b + o_bins);
-  c->order = (int32_t *)(b + o_order);
-  c->esc = (int32_t *)(b + o_esc);
-  c->esc_sorted = c->esc + (kLists + 1) * nj;
-  c->counters = (int32_t *)(b + o_cnt);
-  c->stats = (unsigned long long *)(b + o_stats);
-  c->dummy = (uint32_t *)(b + o_dummy);
-  XD_HIP(hipMemset(c->dummy, 0, 64));
-  c->cap_pairs = cap;
+  carve_jobs(B, (char *)p, cap);
   return XD_OK;
 }
 
 template <int C, bool NARROW>
-hipError_t launch_tier(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_cu,
+hipError_t launch_tier(xd_ctx *c, const Bufs &B, hipStream_t s, bool persistent, int waves_per_cu,
                        int64_t max_jobs, int tier, const Params &P, int multi_wave) {
-  const int64_t stride = 2 * c->cap_pairs;
+  const int64_t stride = 2 * B.cap_pairs;
   TierQueue q;
-  q.order = c->order;
-  q.esc = c->esc + tier * stride;
-  q.counters = c->counters;
-  q.next_esc = c->esc + (tier + 1) * stride;
+  q.order = B.order;
+  q.esc = B.esc + tier * stride;
+  q.counters = B.counters;
+  q.next_esc = B.esc + (tier + 1) * stride;
   q.tier = tier;
-  int32_t *head = persistent ? c->counters + kHead + tier : nullptr;
+  int32_t *head = persistent ? B.counters + kHead + tier : nullptr;
   if (tier > 0) {   // escalated jobs, longest remainder first
-    hipLaunchKernelGGL(k_esc_sort, dim3(1), dim3(kSortBlock), 0, s, c->jobs, q.esc,
-                       c->esc_sorted, c->counters, tier, P);
+    hipLaunchKernelGGL(k_esc_sort, dim3(1), dim3(kSortBlock), 0, s, B.jobs, q.esc,
+                       B.esc_sorted, B.counters, tier, P);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    q.esc = c->esc_sorted;
+    q.esc = B.esc_sorted;
   }
   if constexpr (C >= 8) {
     if (multi_wave != 0) {   // NW wavefronts per job, C / NW registers each
@@ -462,8 +487,8 @@ hipError_t launch_tier(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_
             persistent ? ((int64_t)c->num_cu * waves_per_cu + NW - 1) / NW : max_jobs;
         if (groups < 1) groups = 1;
         hipLaunchKernelGGL((k_extend_mw<NW, C / NW, NARROW>), dim3((unsigned)groups),
-                           dim3(64 * NW), 0, s, c->jobs, q, head, c->outs, c->stats, P,
-                           q.next_esc, c->counters + kEsc + tier + 1);
+                           dim3(64 * NW), 0, s, B.jobs, q, head, B.outs, B.stats, P,
+                           q.next_esc, B.counters + kEsc + tier + 1);
         return hipGetLastError();
       };
       return multi_wave == 2 ? launch_mw(std::integral_constant<int, 2>())
@@ -477,13 +502,13 @@ hipError_t launch_tier(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_
     blocks = (max_jobs + kWavesPerBlock - 1) / kWavesPerBlock;
   }
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((k_extend<C, NARROW>), dim3((unsigned)blocks), dim3(kBlock), 0, s, c->jobs,
-                     q, head, c->outs, c->stats, P);
+  hipLaunchKernelGGL((k_extend<C, NARROW>), dim3((unsigned)blocks), dim3(kBlock), 0, s, B.jobs,
+                     q, head, B.outs, B.stats, P);
   return hipGetLastError();
 }
 
 template <bool NARROW>
-hipError_t launch_tiers(xd_ctx *c, hipStream_t s, bool persistent, int waves_per_cu,
+hipError_t launch_tiers(xd_ctx *c, const Bufs &B, hipStream_t s, bool persistent, int waves_per_cu,
                         int64_t nj, const Params &P, bool prof, int mw) {
   // waves per CU: each tier's resident limit from its register footprint
   // (4 SIMDs x waves per SIMD: 7, 5, 7, 5, 3, 1 for C = 1 .. 32), rounded up
@@ -492,17 +517,17 @@ hipError_t launch_tiers(xd_ctx *c, hipStream_t s, bool persistent, int waves_per
   auto w = [&](int t) { return waves_per_cu > 0 ? waves_per_cu : wpc[t]; };
   hipError_t e;
   auto mark = [&](int i) { return prof ? hipEventRecord(c->ev[i], s) : hipSuccess; };
-  if ((e = launch_tier<1, NARROW>(c, s, persistent, w(0), nj, 0, P, mw)) != hipSuccess) return e;
+  if ((e = launch_tier<1, NARROW>(c, B, s, persistent, w(0), nj, 0, P, mw)) != hipSuccess) return e;
   if ((e = mark(2)) != hipSuccess) return e;
-  if ((e = launch_tier<2, NARROW>(c, s, persistent, w(1), nj, 1, P, mw)) != hipSuccess) return e;
+  if ((e = launch_tier<2, NARROW>(c, B, s, persistent, w(1), nj, 1, P, mw)) != hipSuccess) return e;
   if ((e = mark(3)) != hipSuccess) return e;
-  if ((e = launch_tier<4, NARROW>(c, s, persistent, w(2), nj, 2, P, mw)) != hipSuccess) return e;
+  if ((e = launch_tier<4, NARROW>(c, B, s, persistent, w(2), nj, 2, P, mw)) != hipSuccess) return e;
   if ((e = mark(4)) != hipSuccess) return e;
-  if ((e = launch_tier<8, NARROW>(c, s, persistent, w(3), nj, 3, P, mw)) != hipSuccess) return e;
+  if ((e = launch_tier<8, NARROW>(c, B, s, persistent, w(3), nj, 3, P, mw)) != hipSuccess) return e;
   if ((e = mark(5)) != hipSuccess) return e;
-  if ((e = launch_tier<16, NARROW>(c, s, persistent, w(4), nj, 4, P, mw)) != hipSuccess) return e;
+  if ((e = launch_tier<16, NARROW>(c, B, s, persistent, w(4), nj, 4, P, mw)) != hipSuccess) return e;
   if ((e = mark(6)) != hipSuccess) return e;
-  if ((e = launch_tier<32, NARROW>(c, s, persistent, w(5), nj, 5, P, mw)) != hipSuccess) return e;
+  if ((e = launch_tier<32, NARROW>(c, B, s, persistent, w(5), nj, 5, P, mw)) != hipSuccess) return e;
   return mark(7);
 }
 
@@ -525,15 +550,15 @@ struct Launch {
 
 // Enqueues the whole launch sequence of one call on s (kernels and, when
 // profiling, event records only).
-xd_status enqueue(xd_ctx *c, hipStream_t s, const Launch &L, bool prof) {
+xd_status enqueue(xd_ctx *c, const Bufs &B, hipStream_t s, const Launch &L, bool prof) {
   const xd_opts &o = L.o;
   const xd_scores &sc = L.sc;
   const size_t n_pairs = L.n_pairs;
   const bool persistent = (o.sched != XD_SCHED_PLAIN);
   const int64_t nj = 2 * (int64_t)n_pairs;
   Params P;
-  P.A = L.a_words ? L.d_a : c->dummy;
-  P.B = L.b_words ? L.d_b : c->dummy;
+  P.A = L.a_words ? L.d_a : B.dummy;
+  P.B = L.b_words ? L.d_b : B.dummy;
   P.a_words = L.a_words ? (int64_t)L.a_words : 1;
   P.b_words = L.b_words ? (int64_t)L.b_words : 1;
   P.neg_gap = -sc.gap;
@@ -542,70 +567,145 @@ xd_status enqueue(xd_ctx *c, hipStream_t s, const Launch &L, bool prof) {
   P.pat = (int32_t)((uint32_t)P.delta * 0x55555555u);
   P.impl = o.impl;
   P.unit_match = sc.match == 1;
-  P.save_pool = c->save_pool;
-  P.save_cap = c->save_slots;
+  P.save_pool = B.save_pool;
+  P.save_cap = B.save_slots;
   if (o.max_save_slots > 0 && (uint64_t)o.max_save_slots < P.save_cap)
     P.save_cap = (uint64_t)o.max_save_slots;
-  P.save_top = c->stats + kSaveTop;
-  P.job_save = c->job_save;
+  P.save_top = B.stats + kSaveTop;
+  P.job_save = B.job_save;
+  P.has_lut = 0;
+  for (int t = 0; t < 16; ++t) P.lut[t] = 0;
   const bool narrow = P.delta <= 3;
 
   if (prof) XD_HIP(hipEventRecord(c->ev[0], s));
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, c->counters, c->stats, c->bins);
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, B.counters, B.stats, B.bins, B.dummy);
   XD_HIP(hipGetLastError());
-  const int64_t stride = 2 * c->cap_pairs;
+  const int64_t stride = 2 * B.cap_pairs;
   const bool by_cost = persistent && o.sort_jobs != 0;
-  int32_t *bin_count = c->bins, *bin_cursor = c->bins + kBins, *bin_off = c->bins + 2 * kBins;
+  int32_t *bin_count = B.bins, *bin_cursor = B.bins + kBins, *bin_off = B.bins + 2 * kBins;
   const unsigned plan_blocks = (unsigned)((n_pairs + kPlanBlock - 1) / kPlanBlock);
   hipLaunchKernelGGL(k_plan, dim3(plan_blocks), dim3(kPlanBlock), 0, s, L.d_pairs,
                      (int64_t)n_pairs, (int64_t)P.a_words, (int64_t)P.b_words, sc.match,
                      sc.mismatch, sc.gap, o.min_tier, (int32_t)by_cost, o.long_job,
-                     o.long_tier_bias, c->jobs, c->pair_status, c->bin_of, bin_count,
-                     c->job_save);
+                     o.long_tier_bias, (int32_t)kSpillTier, B.jobs, B.pair_status, B.bin_of, bin_count,
+                     B.job_save);
   XD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanBlock), 0, s, bin_count, bin_off, c->counters);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanBlock), 0, s, bin_count, bin_off, B.counters);
   XD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_scatter, dim3(plan_blocks), dim3(kPlanBlock), 0, s, c->bin_of, nj,
-                     bin_off, bin_cursor, c->order);
+  hipLaunchKernelGGL(k_scatter, dim3(plan_blocks), dim3(kPlanBlock), 0, s, B.bin_of, nj,
+                     bin_off, bin_cursor, B.order);
   XD_HIP(hipGetLastError());
   if (prof) XD_HIP(hipEventRecord(c->ev[1], s));
   const int mw = o.multi_wave;
-  hipError_t e = narrow ? launch_tiers<true>(c, s, persistent, o.waves_per_cu, nj, P, prof, mw)
-                        : launch_tiers<false>(c, s, persistent, o.waves_per_cu, nj, P, prof, mw);
+  hipError_t e = narrow ? launch_tiers<true>(c, B, s, persistent, o.waves_per_cu, nj, P, prof, mw)
+                        : launch_tiers<false>(c, B, s, persistent, o.waves_per_cu, nj, P, prof, mw);
   if (e != hipSuccess) return fail(XD_EDEVICE, std::string("k_extend: ") + hipGetErrorString(e));
   {   // bands wider than one wavefront: a workgroup per job, then global memory
     TierQueue q;
-    q.order = c->order;
-    q.counters = c->counters;
+    q.order = B.order;
+    q.counters = B.counters;
     q.next_esc = nullptr;
     q.tier = kTiers;
-    hipLaunchKernelGGL(k_esc_sort, dim3(1), dim3(kSortBlock), 0, s, c->jobs,
-                       c->esc + kTiers * stride, c->esc_sorted, c->counters, kTiers, P);
+    hipLaunchKernelGGL(k_esc_sort, dim3(1), dim3(kSortBlock), 0, s, B.jobs,
+                       B.esc + kTiers * stride, B.esc_sorted, B.counters, kTiers, P);
     XD_HIP(hipGetLastError());
-    q.esc = c->esc_sorted;
-    int32_t *huge_list = c->esc + kLists * stride;
+    q.esc = B.esc_sorted;
+    int32_t *huge_list = B.esc + kLists * stride;
     // 8,192 slots: 8 wavefronts of 16 registers (measured faster than 16 of 8:
     // fewer waves take part in each anti-diagonal's barrier and reduction)
     constexpr int kHugeNW = 8, kHugeC = 16;
     if (narrow)
       hipLaunchKernelGGL((k_extend_mw<kHugeNW, kHugeC, true>), dim3((unsigned)c->num_cu),
-                         dim3(64 * kHugeNW), 0, s, c->jobs, q, c->counters + kHead + kTiers,
-                         c->outs, c->stats, P, huge_list, c->counters + kHugeCount);
+                         dim3(64 * kHugeNW), 0, s, B.jobs, q, B.counters + kHead + kTiers,
+                         B.outs, B.stats, P, huge_list, B.counters + kHugeCount);
     else
       hipLaunchKernelGGL((k_extend_mw<kHugeNW, kHugeC, false>), dim3((unsigned)c->num_cu),
-                         dim3(64 * kHugeNW), 0, s, c->jobs, q, c->counters + kHead + kTiers,
-                         c->outs, c->stats, P, huge_list, c->counters + kHugeCount);
+                         dim3(64 * kHugeNW), 0, s, B.jobs, q, B.counters + kHead + kTiers,
+                         B.outs, B.stats, P, huge_list, B.counters + kHugeCount);
     XD_HIP(hipGetLastError());
-    if (spill_launch(&c->spill, s, c->jobs, q, c->counters + kHugeHead, huge_list,
-                     c->counters + kHugeCount, c->outs, c->stats, P) != XD_OK)
+    if (spill_launch(&B.spill, s, B.jobs, q, B.counters + kHugeHead, huge_list,
+                     B.counters + kHugeCount, B.outs, B.stats, P) != XD_OK)
       return fail(XD_EDEVICE, "k_spill launch failed");
   }
   if (prof) XD_HIP(hipEventRecord(c->ev[8], s));
   hipLaunchKernelGGL(k_combine, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s,
-                     L.d_pairs, (int64_t)n_pairs, c->pair_status, c->outs, P.A, P.B, sc.match,
-                     sc.mismatch, L.d_out);
+                     L.d_pairs, (int64_t)n_pairs, B.pair_status, B.outs, P.A, P.B, sc.match,
+                     sc.mismatch, P, L.d_out);
   XD_HIP(hipGetLastError());
   if (prof) XD_HIP(hipEventRecord(c->ev[9], s));
+  return XD_OK;
+}
+
+// Enqueues a substitution-table call: planning (every job in the first
+// tier), the one-wavefront table kernel, two global-memory passes for the
+// bands it cannot hold (many workgroups with a share of the band buffers
+// each, then the few with the whole buffers), and the pair combine.
+xd_status enqueue_matrix(xd_ctx *c, const Bufs &B, hipStream_t s, const Launch &L,
+                         const int32_t *table, int32_t gap) {
+  const xd_opts &o = L.o;
+  const size_t n_pairs = L.n_pairs;
+  const int64_t nj = 2 * (int64_t)n_pairs;
+  int32_t maxabs = 0;
+  for (int t = 0; t < 16; ++t) maxabs = std::max(maxabs, table[t] < 0 ? -table[t] : table[t]);
+  Params P;
+  std::memset(&P, 0, sizeof(P));
+  P.A = L.a_words ? L.d_a : B.dummy;
+  P.B = L.b_words ? L.d_b : B.dummy;
+  P.a_words = L.a_words ? (int64_t)L.a_words : 1;
+  P.b_words = L.b_words ? (int64_t)L.b_words : 1;
+  P.neg_gap = -gap;
+  P.base = 0;
+  P.delta = 0;
+  P.save_pool = nullptr;
+  P.save_top = B.stats + kSaveTop;
+  P.job_save = B.job_save;
+  P.has_lut = 1;
+  for (int t = 0; t < 16; ++t) P.lut[t] = table[t];
+
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, B.counters, B.stats, B.bins, B.dummy);
+  XD_HIP(hipGetLastError());
+  const int64_t stride = 2 * B.cap_pairs;
+  int32_t *bin_count = B.bins, *bin_cursor = B.bins + kBins, *bin_off = B.bins + 2 * kBins;
+  const unsigned plan_blocks = (unsigned)((n_pairs + kPlanBlock - 1) / kPlanBlock);
+  // the int32 guard with the table's largest magnitude in place of both
+  // match and mismatch; every job planned into the first tier
+  hipLaunchKernelGGL(k_plan, dim3(plan_blocks), dim3(kPlanBlock), 0, s, L.d_pairs,
+                     (int64_t)n_pairs, (int64_t)P.a_words, (int64_t)P.b_words, maxabs, maxabs,
+                     gap, 0, (int32_t)(o.sort_jobs != 0), 0, 0, 0, B.jobs, B.pair_status,
+                     B.bin_of, bin_count, B.job_save);
+  XD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanBlock), 0, s, bin_count, bin_off, B.counters);
+  XD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_scatter, dim3(plan_blocks), dim3(kPlanBlock), 0, s, B.bin_of, nj,
+                     bin_off, bin_cursor, B.order);
+  XD_HIP(hipGetLastError());
+  TierQueue q;
+  q.order = B.order;
+  q.esc = nullptr;
+  q.counters = B.counters;
+  q.next_esc = nullptr;
+  q.tier = 0;
+  int32_t *wider = B.esc + stride, *wider_count = B.counters + kEsc + 1;
+  // persistent: CUs x waves_per_cu waves popping the queue; plain: one
+  // wavefront per job
+  const int wpc = o.waves_per_cu > 0 ? o.waves_per_cu : 32;
+  const int64_t waves = o.sched == XD_SCHED_PLAIN ? nj : (int64_t)c->num_cu * wpc;
+  const int64_t blocks = std::max<int64_t>(1, (waves + kWavesPerBlock - 1) / kWavesPerBlock);
+  hipLaunchKernelGGL(k_extend_matrix, dim3((unsigned)blocks), dim3(kBlock), 0, s, B.jobs, q,
+                     B.counters + kHead, B.outs, B.stats, P, wider, wider_count);
+  XD_HIP(hipGetLastError());
+  TierQueue q6 = q;
+  q6.tier = kTiers;
+  int32_t *huge_list = B.esc + kLists * stride;
+  if (spill_launch(&B.spill, s, B.jobs, q6, B.counters + kHead + 1, wider, wider_count, B.outs,
+                   B.stats, P, c->num_cu, huge_list, B.counters + kHugeCount) != XD_OK ||
+      spill_launch(&B.spill, s, B.jobs, q6, B.counters + kHugeHead, huge_list,
+                   B.counters + kHugeCount, B.outs, B.stats, P) != XD_OK)
+    return fail(XD_EDEVICE, "k_spill launch failed");
+  hipLaunchKernelGGL(k_combine, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s,
+                     L.d_pairs, (int64_t)n_pairs, B.pair_status, B.outs, P.A, P.B, 0, 0, P,
+                     L.d_out);
+  XD_HIP(hipGetLastError());
   return XD_OK;
 }
 
@@ -613,7 +713,7 @@ xd_status enqueue(xd_ctx *c, hipStream_t s, const Launch &L, bool prof) {
 
 extern "C" {
 
-const char *xd_last_error(void) { return g_err.c_str(); }
+const char *xd_last_error(void) { return g_err; }
 
 xd_status xd_pack(const char *ascii, size_t n, uint32_t *words) {
   if ((!ascii && n) || (!words && n)) return fail(XD_EINVAL, "xd_pack: null pointer");
@@ -670,8 +770,8 @@ xd_status xd_ctx_create(int device, size_t mem_budget, xd_ctx **out) {
 
 xd_status xd_ctx_memory(const xd_ctx *c, uint64_t *bytes) {
   if (!c || !bytes) return fail(XD_EINVAL, "xd_ctx_memory: null pointer");
-  *bytes = (uint64_t)c->scratch.bytes + (c->spill.huge ? spill_bytes(c->spill.cap) : 0) +
-           c->save_slots * kSaveSlotBytes;
+  *bytes = (uint64_t)c->heap.bytes + (c->b.spill.huge ? spill_bytes(c->b.spill.cap) : 0) +
+           c->b.save_slots * kSaveSlotBytes;
   return XD_OK;
 }
 
@@ -681,49 +781,70 @@ void xd_ctx_destroy(xd_ctx *c) {
   (void)hipDeviceSynchronize();
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
-  if (c->scratch.ptr) (void)hipFree(c->scratch.ptr);
-  if (c->save_pool) (void)hipFree(c->save_pool);
-  spill_free(&c->spill);
+  if (c->heap.ptr) (void)hipFree(c->heap.ptr);
+  if (c->b.save_pool) (void)hipFree(c->b.save_pool);
+  spill_free(&c->b.spill);
   if (c->have_events)
     for (int i = 0; i < 10; ++i) (void)hipEventDestroy(c->ev[i]);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
 }
 
-xd_status xdrop_extend(xd_ctx *c, const uint32_t *d_a, uint64_t a_words, const uint32_t *d_b,
-                       uint64_t b_words, const xd_pair *d_pairs, size_t n_pairs,
-                       xd_scores sc, xd_result *d_out, void *stream, const xd_opts *opts) {
-  if (!c) return fail(XD_EINVAL, "xdrop_extend: null context");
+}  // extern "C"
+
+namespace {
+
+// Validation shared by the batch entry points; fills *o (NULL opts = the
+// defaults).  XD_OK with n_pairs == 0 means there is nothing to do.
+xd_status check_call(const char *who, const xd_ctx *c, const uint32_t *d_a, uint64_t a_words,
+                     const uint32_t *d_b, uint64_t b_words, const xd_pair *d_pairs,
+                     size_t n_pairs, xd_scores sc, const xd_result *d_out, void *stream,
+                     const xd_opts *opts, xd_opts *o) {
+  if (!c) return failw(XD_EINVAL, who, "null context");
   if (n_pairs == 0) return XD_OK;
-  if (!d_pairs || !d_out) return fail(XD_EINVAL, "xdrop_extend: null pairs or results");
-  if ((!d_a && a_words) || (!d_b && b_words)) return fail(XD_EINVAL, "xdrop_extend: null arena");
-  if (n_pairs > (size_t(1) << 29)) return fail(XD_EINVAL, "xdrop_extend: too many pairs");
+  if (!d_pairs || !d_out) return failw(XD_EINVAL, who, "null pairs or results");
+  if ((!d_a && a_words) || (!d_b && b_words)) return failw(XD_EINVAL, who, "null arena");
+  if (n_pairs > (size_t(1) << 29)) return failw(XD_EINVAL, who, "too many pairs");
   if (sc.match < sc.mismatch)
-    return fail(XD_EINVAL, "xdrop_extend: mismatch score above match score");
+    return failw(XD_EINVAL, who, "mismatch score above match score");
   const int64_t base = (int64_t)sc.mismatch - 2 * (int64_t)sc.gap;
   const int64_t delta = (int64_t)sc.match - (int64_t)sc.mismatch;
   if (base < -128 || base > 127 || delta > 255 || sc.gap > 0 || sc.gap < -(1 << 20))
-    return fail(XD_EINVAL, "xdrop_extend: unsupported score set");
+    return failw(XD_EINVAL, who, "unsupported score set");
+  std::memset(o, 0, sizeof(*o));
+  if (opts) *o = *opts;
+  else o->sort_jobs = 1;
+  if (o->sched < 0 || o->sched > XD_SCHED_PERSISTENT)
+    return failw(XD_EINVAL, who, "sched out of range");
+  if (o->min_tier < 0 || o->min_tier > kTiers)
+    return failw(XD_EINVAL, who, "min_tier out of range");
+  if (o->impl < 0 || o->impl > 1) return failw(XD_EINVAL, who, "impl out of range");
+  if (o->long_job < 0 || o->long_tier_bias < 0 || o->long_tier_bias >= kTiers)
+    return failw(XD_EINVAL, who, "long_job / long_tier_bias out of range");
+  if (o->multi_wave < 0 || o->multi_wave > 2)
+    return failw(XD_EINVAL, who, "multi_wave out of range");
+  if (o->waves_per_cu < 0 || o->waves_per_cu > 64)
+    return failw(XD_EINVAL, who, "waves_per_cu out of range");
+  if (o->max_save_slots < 0 || o->reserved != 0)
+    return failw(XD_EINVAL, who, "max_save_slots negative or reserved field set");
+  if (o->graph && o->profile) return failw(XD_EINVAL, who, "graph and profile together");
+  if (o->graph && !stream)
+    return failw(XD_EINVAL, who, "graph mode needs a non-NULL stream");
+  return XD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+xd_status xdrop_extend(xd_ctx *c, const uint32_t *d_a, uint64_t a_words, const uint32_t *d_b,
+                       uint64_t b_words, const xd_pair *d_pairs, size_t n_pairs,
+                       xd_scores sc, xd_result *d_out, void *stream, const xd_opts *opts) {
   xd_opts o;
-  std::memset(&o, 0, sizeof(o));
-  if (opts) o = *opts;
-  else o.sort_jobs = 1;
-  if (o.sched < 0 || o.sched > XD_SCHED_PERSISTENT)
-    return fail(XD_EINVAL, "xdrop_extend: sched out of range");
-  if (o.min_tier < 0 || o.min_tier > kTiers)
-    return fail(XD_EINVAL, "xdrop_extend: min_tier out of range");
-  if (o.impl < 0 || o.impl > 1) return fail(XD_EINVAL, "xdrop_extend: impl out of range");
-  if (o.long_job < 0 || o.long_tier_bias < 0 || o.long_tier_bias >= kTiers)
-    return fail(XD_EINVAL, "xdrop_extend: long_job / long_tier_bias out of range");
-  if (o.multi_wave < 0 || o.multi_wave > 2)
-    return fail(XD_EINVAL, "xdrop_extend: multi_wave out of range");
-  if (o.waves_per_cu < 0 || o.waves_per_cu > 64)
-    return fail(XD_EINVAL, "xdrop_extend: waves_per_cu out of range");
-  if (o.max_save_slots < 0 || o.reserved != 0)
-    return fail(XD_EINVAL, "xdrop_extend: max_save_slots negative or reserved field set");
+  const xd_status chk = check_call("xdrop_extend", c, d_a, a_words, d_b, b_words, d_pairs,
+                                   n_pairs, sc, d_out, stream, opts, &o);
+  if (chk != XD_OK || n_pairs == 0) return chk;
   const bool graph = o.graph != 0;
-  if (graph && o.profile) return fail(XD_EINVAL, "xdrop_extend: graph and profile together");
-  if (graph && !stream) return fail(XD_EINVAL, "xdrop_extend: graph mode needs a non-NULL stream");
 
   std::lock_guard<std::mutex> lock(c->mu);
   XD_HIP(hipSetDevice(c->device));
@@ -736,22 +857,23 @@ xd_status xdrop_extend(xd_ctx *c, const uint32_t *d_a, uint64_t a_words, const u
     c->have_events = true;
   }
   c->profiled = prof;
+  c->last = &c->b;
   Launch L;
   std::memset(&L, 0, sizeof(L));   // padding too: the struct is compared bytewise
   L.d_a = d_a; L.a_words = a_words; L.d_b = d_b; L.b_words = b_words;
   L.d_pairs = d_pairs; L.n_pairs = n_pairs; L.sc = sc; L.d_out = d_out; L.o = o;
-  if (!graph) return enqueue(c, s, L, prof);
+  if (!graph) return enqueue(c, c->b, s, L, prof);
 
   // graph mode: replay while every argument (and the scratch) is unchanged
   std::vector<uint8_t> sig(sizeof(L) + sizeof(void *));
   std::memcpy(sig.data(), &L, sizeof(L));
-  std::memcpy(sig.data() + sizeof(L), &c->scratch.ptr, sizeof(void *));
+  std::memcpy(sig.data() + sizeof(L), &c->heap.ptr, sizeof(void *));
   if (!c->graph_exec || sig != c->graph_sig) {
     if (c->graph_exec) { XD_HIP(hipGraphExecDestroy(c->graph_exec)); c->graph_exec = nullptr; }
     if (c->graph) { XD_HIP(hipGraphDestroy(c->graph)); c->graph = nullptr; }
     c->graph_sig.clear();
     XD_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    st = enqueue(c, s, L, false);
+    st = enqueue(c, c->b, s, L, false);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s, &g);
     if (st != XD_OK || e != hipSuccess) {
@@ -830,14 +952,44 @@ xd_status xdrop_extend_host(xd_ctx *c, const uint32_t *a, uint64_t a_words, cons
   return st;
 }
 
+xd_status xdrop_extend_matrix(xd_ctx *c, const uint32_t *d_a, uint64_t a_words,
+                              const uint32_t *d_b, uint64_t b_words, const xd_pair *d_pairs,
+                              size_t n_pairs, const int32_t *matrix, int32_t gap,
+                              xd_result *d_out, void *stream, const xd_opts *opts) {
+  static const char *who = "xdrop_extend_matrix";
+  xd_opts o;
+  xd_scores plain_scores = {0, 0, 0};
+  const xd_status chk = check_call(who, c, d_a, a_words, d_b, b_words, d_pairs, n_pairs,
+                                   plain_scores, d_out, stream, opts, &o);
+  if (chk != XD_OK || n_pairs == 0) return chk;
+  if (!matrix) return failw(XD_EINVAL, who, "null matrix");
+  for (int t = 0; t < 16; ++t)
+    if (matrix[t] > (1 << 20) || matrix[t] < -(1 << 20))
+      return failw(XD_EINVAL, who, "matrix entry outside [-2^20, 2^20]");
+  if (gap > 0 || gap < -(1 << 20)) return failw(XD_EINVAL, who, "gap outside [-2^20, 0]");
+  if (o.graph || o.profile || o.multi_wave || o.min_tier || o.long_job)
+    return failw(XD_EINVAL, who, "only the sched, waves_per_cu and sort_jobs options apply");
+  std::lock_guard<std::mutex> lock(c->mu);
+  XD_HIP(hipSetDevice(c->device));
+  xd_status st = ensure_capacity(c, (int64_t)n_pairs);
+  if (st != XD_OK) return st;
+  c->profiled = false;
+  c->last = &c->b;
+  Launch L;
+  std::memset(&L, 0, sizeof(L));
+  L.d_a = d_a; L.a_words = a_words; L.d_b = d_b; L.b_words = b_words;
+  L.d_pairs = d_pairs; L.n_pairs = n_pairs; L.d_out = d_out; L.o = o;
+  return enqueue_matrix(c, c->b, (hipStream_t)stream, L, matrix, gap);
+}
+
 xd_status xd_last_stats(xd_ctx *c, xd_stats *out) {
   if (!c || !out) return fail(XD_EINVAL, "xd_last_stats: null pointer");
   std::memset(out, 0, sizeof(*out));
-  if (!c->stats) return XD_OK;
+  if (!c->last || !c->last->stats) return XD_OK;
   unsigned long long h[kStats];
   XD_HIP(hipSetDevice(c->device));
   XD_HIP(hipDeviceSynchronize());
-  XD_HIP(hipMemcpy(h, c->stats, sizeof(h), hipMemcpyDeviceToHost));
+  XD_HIP(hipMemcpy(h, c->last->stats, sizeof(h), hipMemcpyDeviceToHost));
   for (int t = 0; t < kLists; ++t) {
     out->jobs[t] = h[t];
     out->cells[t] = h[kLists + t];

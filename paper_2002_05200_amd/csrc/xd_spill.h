@@ -31,7 +31,7 @@ struct SpillScratch {
   int64_t cap = 0;
 };
 
-inline uint64_t spill_bytes(int64_t cap) { return sizeof(int32_t) * 3 * (uint64_t)cap * kHugeSlots; }
+constexpr uint64_t spill_bytes(int64_t cap) { return sizeof(int32_t) * 3 * (uint64_t)cap * kHugeSlots; }
 
 // Where a spill pass takes its jobs from: a tier queue, or a plain list.
 struct SpillSource {
@@ -51,17 +51,19 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(const Job *__restrict__
                                                          SpillSource src,
                                                          int32_t *head, JobOut *__restrict__ outs,
                                                          unsigned long long *stats, Params P,
-                                                         int32_t *__restrict__ scratch) {
+                                                         int32_t *__restrict__ band) {
   __shared__ int32_t s_job;
   __shared__ int32_t s_first, s_last, s_max, s_imax;
+  __shared__ int32_t s_lut[16];
   const int tid = threadIdx.x;
+  if (tid < 16) s_lut[tid] = P.lut[tid];
   const TierQueue &q = src.q;
   const int32_t n_init = src.list ? 0 : q.counters[kInit + q.tier];
   const int32_t n_esc = src.list ? *src.list_count : q.counters[kEsc + q.tier];
   const int32_t count = n_init + n_esc;
   const int64_t cap = src.cap;
   int32_t *bufs[3];
-  for (int t = 0; t < 3; ++t) bufs[t] = scratch + ((int64_t)blockIdx.x * 3 + t) * cap;
+  for (int t = 0; t < 3; ++t) bufs[t] = band + ((int64_t)blockIdx.x * 3 + t) * cap;
   const int32_t gap = -P.neg_gap;
   const int32_t mismatch = P.base + 2 * gap;
   const int32_t match = mismatch + P.delta;
@@ -105,7 +107,9 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(const Job *__restrict__
           if (p != kNeg) {
             const uint32_t ca = base_at(P.A, job.a_start + (int64_t)job.dir * (i - 1));
             const uint32_t cb = base_at(P.B, job.b_start + (int64_t)job.dir * (jj - 1));
-            const int32_t s = p + (ca == cb ? match : mismatch);
+            const int32_t sub =
+                P.has_lut ? s_lut[(ca << 2) | cb] : (ca == cb ? match : mismatch);
+            const int32_t s = p + sub;
             v = s > v ? s : v;
           }
         }
@@ -150,6 +154,8 @@ __global__ __launch_bounds__(kSpillThreads) void k_spill(const Job *__restrict__
       if (moved && src.overflow) {
         src.overflow[atomicAdd(src.overflow_count, 1)] = j;
         atomicAdd(&stats[2 * kLists + q.tier], 1ull);
+        atomicAdd(&stats[kRestart + q.tier], 1ull);
+        atomicAdd(&stats[kWasted + q.tier], (unsigned long long)cells);
       } else {
         if (moved) out.status = XD_ENOMEM;
         outs[j] = out;
@@ -171,20 +177,23 @@ inline xd_status spill_alloc(SpillScratch *sp, int64_t cap) {
   return XD_OK;
 }
 
-// The global-memory pass over `list` (jobs the multi-wave tier could not hold).
-inline xd_status spill_launch(SpillScratch *sp, hipStream_t s, const Job *jobs,
+// A global-memory pass over `list` with `groups` workgroups sharing the band
+// buffers (each holds cells per anti-diagonal = the buffers / (3 groups)).
+// Jobs wider than that go to `overflow` (nullptr: they fail with XD_ENOMEM).
+inline xd_status spill_launch(const SpillScratch *sp, hipStream_t s, const Job *jobs,
                               const TierQueue &q, int32_t *head, const int32_t *list,
                               const int32_t *list_count, JobOut *outs,
-                              unsigned long long *stats, const Params &P) {
-  if (!sp->huge) return XD_ENOMEM;
+                              unsigned long long *stats, const Params &P, int groups = kHugeSlots,
+                              int32_t *overflow = nullptr, int32_t *overflow_count = nullptr) {
+  if (!sp->huge || groups < 1) return XD_ENOMEM;
   SpillSource b;
   b.q = q;
   b.list = list;
   b.list_count = list_count;
-  b.overflow = nullptr;
-  b.overflow_count = nullptr;
-  b.cap = sp->cap;
-  hipLaunchKernelGGL(k_spill, dim3(kHugeSlots), dim3(kSpillThreads), 0, s, jobs, b, head, outs,
+  b.overflow = overflow;
+  b.overflow_count = overflow_count;
+  b.cap = sp->cap * kHugeSlots / groups;
+  hipLaunchKernelGGL(k_spill, dim3(groups), dim3(kSpillThreads), 0, s, jobs, b, head, outs,
                      stats, P, sp->huge);
   return hipGetLastError() == hipSuccess ? XD_OK : XD_EDEVICE;
 }

@@ -101,6 +101,8 @@ def lib() -> ctypes.CDLL:
         L.xd_ctx_memory.restype = i32
         L.xdrop_extend.argtypes = [p, p, u64, p, u64, p, sz, Scores, p, p, p]
         L.xdrop_extend.restype = i32
+        L.xdrop_extend_matrix.argtypes = [p, p, u64, p, u64, p, sz, p, ctypes.c_int32, p, p, p]
+        L.xdrop_extend_matrix.restype = i32
         L.xdrop_extend_host.argtypes = [p, p, u64, p, u64, p, sz, Scores, p, p]
         L.xdrop_extend_host.restype = i32
         L.xd_last_stats.argtypes = [p, ctypes.POINTER(Stats)]
@@ -227,6 +229,26 @@ class Context:
                                   len(db.b_words), db.d_pairs.data_ptr(), db.n, sc,
                                   db.d_out.data_ptr(), ctypes.c_void_p(s.cuda_stream),
                                   ctypes.byref(opts) if opts is not None else None))
+
+    def extend_device_matrix(self, db: DeviceBatch, matrix, gap: int,
+                             stream: Optional[torch.cuda.Stream] = None,
+                             opts: Optional[Opts] = None):
+        """Enqueues xdrop_extend_matrix: matrix[p][q] scores base p of A
+        against base q of B (4 x 4, codes A=0 C=1 G=2 T=3)."""
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        tbl = np.ascontiguousarray(np.asarray(matrix, dtype=np.int32).reshape(16))
+        _check(lib().xdrop_extend_matrix(
+            self.h, db.d_a.data_ptr(), len(db.a_words), db.d_b.data_ptr(), len(db.b_words),
+            db.d_pairs.data_ptr(), db.n, tbl.ctypes.data_as(ctypes.c_void_p), int(gap),
+            db.d_out.data_ptr(), ctypes.c_void_p(s.cuda_stream),
+            ctypes.byref(opts) if opts is not None else None))
+
+    def extend_matrix(self, bt, matrix, gap: int, opts: Optional[Opts] = None) -> np.ndarray:
+        """Synchronous convenience of extend_device_matrix."""
+        db = DeviceBatch(bt, f"cuda:{self.device}")
+        self.extend_device_matrix(db, matrix, gap, opts=opts)
+        torch.cuda.synchronize(self.device)
+        return db.results()
 
     def extend(self, bt, opts: Optional[Opts] = None, device: Optional[str] = None) -> np.ndarray:
         """Synchronous convenience: upload, extend, download."""
