@@ -15,6 +15,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "xdrop_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+SEED_SRC = os.path.join(HERE, "seed_oracle.c")
+SEED_LIB = os.path.join(HERE, "libseedoracle.so")
 NEG = -(1 << 63)
 
 PAIR_FIELDS = ["score", "left_score", "right_score", "seed_score",
@@ -33,14 +35,19 @@ class _Trace(ctypes.Structure):
         (f, ctypes.POINTER(ctypes.c_int64)) for f in ("lo", "hi", "la", "lb", "best", "vmax")]
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain C, -O3, no intrinsics, no threads)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp%d" % os.getpid()
+def _compile(src: str, lib_path: str, force: bool) -> str:
+    if force or not os.path.exists(lib_path) or os.path.getmtime(lib_path) < os.path.getmtime(src):
+        tmp = lib_path + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O3", "-march=native", "-std=c11", "-Wall",
-                               "-shared", "-fPIC", "-o", tmp, SRC])
-        os.replace(tmp, LIB)
-    return LIB
+                               "-shared", "-fPIC", "-o", tmp, src])
+        os.replace(tmp, lib_path)
+    return lib_path
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracles with gcc (plain C, -O3, no intrinsics, no threads)."""
+    _compile(SEED_SRC, SEED_LIB, force)
+    return _compile(SRC, LIB, force)
 
 
 _lib = None
@@ -173,3 +180,47 @@ def batch(bt, return_time: bool = False):
     secs = lib().ox_batch(_ptr(a), _ptr(b), *[_ptr(v) for v in keep], n, bt.k, m, mm, g,
                           _ptr(out))
     return (out, secs) if return_time else out
+
+
+# ---------------------------------------------------------------------------
+# seed choice (seed_oracle.c)
+# ---------------------------------------------------------------------------
+SEED_FIELDS = ["a_seed", "b_seed", "bin_matches", "matches", "found", "status"]
+SEED_DTYPE = np.dtype([(f, np.int64) for f in SEED_FIELDS])
+_seed_lib = None
+
+
+def seed_lib():
+    global _seed_lib
+    if _seed_lib is None:
+        build()
+        L = ctypes.CDLL(SEED_LIB)
+        i64, p = ctypes.c_int64, ctypes.c_void_p
+        L.os_find_seed.argtypes = [p, i64, p, i64, i64, i64, p]
+        L.os_find_seed.restype = ctypes.c_int
+        L.os_find_seeds.argtypes = [p, p, p, p, p, p, i64, i64, i64, p]
+        L.os_find_seeds.restype = None
+        _seed_lib = L
+    return _seed_lib
+
+
+def find_seed(a, b, k=17, width=500) -> dict:
+    """Seed of one read pair by diagonal binning of its exact k-mer matches."""
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    b = np.ascontiguousarray(b, dtype=np.uint8)
+    out = np.zeros(1, SEED_DTYPE)
+    seed_lib().os_find_seed(_ptr(a), len(a), _ptr(b), len(b), k, width, _ptr(out))
+    return {f: int(out[f][0]) for f in SEED_FIELDS}
+
+
+def find_seeds(bt, k=17, width=500) -> np.ndarray:
+    """Seeds of every pair of a generator batch (its own seeds are ignored)."""
+    out = np.zeros(bt.n, SEED_DTYPE)
+    arr = lambda v, dt: np.ascontiguousarray(v, dtype=dt)
+    a = arr(bt.a, np.uint8) if len(bt.a) else np.zeros(1, np.uint8)
+    b = arr(bt.b, np.uint8) if len(bt.b) else np.zeros(1, np.uint8)
+    keep = [arr(bt.a_off, np.int64), arr(bt.a_len, np.int64), arr(bt.b_off, np.int64),
+            arr(bt.b_len, np.int64)]
+    seed_lib().os_find_seeds(_ptr(a), _ptr(b), *[_ptr(v) for v in keep], bt.n, k, width,
+                             _ptr(out))
+    return out
