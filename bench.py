@@ -13,7 +13,10 @@ HIP events recorded by the library around it on the launch stream.
 `sched_compare` runs the other scheduler (the plain one-wavefront-per-job
 grid against the persistent queue) on the same resident inputs;
 `host_buffers` times the host-memory entry point (allocation, PCIe copies
-both ways and the step) on the same reads.  `serving` is the
+both ways and the step) on the same reads.  `other_workloads` times the
+plain 1 kb, uneven and ultra-long batches whole with the autotuner's options
+(uneven and plain1k also with the plain grids, on the same resident inputs)
+and checks every pair against the oracle's stored digests.  `serving` is the
 continuous-batching server under Poisson arrivals at a fraction of its
 saturation rate, with a sweep over further loads.  `cpu_baseline` times the
 CPU oracle, single-threaded, on an evenly spread sample of the same workload,
@@ -299,6 +302,73 @@ def host_buffers(ctx, db, args, tuned, cells_per_step, ref) -> dict:
             "note": "pageable host buffers; includes device allocation and both copies"}
 
 
+def workload_leg(name: str, steps: int, plain: bool, workers: int) -> dict:
+    """Another batch workload timed whole with the autotuner's options (and,
+    with `plain`, with the plain one-wavefront-per-job grids on the same
+    resident inputs); every pair's eleven result fields are checked against
+    the oracle's stored per-chunk digests."""
+    import torch
+    from paper_2002_05200_amd import synth, tune, xdrop
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import digests
+    t0 = time.time()
+    bt, _ = digests.generate(name, workers)
+    gen_s = time.time() - t0
+    tuned = tune.lookup(bt) or {}
+    tuned.pop("sched", None)
+    db = xdrop.DeviceBatch(bt, "cuda:0")
+    del bt
+    ctx = xdrop.Context(0)
+    golden = digests.load()["workloads"].get(name)
+    out = {"workload": synth.WORKLOADS[name].describe, "pairs": db.n,
+           "generate_s": round(gen_s, 1)}
+    try:
+        variants = [("tuned", xdrop.make_opts(**tuned))]
+        if plain:
+            variants.append(("plain", xdrop.make_opts(sched=xdrop.SCHED_PLAIN)))
+        ref = None
+        for label, o in variants:
+            ctx.extend_device(db, opts=o)                 # warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(steps):
+                ctx.extend_device(db, opts=o)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t1) / steps
+            res = db.results()
+            cells = int(res["left_cells"].sum() + res["right_cells"].sum())
+            rec = {"ms_per_step": round(el * 1e3, 3), "gcups": round(cells / el / 1e9, 2),
+                   "steps": steps, "cells_per_step": cells}
+            if label == "tuned":
+                rec["options"] = tuned or "defaults"
+                st = ctx.stats()
+                rec["jobs_per_tier"] = st["jobs"].tolist()
+                rec["restarted"] = int(st["restarted"].sum())
+            if ref is None:
+                ref = res
+            else:
+                rec["results_identical_to_tuned"] = bool(
+                    all(np.array_equal(res[f], ref[f]) for f in RESULT_FIELDS))
+            out[label] = rec
+            print(f"[bench] {name} {label}: {rec}", file=sys.stderr, flush=True)
+        if golden is not None:
+            bad = [c["lo"] for c in golden["chunks"]
+                   if digests.result_digest(ref, c["lo"], c["hi"]) != c["results"]]
+            out["oracle_parity"] = {"pairs_compared": db.n, "chunks": len(golden["chunks"]),
+                                    "mismatched_chunks": len(bad), "first": bad[:3],
+                                    "how": "per-chunk SHA-256 of all eleven result fields against "
+                                           "the oracle's stored digests"}
+        else:
+            out["oracle_parity"] = None
+        if plain:
+            out["persistent_over_plain"] = round(out["tuned"]["gcups"] / out["plain"]["gcups"], 3)
+    finally:
+        ctx.close()
+        del db
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -329,6 +399,10 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="time hipGraph replays of the step (stage times then come from one "
                          "extra profiled eager step)")
+    ap.add_argument("--other-workloads", default="plain1k,uneven,ultralong",
+                    help="further batch workloads timed whole (tuned options; uneven and "
+                         "plain1k also with the plain grids), empty = none")
+    ap.add_argument("--other-steps", type=int, default=3)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic, to scale HBM byte counters)")
@@ -456,6 +530,11 @@ def main():
         line["host_buffers"] = host_buffers(ctx, db, args, tuned, cells_per_step, res2)
     ctx.close()
     del db
+    others = [w.strip() for w in args.other_workloads.split(",") if w.strip()]
+    if others:
+        line["other_workloads"] = {
+            w: workload_leg(w, args.other_steps, w in ("uneven", "plain1k"),
+                            min(16, os.cpu_count() or 1)) for w in others}
     if args.serving_requests:
         sweep = [float(v) for v in args.serving_sweep.split(",") if v.strip()]
         line["serving"] = serving_leg(args.serving_distinct, args.serving_requests,

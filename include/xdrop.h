@@ -198,6 +198,41 @@ xd_status xdrop_extend_matrix(xd_ctx *ctx, const uint32_t *d_a, uint64_t a_words
                               const int32_t *matrix, int32_t gap,
                               xd_result *d_out, void *stream, const xd_opts *opts);
 
+/* Seed of one read pair (xd_find_seeds). */
+typedef struct {
+    uint32_t a_seed, b_seed;  /* the chosen match: A[a_seed, +k) == B[b_seed, +k)
+                                 (0, 0 when found == 0)                        */
+    int32_t found;            /* 1 when the reads share at least one k-mer       */
+    int32_t status;           /* XD_OK, or XD_EINVAL for a read past its arena   */
+    uint64_t bin_matches;     /* exact k-mer matches in the winning bin          */
+    uint64_t matches;         /* all exact k-mer matches of the pair             */
+} xd_seed; /* 32 bytes */
+
+/*
+ * Seed choice for n_pairs read pairs, enqueued on `stream`: the k-mer each
+ * extension starts from, picked by binning (the application of Section V,
+ * where the positions of the k-mers two reads share are binned to estimate
+ * their overlap and the consensus bin gives the seed).  Reading taken, as the
+ * paper gives no formula: every exact match (p, q), A[p, p+k) == B[q, q+k),
+ * lies on diagonal q - p and falls in bin floor((q - p) / width); the bin with
+ * the most matches wins (the lower bin on a tie), and its match with the
+ * smallest p, then the smallest q, is the seed.
+ *   d_a, d_b    device arenas (2-bit packed, as for xdrop_extend);
+ *   d_pairs     device xd_pair records: a_off, b_off, a_len, b_len are read;
+ *               with set_pairs = 1, a_seed, b_seed and k of every pair with a
+ *               seed are overwritten (pairs without one are left as they
+ *               are), so the records can go straight to xdrop_extend;
+ *   k           seed length, 1..31; width: bin width in diagonals, >= 1;
+ *   d_seeds     device array of n_pairs xd_seed (caller-owned).
+ * Reads shorter than k have no seed.  Returns XD_EINVAL for null pointers or
+ * k / width / set_pairs out of range, XD_EDEVICE when the launch fails.  Uses
+ * no context scratch: the hash table and bins of each pair live in LDS.
+ */
+xd_status xd_find_seeds(xd_ctx *ctx, const uint32_t *d_a, uint64_t a_words,
+                        const uint32_t *d_b, uint64_t b_words, xd_pair *d_pairs,
+                        size_t n_pairs, uint32_t k, uint32_t width, int32_t set_pairs,
+                        xd_seed *d_seeds, void *stream);
+
 /* Synchronous convenience: host arenas, pairs and results; copies in, runs
  * xdrop_extend on an internal stream, copies out. */
 xd_status xdrop_extend_host(xd_ctx *ctx, const uint32_t *a, uint64_t a_words,
@@ -214,15 +249,22 @@ xd_status xd_last_stats(xd_ctx *ctx, xd_stats *out);
  *
  * Requests (1 .. max_batch_pairs pairs with their own packed reads) are
  * submitted from any host thread and queue in arrival order.  A scheduler
- * thread owned by the server forms a batch from the head of the queue as soon
- * as one of its `slots` is free: it admits requests while the batch's packed
- * reads and pair records fit in the slot's device memory (its share of
- * mem_budget), copies them to the device, where they stay until the batch is
- * done, and launches xdrop_extend on the slot's own stream.  Requests that
- * arrive while other batches run are admitted into the next free slot, so
- * their kernels overlap with the batches already on the device.  Results are
- * the same whether a request runs alone or in a mix (every pair is an
- * independent extension).
+ * thread owned by the server forms a batch as soon as one of its `slots` is
+ * free: it admits the oldest queued request, then later requests with the
+ * same scores (and, with group_by_class, the same cost class: the tier X
+ * selects and the octave of the longest pair) while the batch's packed reads
+ * and pair records fit in the slot's device memory.  It copies them to the
+ * device, where they stay until the batch is done, and launches xdrop_extend
+ * on the slot's own stream.  Requests that arrive while other batches run are
+ * admitted into the next free slot, so their kernels overlap with the
+ * batches already on the device.  Results are the same whether a request
+ * runs alone or in a mix (every pair is an independent extension).
+ *
+ * Memory: every slot holds an equal share of mem_budget, and everything the
+ * slot allocates on the device stays inside it: its extension context
+ * (created under half the share and sized for a full batch up front: job
+ * lists, global-memory band buffers, escalation saves), the pair records and
+ * results of one batch, and two read arenas of what remains.
  * ------------------------------------------------------------------------- */
 typedef struct xd_server xd_server;
 
@@ -232,11 +274,14 @@ typedef struct {
     int32_t max_batch_pairs;  /* pairs per batch (0 = 2048)                         */
     int32_t graph;            /* 1 = every slot replays a captured hipGraph of
                                  xdrop_extend (batches padded to max_batch_pairs)  */
-    uint64_t mem_budget;      /* device bytes for all slots' request memory
-                                 (0 = 1 GiB); each slot holds an equal share       */
+    uint64_t mem_budget;      /* device bytes for all slots (0 = 1 GiB); each
+                                 slot holds an equal share                          */
     xd_opts extend_opts;      /* launch options of every batch (graph and
                                  profile are set by the server)                     */
-} xd_server_opts; /* 72 bytes */
+    int32_t group_by_class;   /* 1 = a batch takes only requests of the oldest
+                                 request's cost class; 0 = any, in arrival order    */
+    int32_t reserved;         /* must be 0                                          */
+} xd_server_opts; /* 80 bytes */
 
 /* One request: host buffers, read by xd_server_submit before it returns. */
 typedef struct {
@@ -272,12 +317,27 @@ typedef struct {
     uint64_t cells;                    /* cells of completed requests             */
     uint64_t queued;                   /* requests waiting for admission now      */
     uint64_t max_inflight;             /* most batches on the device at once      */
+    uint64_t canceled;                 /* requests canceled before admission      */
+    uint64_t device_bytes;             /* device memory the slots hold (at most
+                                          mem_budget)                             */
+    uint64_t arena_words;              /* packed words of each read arena of a
+                                          slot: the reads one batch can hold      */
+    uint64_t waiting_polls;            /* xd_server_poll calls waiting inside the
+                                          server now                              */
 } xd_server_stats;
 
 xd_status xd_server_get_stats(xd_server *srv, xd_server_stats *out);
 
-/* Stops the scheduler after the batches on the device finish; tickets not
- * yet admitted are dropped.  Safe on NULL. */
+/* Cancels a request that is still waiting for admission: it leaves the queue
+ * and its poll returns XD_ECANCELED.  XD_EBUSY if it is already on the device
+ * or done (its poll then returns its results as usual); XD_EINVAL for an
+ * unknown ticket. */
+xd_status xd_server_cancel(xd_server *srv, uint64_t ticket);
+
+/* Stops the scheduler after the batches on the device finish.  Requests not
+ * yet admitted are canceled (their polls return XD_ECANCELED); polls waiting
+ * inside the server are woken and return before the server is freed.  No
+ * call on the server may start once destroy has begun.  Safe on NULL. */
 void xd_server_destroy(xd_server *srv);
 
 const char *xd_last_error(void);

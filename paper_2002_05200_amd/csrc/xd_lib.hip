@@ -41,6 +41,7 @@
 #include "xd_w2_asm.h"
 #include "xd_multi.h"
 #include "xd_matrix.h"
+#include "xd_seed.h"
 
 namespace xd {
 
@@ -796,11 +797,10 @@ namespace {
 
 // Validation shared by the batch entry points; fills *o (NULL opts = the
 // defaults).  XD_OK with n_pairs == 0 means there is nothing to do.
-xd_status check_call(const char *who, const xd_ctx *c, const uint32_t *d_a, uint64_t a_words,
+xd_status check_args(const char *who, const uint32_t *d_a, uint64_t a_words,
                      const uint32_t *d_b, uint64_t b_words, const xd_pair *d_pairs,
                      size_t n_pairs, xd_scores sc, const xd_result *d_out, void *stream,
                      const xd_opts *opts, xd_opts *o) {
-  if (!c) return failw(XD_EINVAL, who, "null context");
   if (n_pairs == 0) return XD_OK;
   if (!d_pairs || !d_out) return failw(XD_EINVAL, who, "null pairs or results");
   if ((!d_a && a_words) || (!d_b && b_words)) return failw(XD_EINVAL, who, "null arena");
@@ -831,6 +831,14 @@ xd_status check_call(const char *who, const xd_ctx *c, const uint32_t *d_a, uint
   if (o->graph && !stream)
     return failw(XD_EINVAL, who, "graph mode needs a non-NULL stream");
   return XD_OK;
+}
+
+xd_status check_call(const char *who, const xd_ctx *c, const uint32_t *d_a, uint64_t a_words,
+                     const uint32_t *d_b, uint64_t b_words, const xd_pair *d_pairs,
+                     size_t n_pairs, xd_scores sc, const xd_result *d_out, void *stream,
+                     const xd_opts *opts, xd_opts *o) {
+  if (!c) return failw(XD_EINVAL, who, "null context");
+  return check_args(who, d_a, a_words, d_b, b_words, d_pairs, n_pairs, sc, d_out, stream, opts, o);
 }
 
 }  // namespace
@@ -980,6 +988,37 @@ xd_status xdrop_extend_matrix(xd_ctx *c, const uint32_t *d_a, uint64_t a_words,
   L.d_a = d_a; L.a_words = a_words; L.d_b = d_b; L.b_words = b_words;
   L.d_pairs = d_pairs; L.n_pairs = n_pairs; L.d_out = d_out; L.o = o;
   return enqueue_matrix(c, c->b, (hipStream_t)stream, L, matrix, gap);
+}
+
+xd_status xd_find_seeds(xd_ctx *c, const uint32_t *d_a, uint64_t a_words, const uint32_t *d_b,
+                        uint64_t b_words, xd_pair *d_pairs, size_t n_pairs, uint32_t k,
+                        uint32_t width, int32_t set_pairs, xd_seed *d_seeds, void *stream) {
+  static const char *who = "xd_find_seeds";
+  if (!c) return failw(XD_EINVAL, who, "null context");
+  if (k < 1 || k > (uint32_t)kSeedMaxK) return failw(XD_EINVAL, who, "k outside 1..31");
+  if (width < 1 || width > (1u << 30)) return failw(XD_EINVAL, who, "width outside 1..2^30");
+  if (set_pairs != 0 && set_pairs != 1) return failw(XD_EINVAL, who, "set_pairs is not 0 or 1");
+  if (n_pairs == 0) return XD_OK;
+  if (!d_pairs || !d_seeds) return failw(XD_EINVAL, who, "null pairs or seeds");
+  if ((!d_a && a_words) || (!d_b && b_words)) return failw(XD_EINVAL, who, "null arena");
+  if (n_pairs > (size_t(1) << 29)) return failw(XD_EINVAL, who, "too many pairs");
+  std::lock_guard<std::mutex> lock(c->mu);
+  XD_HIP(hipSetDevice(c->device));
+  SeedArgs S;
+  S.A = d_a;
+  S.B = d_b;
+  S.a_words = (int64_t)a_words;
+  S.b_words = (int64_t)b_words;
+  S.pairs = d_pairs;
+  S.n_pairs = (int64_t)n_pairs;
+  S.k = (int32_t)k;
+  S.width = width;
+  S.set_pairs = set_pairs;
+  S.out = d_seeds;
+  const unsigned grid = (unsigned)std::min<size_t>(n_pairs, size_t(1) << 24);
+  hipLaunchKernelGGL(k_find_seeds, dim3(grid), dim3(kSeedThreads), 0, (hipStream_t)stream, S);
+  XD_HIP(hipGetLastError());
+  return XD_OK;
 }
 
 xd_status xd_last_stats(xd_ctx *c, xd_stats *out) {

@@ -19,9 +19,7 @@
 #pragma once
 
 #include "xd_wide.h"
-#ifndef XD_EMULATION
 #include "xd_queue.h"
-#endif
 
 namespace xd {
 
@@ -162,7 +160,6 @@ XD_FN bool mw_step(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w, int 
     }
     vint vmx = splat(kNeg);
     uint64_t live_lo, live_hi;
-#ifndef XD_EMULATION
     if constexpr (ASM && NARROW) {
       // the same chain as generated assembly, with the chunk's edge
       // registers clipped inside it
@@ -179,7 +176,6 @@ XD_FN bool mw_step(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w, int 
       live_lo = PAR == 0 ? lf : ll;
       live_hi = PAR == 0 ? ll : lf;
     } else
-#endif
     {
       if constexpr (PAR == 0) {
         switch (rlo) {
@@ -246,7 +242,6 @@ XD_FN bool mw_step(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w, int 
       }
     }
     if (imp != 0 && P.unit_match) {   // best can rise by 1 only: one pass
-#ifndef XD_EMULATION
       if constexpr (ASM && NARROW) {
         const int32_t sb = WFirst<C>::run(cur, uniform(bw), uniform(rlo), uniform(rhi));
         if (sb >= 0) {
@@ -254,7 +249,6 @@ XD_FN bool mw_step(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w, int 
           bests = base + sb;
         }
       } else
-#endif
       {
 #pragma unroll
         for (int r = 0; r < C; ++r) {
@@ -524,7 +518,6 @@ XD_FN JobOut mw_extend(const Job &job, const Params &P, int32_t j, MwShared<NW, 
   return out;
 }
 
-#ifndef XD_EMULATION
 // One job per workgroup.  Plain (head == nullptr): workgroup b takes work item
 // b.  Persistent: workgroups pop work items.  A job whose band outgrows the
 // window is appended to `overflow` (the next tier's escalation list, with its
@@ -571,6 +564,5 @@ __global__ __launch_bounds__(64 * NW) void k_extend_mw(const Job *__restrict__ j
     if (head == nullptr) break;
   }
 }
-#endif
 
 }  // namespace xd

@@ -2,14 +2,16 @@
 // xd_lib.hip after the batch entry points).
 //
 // A scheduler thread owns `slots` execution slots.  Each slot has its own
-// stream, its own xd_ctx (job scratch), a device arena for the packed reads
-// and pair records of one batch, pinned host staging of the same size, and a
-// completion event.  Requests wait in one FIFO; whenever a slot is free and
-// the FIFO is not empty, the scheduler admits requests from its head while
-// they fit in the slot's memory, copies them to the device, launches
-// xdrop_extend on the slot's stream and records the event.  Requests arriving
-// meanwhile go to the next free slot, whose kernels then run beside the
-// batches already on the device.
+// stream, its own xd_ctx (job scratch, band buffers and escalation saves,
+// sized for a full batch under half the slot's share of the memory budget),
+// a device arena for the packed reads and pair records of one batch, pinned
+// host staging of the same size, and a completion event.  Requests wait in
+// one FIFO; whenever a slot is free and the FIFO is not empty, the scheduler
+// admits the oldest request and later ones of its score set and cost class
+// while they fit in the slot's memory (xd_admit.h), copies them to the
+// device, launches xdrop_extend on the slot's stream and records the event.
+// Requests arriving meanwhile go to the next free slot, whose kernels then
+// run beside the batches already on the device.
 #pragma once
 
 #include <atomic>
@@ -20,6 +22,8 @@
 #include <thread>
 #include <unordered_map>
 #include <vector>
+
+#include "xd_admit.h"
 
 namespace {
 
@@ -44,7 +48,8 @@ struct Request {
   std::vector<xd_pair> pairs;
   xd_scores scores{};
   std::vector<xd_result> out;
-  int state = 0;            // 0 queued, 1 on the device, 2 done, 3 failed
+  int32_t cls = 0;          // cost class (xd_admit.h)
+  int state = 0;            // 0 queued, 1 on the device, 2 done, 3 failed, 4 canceled
   uint64_t done_ns = 0;
 };
 
@@ -60,6 +65,7 @@ struct Slot {
   xd_result *h_out = nullptr;
   uint64_t cap_words = 0;   // per arena
   int32_t cap_pairs = 0;
+  uint64_t device_bytes = 0;   // arenas, pair records, results and the context
   bool busy = false;
   int32_t n_pairs = 0;
   std::vector<std::shared_ptr<Request>> reqs;
@@ -81,6 +87,10 @@ struct xd_server {
   std::thread thread;
   xd_server_stats st{};
   std::string thread_error;
+  int pollers = 0;                   // xd_server_poll calls inside the server now
+  std::condition_variable cv_pollers;
+  std::vector<AdmitItem> items;      // admission scratch (scheduler thread only)
+  std::vector<size_t> take;
 };
 
 namespace {
@@ -100,11 +110,21 @@ void free_slot(Slot &s) {
   s = Slot();
 }
 
+// A slot's context is created under half the slot's share and sized for a
+// full batch first; the arenas get what the share has left (xd_admit.h).
 xd_status alloc_slot(const xd_server_opts &o, uint64_t share, Slot &s) {
   s.cap_pairs = o.max_batch_pairs;
-  const uint64_t pair_bytes = (uint64_t)s.cap_pairs * (sizeof(xd_pair) + sizeof(xd_result));
-  if (share <= pair_bytes + 64) return XD_EINVAL;
-  s.cap_words = (share - pair_bytes) / 8;   // two arenas of 4-byte words
+  SlotPlan plan;
+  plan_slot(share, s.cap_pairs, 0, &plan);
+  xd_status st = xd_ctx_create(o.device, plan.ctx_budget, &s.ctx);
+  if (st != XD_OK) return st;
+  st = ensure_capacity(s.ctx, s.cap_pairs);
+  if (st != XD_OK) return st == XD_ENOMEM ? XD_EINVAL : st;
+  uint64_t ctx_bytes = 0;
+  xd_ctx_memory(s.ctx, &ctx_bytes);
+  if (!plan_slot(share, s.cap_pairs, ctx_bytes, &plan)) return XD_EINVAL;
+  s.cap_words = plan.cap_words;
+  s.device_bytes = ctx_bytes + plan.pair_bytes + 2 * 4 * s.cap_words;
   if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
     return XD_EDEVICE;
@@ -117,7 +137,7 @@ xd_status alloc_slot(const xd_server_opts &o, uint64_t share, Slot &s) {
       hipHostMalloc(&s.h_pairs, sizeof(xd_pair) * s.cap_pairs) != hipSuccess ||
       hipHostMalloc(&s.h_out, sizeof(xd_result) * s.cap_pairs) != hipSuccess)
     return XD_ENOMEM;
-  return xd_ctx_create(o.device, 0, &s.ctx);
+  return XD_OK;
 }
 
 // Packs the admitted requests of a slot into its staging buffers and
@@ -217,24 +237,23 @@ void scheduler(xd_server *srv) {
       {
         std::unique_lock<std::mutex> lock(srv->mu);
         if (srv->queue.empty()) break;
-        uint64_t a = 0, b = 0;
-        int64_t np = 0;
-        const xd_scores sc = srv->queue.front()->scores;
-        while (!srv->queue.empty()) {
-          Request &r = *srv->queue.front();
-          if (r.scores.match != sc.match || r.scores.mismatch != sc.mismatch ||
-              r.scores.gap != sc.gap)
-            break;
-          if (a + r.a.size() > s.cap_words || b + r.b.size() > s.cap_words ||
-              np + (int64_t)r.pairs.size() > s.cap_pairs)
-            break;
-          a += r.a.size();
-          b += r.b.size();
-          np += (int64_t)r.pairs.size();
-          r.state = 1;
-          s.reqs.push_back(srv->queue.front());
-          srv->queue.pop_front();
+        // admission (xd_admit.h): the oldest request, then later ones of its
+        // score set and cost class while the batch fits the slot
+        constexpr size_t kScan = 4096;
+        const size_t nq = std::min(srv->queue.size(), kScan);
+        srv->items.resize(nq);
+        for (size_t i = 0; i < nq; ++i) {
+          const Request &r = *srv->queue[i];
+          srv->items[i] = {r.a.size(), r.b.size(), (uint32_t)r.pairs.size(), r.scores, r.cls};
         }
+        admit(srv->items.data(), nq, s.cap_words, s.cap_pairs, srv->o.group_by_class != 0,
+              kScan, &srv->take);
+        for (size_t i : srv->take) {
+          srv->queue[i]->state = 1;
+          s.reqs.push_back(srv->queue[i]);
+        }
+        for (size_t t = srv->take.size(); t-- > 0;)
+          srv->queue.erase(srv->queue.begin() + (ptrdiff_t)srv->take[t]);
         srv->st.queued = srv->queue.size();
       }
       if (s.reqs.empty()) break;
@@ -274,6 +293,8 @@ xd_status xd_server_create(const xd_server_opts *opts, xd_server **out) {
   if (o.mem_budget == 0) o.mem_budget = 1ull << 30;
   if (o.slots < 1 || o.slots > 16 || o.max_batch_pairs < 1 || o.max_batch_pairs > (1 << 24))
     return fail(XD_EINVAL, "xd_server_create: slots or max_batch_pairs out of range");
+  if (o.group_by_class < 0 || o.group_by_class > 1 || o.reserved != 0)
+    return fail(XD_EINVAL, "xd_server_create: group_by_class not 0/1 or reserved field set");
   int ndev = 0;
   XD_HIP(hipGetDeviceCount(&ndev));
   if (o.device < 0 || o.device >= ndev) return fail(XD_EINVAL, "xd_server_create: no such device");
@@ -290,6 +311,8 @@ xd_status xd_server_create(const xd_server_opts *opts, xd_server **out) {
       return fail(st, st == XD_EINVAL ? "xd_server_create: mem_budget too small for the slots"
                                       : "xd_server_create: slot allocation failed");
     }
+    srv->st.device_bytes += s.device_bytes;
+    srv->st.arena_words = s.cap_words;
   }
   srv->thread = std::thread(scheduler, srv);
   *out = srv;
@@ -318,6 +341,7 @@ xd_status xd_server_submit(xd_server *srv, const xd_request *req, uint64_t *tick
   r->b.assign(req->b, req->b + req->b_words);
   r->pairs.assign(req->pairs, req->pairs + req->n_pairs);
   r->scores = req->scores;
+  r->cls = cost_class(req->pairs, req->n_pairs);
   {
     std::lock_guard<std::mutex> lock(srv->mu);
     if (srv->stop) return fail(XD_ECANCELED, "xd_server_submit: server is stopping");
@@ -340,14 +364,40 @@ xd_status xd_server_poll(xd_server *srv, uint64_t ticket, xd_result *out, int32_
   std::shared_ptr<Request> r = it->second;
   auto ready = [&] { return r->state >= 2; };
   if (!ready()) {
+    ++srv->pollers;   // xd_server_destroy waits until no poll is inside
     if (wait_ms < 0) srv->cv_done.wait(lock, ready);
     else if (wait_ms > 0) srv->cv_done.wait_for(lock, std::chrono::milliseconds(wait_ms), ready);
+    if (--srv->pollers == 0) srv->cv_pollers.notify_all();
   }
   if (!ready()) return XD_ENOTREADY;
-  srv->table.erase(ticket);
+  srv->table.erase(r->ticket);
   if (done_ns) *done_ns = r->done_ns;
+  if (r->state == 4) return fail(XD_ECANCELED, "xd_server_poll: the request was canceled");
   if (r->state == 3) return fail(XD_EDEVICE, "xd_server_poll: the request's batch failed");
   std::memcpy(out, r->out.data(), sizeof(xd_result) * r->out.size());
+  return XD_OK;
+}
+
+xd_status xd_server_cancel(xd_server *srv, uint64_t ticket) {
+  if (!srv) return fail(XD_EINVAL, "xd_server_cancel: null server");
+  {
+    std::lock_guard<std::mutex> lock(srv->mu);
+    auto it = srv->table.find(ticket);
+    if (it == srv->table.end()) return fail(XD_EINVAL, "xd_server_cancel: unknown ticket");
+    Request &r = *it->second;
+    if (r.state != 0)
+      return fail(XD_EBUSY, "xd_server_cancel: the request is already on the device or done");
+    for (auto q = srv->queue.begin(); q != srv->queue.end(); ++q)
+      if ((*q)->ticket == ticket) {
+        srv->queue.erase(q);
+        break;
+      }
+    r.state = 4;
+    r.done_ns = steady_ns();
+    srv->st.canceled += 1;
+    srv->st.queued = srv->queue.size();
+  }
+  srv->cv_done.notify_all();
   return XD_OK;
 }
 
@@ -355,6 +405,7 @@ xd_status xd_server_get_stats(xd_server *srv, xd_server_stats *out) {
   if (!srv || !out) return fail(XD_EINVAL, "xd_server_get_stats: null pointer");
   std::lock_guard<std::mutex> lock(srv->mu);
   *out = srv->st;
+  out->waiting_polls = (uint64_t)srv->pollers;
   return XD_OK;
 }
 
@@ -363,10 +414,22 @@ void xd_server_destroy(xd_server *srv) {
   {
     std::lock_guard<std::mutex> lock(srv->mu);
     srv->stop = true;
+    const uint64_t now = steady_ns();
+    for (auto &r : srv->queue) {   // never admitted: canceled
+      r->state = 4;
+      r->done_ns = now;
+      srv->st.canceled += 1;
+    }
     srv->queue.clear();
   }
   srv->cv_work.notify_all();
+  srv->cv_done.notify_all();
   if (srv->thread.joinable()) srv->thread.join();
+  {   // pollers woken by the last completions or cancellations leave first
+    std::unique_lock<std::mutex> lock(srv->mu);
+    srv->cv_done.notify_all();
+    srv->cv_pollers.wait(lock, [&] { return srv->pollers == 0; });
+  }
   (void)hipSetDevice(srv->o.device);
   for (Slot &s : srv->slots) {
     if (s.stream) (void)hipStreamSynchronize(s.stream);

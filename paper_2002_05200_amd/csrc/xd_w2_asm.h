@@ -173,7 +173,6 @@ namespace xd {
   XD_SW_D2(SE, "x0")                                                              \
   XD_SW_D2(SO, "x1")
 
-#if !defined(XD_EMULATION)
 template <bool NARROW, bool FWD>
 XD_FN int w2_loop(WBand<2> &bd, WScalars &st, const JobView &jv, const Params &P, uint64_t &m0,
                   uint64_t &m1) {
@@ -318,6 +317,5 @@ XD_FN int w2_loop(WBand<2> &bd, WScalars &st, const JobView &jv, const Params &P
   }
   return status;
 }
-#endif  // !XD_EMULATION
 
 }  // namespace xd

@@ -19,9 +19,7 @@
 #pragma once
 
 #include "xd_extend.h"
-#ifndef XD_EMULATION
 #include "xd_wchain_asm.h"
-#endif
 
 namespace xd {
 
@@ -198,7 +196,6 @@ XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Par
   const uint64_t lo_mask = ~0ull << (st.lo & 63);
   const uint64_t hi_mask = ~0ull >> (63 - (st.hi & 63));
   uint64_t live_lo, live_hi;
-#ifndef XD_EMULATION
   if constexpr (ASM && NARROW) {
     // the same chain as generated assembly, with the edge registers clipped
     // to the range inside it (the entry register is rlo going up, rhi going
@@ -211,7 +208,6 @@ XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Par
     live_lo = PAR == 0 ? lf : ll;
     live_hi = PAR == 0 ? ll : lf;
   } else
-#endif
   {
     if constexpr (PAR == 0) {   // upwards from rlo
       switch (rlo) {
@@ -302,11 +298,9 @@ XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Par
     // unrolled loop, whose code its register allocation handles better)
     int sbest = -1;
     const int32_t bw0 = st.bw;
-#ifndef XD_EMULATION
     if constexpr (ASM && NARROW) {
       sbest = WFirst<C>::run(cur, uniform(bw0), uniform(rlo), uniform(rhi));
     } else
-#endif
     if constexpr (C >= 32) {
 #pragma unroll
       for (int r = 0; r < C; ++r) {

@@ -29,6 +29,11 @@ RESULT_DTYPE = np.dtype([("score", "<i4"), ("left_score", "<i4"), ("right_score"
                          ("right_cells", "<u8"), ("status", "<i4"), ("reserved", "<i4")])
 assert PAIR_DTYPE.itemsize == 40 and RESULT_DTYPE.itemsize == 56
 
+SEED_DTYPE = np.dtype([("a_seed", "<u4"), ("b_seed", "<u4"), ("found", "<i4"), ("status", "<i4"),
+                       ("bin_matches", "<u8"), ("matches", "<u8")])
+assert SEED_DTYPE.itemsize == 32
+SEED_FIELDS = ["a_seed", "b_seed", "bin_matches", "matches", "found", "status"]
+
 RESULT_FIELDS = ["score", "left_score", "right_score", "seed_score", "a_begin", "a_end",
                  "b_begin", "b_end", "left_cells", "right_cells", "status"]
 
@@ -56,7 +61,8 @@ class Stats(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("slots", ctypes.c_int32),
                 ("max_batch_pairs", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("mem_budget", ctypes.c_uint64), ("extend_opts", Opts)]
+                ("mem_budget", ctypes.c_uint64), ("extend_opts", Opts),
+                ("group_by_class", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -69,7 +75,9 @@ class Request(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("requests", ctypes.c_uint64), ("pairs", ctypes.c_uint64),
                 ("batches", ctypes.c_uint64), ("cells", ctypes.c_uint64),
-                ("queued", ctypes.c_uint64), ("max_inflight", ctypes.c_uint64)]
+                ("queued", ctypes.c_uint64), ("max_inflight", ctypes.c_uint64),
+                ("canceled", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
+                ("arena_words", ctypes.c_uint64), ("waiting_polls", ctypes.c_uint64)]
 
 
 class XdropError(RuntimeError):
@@ -103,6 +111,9 @@ def lib() -> ctypes.CDLL:
         L.xdrop_extend.restype = i32
         L.xdrop_extend_matrix.argtypes = [p, p, u64, p, u64, p, sz, p, ctypes.c_int32, p, p, p]
         L.xdrop_extend_matrix.restype = i32
+        L.xd_find_seeds.argtypes = [p, p, u64, p, u64, p, sz, ctypes.c_uint32, ctypes.c_uint32,
+                                    ctypes.c_int32, p, p]
+        L.xd_find_seeds.restype = i32
         L.xdrop_extend_host.argtypes = [p, p, u64, p, u64, p, sz, Scores, p, p]
         L.xdrop_extend_host.restype = i32
         L.xd_last_stats.argtypes = [p, ctypes.POINTER(Stats)]
@@ -113,6 +124,8 @@ def lib() -> ctypes.CDLL:
         L.xd_server_submit.restype = i32
         L.xd_server_poll.argtypes = [p, u64, p, ctypes.c_int32, ctypes.POINTER(u64)]
         L.xd_server_poll.restype = i32
+        L.xd_server_cancel.argtypes = [p, u64]
+        L.xd_server_cancel.restype = i32
         L.xd_server_get_stats.argtypes = [p, ctypes.POINTER(ServerStats)]
         L.xd_server_get_stats.restype = i32
         L.xd_server_destroy.argtypes = [p]
@@ -250,6 +263,29 @@ class Context:
         torch.cuda.synchronize(self.device)
         return db.results()
 
+    def find_seeds_device(self, db: DeviceBatch, k: int = 17, width: int = 500,
+                          set_pairs: bool = False, d_seeds: Optional[torch.Tensor] = None,
+                          stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+        """Enqueues xd_find_seeds over the batch's reads; returns the device
+        buffer of xd_seed records.  With set_pairs the batch's pair records
+        get the found seeds (and k)."""
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if d_seeds is None:
+            d_seeds = torch.empty(max(db.n, 1) * SEED_DTYPE.itemsize, dtype=torch.uint8,
+                                  device=db.d_pairs.device)
+        _check(lib().xd_find_seeds(self.h, db.d_a.data_ptr(), len(db.a_words), db.d_b.data_ptr(),
+                                   len(db.b_words), db.d_pairs.data_ptr(), db.n, int(k),
+                                   int(width), int(bool(set_pairs)), d_seeds.data_ptr(),
+                                   ctypes.c_void_p(s.cuda_stream)))
+        return d_seeds
+
+    def find_seeds(self, bt, k: int = 17, width: int = 500) -> np.ndarray:
+        """Synchronous convenience: the xd_seed records of every pair of bt."""
+        db = DeviceBatch(bt, f"cuda:{self.device}")
+        d = self.find_seeds_device(db, k=k, width=width)
+        torch.cuda.synchronize(self.device)
+        return d[: db.n * SEED_DTYPE.itemsize].cpu().numpy().view(SEED_DTYPE).copy()
+
     def extend(self, bt, opts: Optional[Opts] = None, device: Optional[str] = None) -> np.ndarray:
         """Synchronous convenience: upload, extend, download."""
         db = DeviceBatch(bt, device or f"cuda:{self.device}")
@@ -311,11 +347,13 @@ class Server:
     """xd_server: continuous batching of extension requests on one device."""
 
     def __init__(self, device: int = 0, slots: int = 4, max_batch_pairs: int = 2048,
-                 graph: int = 0, mem_budget: int = 0, opts: Optional[Opts] = None):
+                 graph: int = 0, mem_budget: int = 0, opts: Optional[Opts] = None,
+                 group_by_class: int = 1):
         torch.cuda.init()
         o = ServerOpts()
         o.device, o.slots, o.max_batch_pairs, o.graph = device, slots, max_batch_pairs, graph
         o.mem_budget = mem_budget
+        o.group_by_class = group_by_class
         o.extend_opts = opts if opts is not None else make_opts()
         h = ctypes.c_void_p()
         _check(lib().xd_server_create(ctypes.byref(o), ctypes.byref(h)))
@@ -336,6 +374,14 @@ class Server:
             return None
         _check(st)
         return out, done.value
+
+    def cancel(self, ticket: int) -> int:
+        """xd_server_cancel: XD_OK if the request left the queue, XD_EBUSY if
+        it is already on the device or done."""
+        st = lib().xd_server_cancel(self.h, ticket)
+        if st not in (XD_OK, XD_EBUSY):
+            _check(st)
+        return st
 
     def stats(self) -> dict:
         st = ServerStats()

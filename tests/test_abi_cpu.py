@@ -100,11 +100,13 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_2002_05200_amd import xdrop
     structs = {"xd_pair": None, "xd_result": None, "xd_opts": xdrop.Opts,
                "xd_stats": xdrop.Stats, "xd_server_opts": xdrop.ServerOpts,
-               "xd_request": xdrop.Request, "xd_server_stats": xdrop.ServerStats}
+               "xd_request": xdrop.Request, "xd_server_stats": xdrop.ServerStats,
+               "xd_seed": None}
     fields = {"xd_opts": [f for f, _ in xdrop.Opts._fields_],
               "xd_stats": [f for f, _ in xdrop.Stats._fields_],
               "xd_server_opts": [f for f, _ in xdrop.ServerOpts._fields_],
               "xd_pair": list(xdrop.PAIR_DTYPE.names),
+              "xd_seed": list(xdrop.SEED_DTYPE.names),
               "xd_result": list(xdrop.RESULT_DTYPE.names)}
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "xdrop.h"', "int main(void) {"]
     for s in structs:
@@ -119,7 +121,8 @@ def test_struct_layouts_match_header(tmp_path):
     got = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
     assert int(got["xd_pair"]) == xdrop.PAIR_DTYPE.itemsize == 40
     assert int(got["xd_result"]) == xdrop.RESULT_DTYPE.itemsize == 56
-    for name, dt in (("xd_pair", xdrop.PAIR_DTYPE), ("xd_result", xdrop.RESULT_DTYPE)):
+    for name, dt in (("xd_pair", xdrop.PAIR_DTYPE), ("xd_result", xdrop.RESULT_DTYPE),
+                     ("xd_seed", xdrop.SEED_DTYPE)):
         for f in dt.names:
             assert int(got[f"{name}.{f}"]) == dt.fields[f][1], (name, f)
     for s, cls in structs.items():
@@ -130,7 +133,8 @@ def test_struct_layouts_match_header(tmp_path):
             assert int(got[f"{s}.{f}"]) == getattr(cls, f).offset, (s, f)
     text = open(HEADER).read()
     assert "} xd_opts; /* 48 bytes */" in text and int(got["xd_opts"]) == 48
-    assert "} xd_server_opts; /* 72 bytes */" in text and int(got["xd_server_opts"]) == 72
+    assert "} xd_server_opts; /* 80 bytes */" in text and int(got["xd_server_opts"]) == 80
+    assert "} xd_seed; /* 32 bytes */" in text and int(got["xd_seed"]) == 32
     assert "} xd_request; /* 56 bytes */" in text and int(got["xd_request"]) == 56
 
 
@@ -141,3 +145,4 @@ def test_server_rejects_null_arguments_without_a_device(L):
     assert L.xd_server_poll(None, 1, None, 0, None) == xdrop.XD_EINVAL
     assert L.xd_server_get_stats(None, None) == xdrop.XD_EINVAL
     L.xd_server_destroy(None)
+

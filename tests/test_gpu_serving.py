@@ -64,18 +64,22 @@ def test_alone_and_in_a_mix_agree_with_the_oracle(xd, requests, graph):
 
 
 def test_tight_admission_memory_still_completes_everything(xd, requests):
-    """A slot share that holds only a few requests: the queue drains batch
-    by batch and every result still equals the unconstrained run."""
+    """A memory budget whose slot arenas hold only a few requests: the queue
+    drains batch by batch, every result still equals the unconstrained run,
+    and the slots' device memory stays inside the budget."""
     ref_srv = xd.Server(slots=2, max_batch_pairs=256)
     try:
         ref = run_all(ref_srv, xd, requests[:12])
     finally:
         ref_srv.close()
     words = [(len(xd.pack_codes(bt.a)), len(xd.pack_codes(bt.b))) for bt in requests[:12]]
-    cap_words = max(max(w) for w in words) + 64           # one slot: the largest request + a little
-    share = cap_words * 8 + 256 * (40 + 56)
-    srv = xd.Server(slots=2, max_batch_pairs=256, mem_budget=2 * share)
+    budget = 2 * (7 << 19)                                # two slots of 3.5 MiB
+    srv = xd.Server(slots=2, max_batch_pairs=256, mem_budget=budget)
     try:
+        st0 = srv.stats()
+        assert 0 < st0["device_bytes"] <= budget, st0
+        cap_words = st0["arena_words"]
+        assert max(max(w) for w in words) <= cap_words < sum(a for a, _ in words), (cap_words, words)
         got = run_all(srv, xd, requests[:12])
         for r in range(12):
             assert same(got[r], ref[r]), f"request {r}"
@@ -84,6 +88,68 @@ def test_tight_admission_memory_still_completes_everything(xd, requests):
         assert srv.stats()["batches"] >= max(least, 2), (srv.stats(), least)
     finally:
         srv.close()
+
+
+def test_device_memory_stays_inside_the_budget(xd):
+    for slots, budget in [(1, 64 << 20), (4, 1 << 30), (16, 2 << 30)]:
+        srv = xd.Server(slots=slots, max_batch_pairs=2048, mem_budget=budget)
+        try:
+            st = srv.stats()
+            assert 0 < st["device_bytes"] <= budget, (slots, budget, st)
+        finally:
+            srv.close()
+    with pytest.raises(xd.XdropError) as e:        # too small for one slot's context
+        xd.Server(slots=4, max_batch_pairs=2048, mem_budget=4 << 20)
+    assert e.value.status == xd.XD_EINVAL
+
+
+def test_cancel_and_destroy(xd, requests):
+    """Requests still queued can be canceled (their polls say so); requests
+    on the device finish; destroying the server cancels what is queued and
+    wakes every poll waiting inside it."""
+    import threading
+    srv = xd.Server(slots=1, max_batch_pairs=64, mem_budget=64 << 20)
+    packed = [xd.PackedRequest(bt) for bt in requests[:10]]
+    tickets = [srv.submit(p) for p in packed]
+    outcome = {}
+    for t in tickets[::-1]:                        # newest first: most are still queued
+        outcome[t] = srv.cancel(t)
+    assert xd.XD_OK in outcome.values()
+    for t, p in zip(tickets, packed):
+        if outcome[t] == xd.XD_OK:
+            with pytest.raises(xd.XdropError) as e:
+                srv.poll(t, p.n, wait_ms=-1)
+            assert e.value.status == xd.XD_ECANCELED
+        else:
+            assert outcome[t] == xd.XD_EBUSY
+            assert srv.poll(t, p.n, wait_ms=60000) is not None
+    with pytest.raises(xd.XdropError):
+        srv.cancel(tickets[0])                     # released by its poll: unknown now
+    assert srv.stats()["canceled"] == sum(v == xd.XD_OK for v in outcome.values())
+    # destroy with requests queued and polls waiting on them
+    tickets = [srv.submit(p) for p in packed]
+    results = {}
+
+    def wait(t, n):
+        try:
+            results[t] = srv.poll(t, n, wait_ms=-1)
+        except xd.XdropError as e:
+            results[t] = e.status
+
+    threads = [threading.Thread(target=wait, args=(t, p.n)) for t, p in zip(tickets, packed)]
+    for th in threads:
+        th.start()
+    import time
+    t0 = time.time()                               # every poll is inside the server or done
+    while srv.stats()["waiting_polls"] + len(results) < len(threads):
+        assert time.time() - t0 < 60
+        time.sleep(0.001)
+    srv.close()
+    for th in threads:
+        th.join(timeout=60)
+        assert not th.is_alive()
+    assert len(results) == len(tickets)
+    assert all(v == xd.XD_ECANCELED or (isinstance(v, tuple)) for v in results.values())
 
 
 def test_oversized_request_is_rejected(xd, requests):
