@@ -240,6 +240,37 @@ xd_status xdrop_extend_host(xd_ctx *ctx, const uint32_t *a, uint64_t a_words,
                             const xd_pair *pairs, size_t n_pairs, xd_scores scores,
                             xd_result *out, const xd_opts *opts);
 
+/*
+ * xdrop_extend without a context and without any device allocation, for
+ * callers that cannot allocate: code under hipGraph stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc.
+ *   - Runs on HIP device `device`, which is made current for the call and
+ *     restored afterwards; arguments, results and asynchrony are those of
+ *     xdrop_extend.
+ *   - Scratch is one fixed array in the library's device memory, of
+ *     XD_NOALLOC_SCRATCH_BYTES on every GPU the library runs on, held until the
+ *     process ends: job lists for at most XD_NOALLOC_MAX_PAIRS pairs,
+ *     XD_NOALLOC_SAVE_SLOTS escalation saves (later escalations start over in
+ *     the wider tier, as xd_opts.max_save_slots describes) and global-memory
+ *     band buffers of XD_NOALLOC_BAND_CELLS cells per anti-diagonal (a job
+ *     whose band is wider fails with XD_ENOMEM in its pair status).
+ *   - Every call on one GPU uses that GPU's one array, which keeps the last
+ *     call's contents (each call clears what must start at zero with a
+ *     kernel).  Calls that overlap on one GPU -- on different streams, or from
+ *     different threads -- race on it; serialise them.
+ *   - Returns XD_EINVAL for n_pairs > XD_NOALLOC_MAX_PAIRS, for graph or
+ *     profile options, and for everything xdrop_extend rejects; calls no
+ *     hipMalloc, hipFree or other allocating routine.
+ */
+#define XD_NOALLOC_MAX_PAIRS 8192
+#define XD_NOALLOC_SAVE_SLOTS 512
+#define XD_NOALLOC_BAND_CELLS 16388
+#define XD_NOALLOC_SCRATCH_BYTES (13u << 20)
+xd_status xdrop_extend_noalloc(int device, const uint32_t *d_a, uint64_t a_words,
+                               const uint32_t *d_b, uint64_t b_words,
+                               const xd_pair *d_pairs, size_t n_pairs, xd_scores scores,
+                               xd_result *d_out, void *stream, const xd_opts *opts);
+
 /* Statistics of the last xdrop_extend on this context (synchronises the
  * context's device first). */
 xd_status xd_last_stats(xd_ctx *ctx, xd_stats *out);

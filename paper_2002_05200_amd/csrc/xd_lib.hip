@@ -1045,4 +1045,95 @@ xd_status xd_last_stats(xd_ctx *c, xd_stats *out) {
 
 }  // extern "C"
 
+// Scratch of xdrop_extend_noalloc: one fixed array per GPU, laid out as the
+// job lists of XD_NOALLOC_MAX_PAIRS pairs, then the global-memory band
+// buffers, then the escalation saves.  Host code never passes this name to a
+// kernel or a copy: it is a host-side stand-in for the device array, whose
+// address on each GPU comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[XD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr size_t kNaJobBytes = size_t(2) << 20;
+constexpr size_t kNaSpillBytes = (spill_bytes(XD_NOALLOC_BAND_CELLS) + 255) & ~size_t(255);
+constexpr size_t kNaSaveBytes = kSaveSlotBytes * XD_NOALLOC_SAVE_SLOTS;
+static_assert(kNaJobBytes + kNaSpillBytes + kNaSaveBytes <= XD_NOALLOC_SCRATCH_BYTES,
+              "no-allocation scratch layout exceeds its array");
+static_assert(XD_NOALLOC_BAND_CELLS >= kHugeCapMin, "band buffers below the spill minimum");
+constexpr int kNaMaxDevices = 64;
+
+// Per device: the array's device address and the buffers carved from it,
+// set once (with the device current) by the first call on that device.
+struct NoAllocDevice {
+  bool ready = false;
+  void *ptr = nullptr;
+  Bufs b;
+};
+NoAllocDevice g_na[kNaMaxDevices];
+xd_ctx g_na_ctx[kNaMaxDevices];   // device number and CU count only; no memory
+std::mutex g_na_mu;
+
+xd_status noalloc_setup(int device) {
+  NoAllocDevice &D = g_na[device];
+  if (D.ready) return XD_OK;
+  void *ptr = nullptr;
+  XD_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) return fail(XD_EDEVICE, "xdrop_extend_noalloc: no device address for the scratch array");
+  int ncu = 0;
+  XD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
+  char *base = (char *)ptr;
+  Bufs &B = D.b;
+  if (carve_jobs(B, base, XD_NOALLOC_MAX_PAIRS) > kNaJobBytes)
+    return fail(XD_EINVAL, "xdrop_extend_noalloc: job lists exceed their part of the scratch");
+  B.spill.huge = (int32_t *)(base + kNaJobBytes);
+  B.spill.cap = XD_NOALLOC_BAND_CELLS;
+  B.save_pool = (int32_t *)(base + kNaJobBytes + kNaSpillBytes);
+  B.save_slots = XD_NOALLOC_SAVE_SLOTS;
+  g_na_ctx[device].device = device;
+  g_na_ctx[device].num_cu = ncu;
+  D.ptr = ptr;
+  D.ready = true;
+  return XD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+xd_status xdrop_extend_noalloc(int device, const uint32_t *d_a, uint64_t a_words,
+                               const uint32_t *d_b, uint64_t b_words, const xd_pair *d_pairs,
+                               size_t n_pairs, xd_scores sc, xd_result *d_out, void *stream,
+                               const xd_opts *opts) {
+  static const char *who = "xdrop_extend_noalloc";
+  if (n_pairs > XD_NOALLOC_MAX_PAIRS)
+    return failw(XD_EINVAL, who, "more pairs than XD_NOALLOC_MAX_PAIRS");
+  xd_opts o;
+  const xd_status chk = check_args(who, d_a, a_words, d_b, b_words, d_pairs, n_pairs, sc, d_out,
+                                   stream, opts, &o);
+  if (chk != XD_OK || n_pairs == 0) return chk;
+  if (o.graph || o.profile) return failw(XD_EINVAL, who, "graph and profile options do not apply");
+  if (device < 0 || device >= kNaMaxDevices) return failw(XD_EINVAL, who, "no such device");
+  std::lock_guard<std::mutex> lock(g_na_mu);
+  int ndev = 0, prev = 0;
+  XD_HIP(hipGetDeviceCount(&ndev));
+  if (device >= ndev) return failw(XD_EINVAL, who, "no such device");
+  XD_HIP(hipGetDevice(&prev));
+  XD_HIP(hipSetDevice(device));
+  xd_status st = noalloc_setup(device);
+  if (st == XD_OK) {
+    Launch L;
+    std::memset(&L, 0, sizeof(L));
+    L.d_a = d_a; L.a_words = a_words; L.d_b = d_b; L.b_words = b_words;
+    L.d_pairs = d_pairs; L.n_pairs = n_pairs; L.sc = sc; L.d_out = d_out; L.o = o;
+    st = enqueue(&g_na_ctx[device], g_na[device].b, (hipStream_t)stream, L, false);
+  }
+  const hipError_t e = hipSetDevice(prev);
+  if (st == XD_OK && e != hipSuccess)
+    return fail(XD_EDEVICE, std::string("xdrop_extend_noalloc: restoring the device: ") +
+                                hipGetErrorString(e));
+  return st;
+}
+
+}  // extern "C"
+
 #include "xd_server.h"

@@ -114,6 +114,8 @@ def lib() -> ctypes.CDLL:
         L.xd_find_seeds.argtypes = [p, p, u64, p, u64, p, sz, ctypes.c_uint32, ctypes.c_uint32,
                                     ctypes.c_int32, p, p]
         L.xd_find_seeds.restype = i32
+        L.xdrop_extend_noalloc.argtypes = [i32, p, u64, p, u64, p, sz, Scores, p, p, p]
+        L.xdrop_extend_noalloc.restype = i32
         L.xdrop_extend_host.argtypes = [p, p, u64, p, u64, p, sz, Scores, p, p]
         L.xdrop_extend_host.restype = i32
         L.xd_last_stats.argtypes = [p, ctypes.POINTER(Stats)]
@@ -329,6 +331,22 @@ class Context:
         if st.profiled:
             out["stage_ms"] = np.array(list(st.stage_ms), np.float64)
         return out
+
+
+NOALLOC_MAX_PAIRS = 8192
+
+
+def extend_noalloc(db: DeviceBatch, device: int = 0, stream: Optional[torch.cuda.Stream] = None,
+                   opts: Optional[Opts] = None, scores: Optional[Sequence[int]] = None):
+    """Enqueues xdrop_extend_noalloc (no context, no device allocation) on
+    ``stream`` (default: torch's current stream of ``device``)."""
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    sc = Scores(*(scores if scores is not None else db.scores))
+    _check(lib().xdrop_extend_noalloc(device, db.d_a.data_ptr(), len(db.a_words),
+                                      db.d_b.data_ptr(), len(db.b_words), db.d_pairs.data_ptr(),
+                                      db.n, sc, db.d_out.data_ptr(),
+                                      ctypes.c_void_p(s.cuda_stream),
+                                      ctypes.byref(opts) if opts is not None else None))
 
 
 class PackedRequest:

@@ -146,3 +146,24 @@ def test_server_rejects_null_arguments_without_a_device(L):
     assert L.xd_server_get_stats(None, None) == xdrop.XD_EINVAL
     L.xd_server_destroy(None)
 
+
+def test_noalloc_rejects_before_touching_a_device(L):
+    """xdrop_extend_noalloc refuses oversize batches and the graph/profile
+    options from the arguments alone (no device is touched, so this runs
+    without a GPU; the pointers are never dereferenced)."""
+    from paper_2002_05200_amd import xdrop
+    fake = ctypes.c_void_p(0x1000)
+    sc = xdrop.Scores(1, -1, -1)
+    rc = L.xdrop_extend_noalloc(0, fake, 1, fake, 1, fake, xdrop.NOALLOC_MAX_PAIRS + 1, sc,
+                                fake, None, None)
+    assert rc == xdrop.XD_EINVAL and "XD_NOALLOC_MAX_PAIRS" in xdrop.last_error()
+    for kw in (dict(profile=1), dict(graph=1)):
+        o = xdrop.make_opts(**kw)
+        rc = L.xdrop_extend_noalloc(0, fake, 1, fake, 1, fake, 4, sc, fake, fake, ctypes.byref(o))
+        assert rc == xdrop.XD_EINVAL, kw
+    rc = L.xdrop_extend_noalloc(0, fake, 1, fake, 1, fake, 4, xdrop.Scores(1, 2, -1), fake,
+                                None, None)
+    assert rc == xdrop.XD_EINVAL
+    assert L.xdrop_extend_noalloc(0, None, 0, None, 0, None, 0, sc, None, None, None) == 0
+    text = open(HEADER).read()
+    assert re.search(r"#define XD_NOALLOC_MAX_PAIRS %d\b" % xdrop.NOALLOC_MAX_PAIRS, text)
