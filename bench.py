@@ -16,7 +16,9 @@ grid against the persistent queue) on the same resident inputs;
 both ways and the step) on the same reads.  `other_workloads` times the
 plain 1 kb, uneven and ultra-long batches whole with the autotuner's options
 (uneven and plain1k also with the plain grids, on the same resident inputs)
-and checks every pair against the oracle's stored digests.  `serving` is the
+and checks every pair against the oracle's stored digests.  `seed_choice`
+times the GPU seed choice (xd_find_seeds) over the same resident reads and
+checks a sample against the seed oracle.  `serving` is the
 continuous-batching server under Poisson arrivals at a fraction of its
 saturation rate, with a sweep over further loads.  `cpu_baseline` times the
 CPU oracle, single-threaded, on an evenly spread sample of the same workload,
@@ -302,6 +304,90 @@ def host_buffers(ctx, db, args, tuned, cells_per_step, ref) -> dict:
             "note": "pageable host buffers; includes device allocation and both copies"}
 
 
+def kernel_name(tier: int, multi_wave: int):
+    """Name and file tag of the kernel that runs a tier (stage) of the step."""
+    if tier >= 6:
+        return "k_spill (global-memory band)", "k_spill"
+    c = 1 << tier
+    if tier >= 3 and multi_wave in (1, 2):
+        nw = 4 if multi_wave == 1 else 2
+        return (f"k_extend_mw<{nw}, {c // nw}> ({nw} wavefronts per job, {c} cells per lane "
+                f"in all)", f"k_extend_mw{nw}{c // nw}")
+    return f"k_extend<C={c}> (cells per lane {c})", f"k_extend_c{c}"
+
+
+def dominant_kernel(ctx, db, opts_kw: dict) -> dict:
+    """One profiled step (HIP events around every stage on the launch stream):
+    the stage that takes longest, priced against the INT32 roofline."""
+    import torch
+    from paper_2002_05200_amd import xdrop
+    ctx.extend_device(db, opts=xdrop.make_opts(profile=1, **{k: v for k, v in opts_kw.items()
+                                                             if k != "graph"}))
+    st = ctx.stats()
+    torch.cuda.synchronize()
+    tiers_ms = st["stage_ms"][1:8]
+    dom = int(np.argmax(tiers_ms))
+    cells = int(st["cells"][dom])
+    ms = float(tiers_ms[dom])
+    name, _ = kernel_name(dom, opts_kw.get("multi_wave", 0))
+    achieved = cells * OPS_PER_CELL / (ms / 1e3) / 1e12
+    return {"kernel": name, "ms": round(ms, 3), "cells": cells,
+            "frac": round(achieved / INT32_PEAK_TOPS, 4),
+            "stage_ms": {k: round(float(v), 3) for k, v in zip(
+                ["plan", "tier0", "tier1", "tier2", "tier3", "tier4", "tier5", "spill",
+                 "combine"], st["stage_ms"])}}
+
+
+def seed_leg(ctx, db, steps: int, k: int = 17, width: int = 500):
+    """xd_find_seeds over the same resident reads (every pair's k-mer matches
+    binned by diagonal), timed with HIP events on its stream.  Returns the
+    record and the seeds (checked against the seed oracle in the CPU leg)."""
+    import torch
+    from paper_2002_05200_amd import xdrop
+    stream = torch.cuda.current_stream()
+    d_seeds = ctx.find_seeds_device(db, k=k, width=width)          # warm-up
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        ctx.find_seeds_device(db, k=k, width=width, d_seeds=d_seeds)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    got = d_seeds[: db.n * xdrop.SEED_DTYPE.itemsize].cpu().numpy().view(xdrop.SEED_DTYPE).copy()
+    kmers = int(np.maximum(db.pairs["a_len"].astype(np.int64) - k + 1, 0).sum() +
+                np.maximum(db.pairs["b_len"].astype(np.int64) - k + 1, 0).sum())
+    bases = int(db.pairs["a_len"].astype(np.int64).sum() + db.pairs["b_len"].astype(np.int64).sum())
+    rec = {"api": "xd_find_seeds", "k": k, "width": width, "steps": steps,
+           "ms_per_call": round(ms, 3), "pairs_per_s": round(db.n / (ms / 1e3), 1),
+           "gkmers_per_s": round(kmers / (ms / 1e3) / 1e9, 3),
+           "packed_bases_gb_per_s": round(bases / 4 / (ms / 1e3) / 1e9, 2),
+           "found": int((got["found"] == 1).sum()), "pairs": db.n,
+           "matches_total": int(got["matches"].sum())}
+    return rec, got
+
+
+def seed_oracle_check(workload: str, gpu_seeds, n_check: int = 2000, k: int = 17,
+                      width: int = 500) -> dict:
+    """The seed oracle on an evenly spread sample of the workload's pairs,
+    compared field by field with the GPU's seeds of those pairs."""
+    from oracle import oracle
+    from paper_2002_05200_amd import synth
+    n = len(gpu_seeds)
+    stride = max(1, n // n_check)
+    idx = np.arange(0, n, stride)[:n_check]
+    bt = synth.make_batch(workload, n=len(idx), start=0, stride=stride)
+    t0 = time.perf_counter()
+    ref = oracle.find_seeds(bt, k=k, width=width)
+    secs = time.perf_counter() - t0
+    fields = ["a_seed", "b_seed", "bin_matches", "matches", "found", "status"]
+    bad = [int(i) for j, i in enumerate(idx)
+           if any(int(gpu_seeds[f][i]) != int(ref[f][j]) for f in fields)]
+    return {"pairs_compared": len(idx), "mismatched_pairs": len(bad), "first": bad[:5],
+            "sample": f"every {stride}th pair", "oracle_s": round(secs, 2),
+            "oracle_pairs_per_s_one_thread": round(len(idx) / secs, 1)}
+
+
 def workload_leg(name: str, steps: int, plain: bool, workers: int) -> dict:
     """Another batch workload timed whole with the autotuner's options (and,
     with `plain`, with the plain one-wavefront-per-job grids on the same
@@ -315,24 +401,28 @@ def workload_leg(name: str, steps: int, plain: bool, workers: int) -> dict:
     bt, _ = digests.generate(name, workers)
     gen_s = time.time() - t0
     tuned = tune.lookup(bt) or {}
-    tuned.pop("sched", None)
     db = xdrop.DeviceBatch(bt, "cuda:0")
     del bt
     ctx = xdrop.Context(0)
     golden = digests.load()["workloads"].get(name)
+    if name == "plain1k":           # sub-millisecond steps: time many
+        steps = max(steps, 50)
     out = {"workload": synth.WORKLOADS[name].describe, "pairs": db.n,
            "generate_s": round(gen_s, 1)}
     try:
-        variants = [("tuned", xdrop.make_opts(**tuned))]
+        variants = [("tuned", xdrop.make_opts(**tuned), None)]
         if plain:
-            variants.append(("plain", xdrop.make_opts(sched=xdrop.SCHED_PLAIN)))
+            variants.append(("plain", xdrop.make_opts(sched=xdrop.SCHED_PLAIN), None))
+        if name == "plain1k":       # a small batch: launches dominate, so replay a graph
+            variants.append(("tuned_graph", xdrop.make_opts(graph=1, **tuned),
+                             torch.cuda.Stream()))
         ref = None
-        for label, o in variants:
-            ctx.extend_device(db, opts=o)                 # warm-up
+        for label, o, strm in variants:
+            ctx.extend_device(db, opts=o, stream=strm)    # warm-up (and graph capture)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             for _ in range(steps):
-                ctx.extend_device(db, opts=o)
+                ctx.extend_device(db, opts=o, stream=strm)
             torch.cuda.synchronize()
             el = (time.perf_counter() - t1) / steps
             res = db.results()
@@ -344,6 +434,7 @@ def workload_leg(name: str, steps: int, plain: bool, workers: int) -> dict:
                 st = ctx.stats()
                 rec["jobs_per_tier"] = st["jobs"].tolist()
                 rec["restarted"] = int(st["restarted"].sum())
+                rec["dominant_kernel"] = dominant_kernel(ctx, db, tuned)
             if ref is None:
                 ref = res
             else:
@@ -403,6 +494,8 @@ def main():
                     help="further batch workloads timed whole (tuned options; uneven and "
                          "plain1k also with the plain grids), empty = none")
     ap.add_argument("--other-steps", type=int, default=3)
+    ap.add_argument("--seed-steps", type=int, default=5,
+                    help="timed xd_find_seeds calls over the batch's reads (0 = skip)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic, to scale HBM byte counters)")
@@ -491,9 +584,7 @@ def main():
     dom_ms_per_launch = tiers_ms[dom] / args.steps
     dom_cells_per_launch = tier_cells[dom] / args.steps
     achieved = dom_cells_per_launch * OPS_PER_CELL / (dom_ms_per_launch / 1e3) / 1e12
-    kname = (f"k_extend<C={1 << dom}> (cells per lane {1 << dom})" if dom < 6
-             else "k_spill (global-memory band)")
-    ktag = f"k_extend_c{1 << dom}" if dom < 6 else "k_spill"
+    kname, ktag = kernel_name(dom, tuned.get("multi_wave", 0))
     traffic, traffic_src = profiled_traffic(ktag, args.workload)
     if n_pairs != wl.n_pairs:          # the summary covers the whole workload only
         traffic, traffic_src = None, None
@@ -528,6 +619,10 @@ def main():
     if not args.no_compare:
         line["sched_compare"] = sched_compare(ctx, db, stream, args, tuned, gcups, res2)
         line["host_buffers"] = host_buffers(ctx, db, args, tuned, cells_per_step, res2)
+    gpu_seeds = None
+    if args.seed_steps and args.workload == "batch10k" and n_pairs == wl.n_pairs:
+        line["seed_choice"], gpu_seeds = seed_leg(ctx, db, args.seed_steps)
+        print(f"[bench] seed choice: {line['seed_choice']}", file=sys.stderr, flush=True)
     ctx.close()
     del db
     others = [w.strip() for w in args.other_workloads.split(",") if w.strip()]
@@ -543,6 +638,11 @@ def main():
                                       sweep, args.serving_sweep_requests)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget, n_pairs, res2)
+        if gpu_seeds is not None:
+            sc = seed_oracle_check(args.workload, gpu_seeds)
+            line["cpu_baseline"]["seed_oracle"] = sc
+            line["seed_choice"]["oracle_parity"] = {
+                k: sc[k] for k in ("pairs_compared", "mismatched_pairs", "first", "sample")}
         if dom < 6:
             ce = eq1_ceiling(args.workload, n_pairs, dom)
             ce["achieved_over_ceiling"] = round(line["roofline"]["frac"] / ce["frac"], 4) \

@@ -7,7 +7,9 @@ The kernels' results never depend on these options, only their speed does:
   grow wide skip the narrow windows they would outgrow);
 - sort_jobs: longest-estimated-job-first order on or off;
 - multi_wave: four (1) or two (2) wavefronts per job in the widest
-  single-job tiers.
+  single-job tiers;
+- sched: the persistent queue (0) or the plain grids of one wavefront per job
+  (1), which win on small batches whose time is mostly launches.
 
 `tune` times candidates on a sample batch already resident on the device
 (coordinate descent from the defaults, median of a few repetitions, timed
@@ -35,6 +37,7 @@ TABLE_PATH = os.path.join(HERE, "tune_table.json")
 # four-wavefront job needs a grid large enough that the longest jobs, not the
 # queue, set the end), so those two are searched jointly.
 CANDIDATES: Dict[str, list] = {
+    "sched": [0, 1],
     "long_tier_bias": [0, 1, 2, 3],
     "long_job": [2000, 10000, 40000],
     "multi_wave+waves_per_cu": [(m, w) for m in (0, 1, 2) for w in (0, 8, 16, 24)],
