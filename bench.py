@@ -36,6 +36,10 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# The serving leg runs several slots, each on its own stream; HIP maps streams
+# onto GPU_MAX_HW_QUEUES hardware queues (4 unless set), and streams sharing a
+# queue run their kernels one after another.  Set before the runtime starts.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 METRIC = "GCUPS (computed cells) at 1 MI355X, % INT32 roofline; p50/p99 latency in serving"
 OPS_PER_CELL = 9                       # algorithmic int32 operations per cell
@@ -172,7 +176,8 @@ def cpu_all_cores(workload: str, n_total: int, n_sample: int, gpu_results=None) 
 
 
 def serving_leg(n_distinct: int, n_requests: int, load: float, slots: int, max_batch: int,
-                graph: bool, workers: int, sweep=(), sweep_requests: int = 0) -> dict:
+                graph: bool, workers: int, sweep=(), sweep_requests: int = 0,
+                sched: str = "plain", by_class: bool = True) -> dict:
     """Continuous-batching serving run: saturation throughput closed-loop (whose
     requests are also the warm-up), then Poisson arrivals at load * saturation;
     latency from the scheduled arrival to the completion the server's
@@ -190,8 +195,11 @@ def serving_leg(n_distinct: int, n_requests: int, load: float, slots: int, max_b
     packed = [xdrop.PackedRequest(bt) for bt in reqs]
     print(f"[bench] serving: {n_distinct} distinct requests generated in {time.time()-t0:.1f} s",
           file=sys.stderr, flush=True)
+    sched_code = {"auto": xdrop.SCHED_AUTO, "plain": xdrop.SCHED_PLAIN,
+                  "persistent": xdrop.SCHED_PERSISTENT}[sched]
     srv = xdrop.Server(slots=slots, max_batch_pairs=max_batch, graph=int(graph),
-                       mem_budget=2 << 30)
+                       mem_budget=2 << 30, opts=xdrop.make_opts(sched=sched_code),
+                       group_by_class=int(by_class))
     try:
         def closed(n):
             ts = [srv.submit(packed[i % n_distinct]) for i in range(n)]
@@ -252,6 +260,9 @@ def serving_leg(n_distinct: int, n_requests: int, load: float, slots: int, max_b
            "distinct_requests": n_distinct, "saturation_requests_per_s": round(r_sat, 1)}
     out.update(main_run)
     out.update({"slots": slots, "max_batch_pairs": max_batch, "graph": bool(graph),
+                "batch_sched": sched, "group_by_class": bool(by_class),
+                "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
+                "device_bytes": st["device_bytes"], "mem_budget": 2 << 30,
                 "batches": st["batches"], "max_inflight": st["max_inflight"],
                 "load_sweep": others, "workload": synth.WORKLOADS["serving"].describe})
     return out
@@ -480,7 +491,11 @@ def main():
     ap.add_argument("--serving-distinct", type=int, default=1000,
                     help="distinct generated requests the serving leg cycles through")
     ap.add_argument("--serving-load", type=float, default=0.7)
-    ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--serving-sched", default="plain", choices=["auto", "plain", "persistent"],
+                    help="launch schedule of each serving batch (small batches: plain grids)")
+    ap.add_argument("--serving-by-class", type=int, default=1,
+                    help="1 = batches take requests of one cost class only")
     ap.add_argument("--serving-batch", type=int, default=2048)
     ap.add_argument("--serving-graph", type=int, default=1)
     ap.add_argument("--multi-wave", type=int, default=None,
@@ -635,7 +650,8 @@ def main():
         line["serving"] = serving_leg(args.serving_distinct, args.serving_requests,
                                       args.serving_load, args.serving_slots, args.serving_batch,
                                       bool(args.serving_graph), min(16, os.cpu_count() or 1),
-                                      sweep, args.serving_sweep_requests)
+                                      sweep, args.serving_sweep_requests, args.serving_sched,
+                                      bool(args.serving_by_class))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget, n_pairs, res2)
         if gpu_seeds is not None:

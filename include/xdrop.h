@@ -301,7 +301,12 @@ typedef struct xd_server xd_server;
 
 typedef struct {
     int32_t device;
-    int32_t slots;            /* batches in flight at once, 1..16 (0 = 4)           */
+    int32_t slots;            /* batches in flight at once, 1..16 (0 = 4); each
+                                 slot has its own stream, and HIP runs the
+                                 streams of a process on GPU_MAX_HW_QUEUES
+                                 hardware queues (4 unless the environment sets
+                                 it before the runtime starts): slots beyond that
+                                 share queues and their kernels serialise       */
     int32_t max_batch_pairs;  /* pairs per batch (0 = 2048)                         */
     int32_t graph;            /* 1 = every slot replays a captured hipGraph of
                                  xdrop_extend (batches padded to max_batch_pairs)  */
