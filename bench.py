@@ -38,8 +38,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 # The serving leg runs several slots, each on its own stream; HIP maps streams
 # onto GPU_MAX_HW_QUEUES hardware queues (4 unless set), and streams sharing a
-# queue run their kernels one after another.  Set before the runtime starts.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+# queue run their kernels one after another.  Set before the runtime starts
+# (an environment that already fixes a smaller number is raised to 16).
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < 16:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 METRIC = "GCUPS (computed cells) at 1 MI355X, % INT32 roofline; p50/p99 latency in serving"
 OPS_PER_CELL = 9                       # algorithmic int32 operations per cell
