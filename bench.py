@@ -212,8 +212,11 @@ def serving_leg(n_distinct: int, n_requests: int, load: float, slots: int, max_b
             return cells
         closed(min(200, n_distinct))                       # warm-up (graphs, scratch)
         t1 = time.perf_counter()
-        closed(n_distinct)
-        r_sat = n_distinct / (time.perf_counter() - t1)
+        n_sat = 3 * n_distinct             # long enough that ramp-up and drain are small
+        sat_cells = closed(n_sat)
+        sat_s = time.perf_counter() - t1
+        r_sat = n_sat / sat_s
+        sat_gcups = sat_cells / sat_s / 1e9
 
         def open_loop(load, n_requests, seed_key):
             rate = load * r_sat
@@ -258,8 +261,9 @@ def serving_leg(n_distinct: int, n_requests: int, load: float, slots: int, max_b
         st = srv.stats()
     finally:
         srv.close()
-    out = {"requests": n_requests, "warmup_requests": min(200, n_distinct) + n_distinct,
-           "distinct_requests": n_distinct, "saturation_requests_per_s": round(r_sat, 1)}
+    out = {"requests": n_requests, "warmup_requests": min(200, n_distinct) + n_sat,
+           "distinct_requests": n_distinct, "saturation_requests_per_s": round(r_sat, 1),
+           "saturation_gcups": round(sat_gcups, 2), "saturation_requests": n_sat}
     out.update(main_run)
     out.update({"slots": slots, "max_batch_pairs": max_batch, "graph": bool(graph),
                 "batch_sched": sched, "group_by_class": bool(by_class),

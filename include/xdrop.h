@@ -47,7 +47,8 @@ typedef enum {
     XD_EBUSY = 4,      /* serving: no admission capacity right now                   */
     XD_EOVERFLOW = 5,  /* pair: int32 score range could be exceeded (see xdrop_extend) */
     XD_ECANCELED = 6,  /* serving: request canceled                                  */
-    XD_ENOTREADY = 7   /* serving: result not complete yet                           */
+    XD_ENOTREADY = 7,  /* serving: result not complete yet                           */
+    XD_ETIMEDOUT = 8   /* serving: the request's batch outran the server's watchdog   */
 } xd_status;
 
 /* Linear-gap scoring (Section III-A), signed and additive: a match adds
@@ -316,7 +317,11 @@ typedef struct {
                                  profile are set by the server)                     */
     int32_t group_by_class;   /* 1 = a batch takes only requests of the oldest
                                  request's cost class; 0 = any, in arrival order    */
-    int32_t reserved;         /* must be 0                                          */
+    int32_t watchdog_ms;      /* 0 = off; else a batch still running this many
+                                 milliseconds after its launch fails its requests
+                                 with XD_ETIMEDOUT at once (their polls return);
+                                 its kernels still run to the end, and the slot
+                                 takes new work only after they have             */
 } xd_server_opts; /* 80 bytes */
 
 /* One request: host buffers, read by xd_server_submit before it returns. */
@@ -344,7 +349,8 @@ xd_status xd_server_submit(xd_server *srv, const xd_request *req, uint64_t *tick
  * time (nanoseconds, CLOCK_MONOTONIC) at which the scheduler saw the batch
  * complete in done_ns (if not NULL), releases the ticket and returns XD_OK.
  * XD_ENOTREADY if not done in time; XD_EINVAL for an unknown ticket;
- * XD_EDEVICE if its batch failed. */
+ * XD_EDEVICE if its batch failed; XD_ETIMEDOUT if its batch outran the
+ * watchdog; XD_ECANCELED if it was canceled. */
 xd_status xd_server_poll(xd_server *srv, uint64_t ticket, xd_result *out, int32_t wait_ms,
                          uint64_t *done_ns);
 
@@ -360,6 +366,7 @@ typedef struct {
                                           slot: the reads one batch can hold      */
     uint64_t waiting_polls;            /* xd_server_poll calls waiting inside the
                                           server now                              */
+    uint64_t timed_out;                /* requests failed by the watchdog         */
 } xd_server_stats;
 
 xd_status xd_server_get_stats(xd_server *srv, xd_server_stats *out);

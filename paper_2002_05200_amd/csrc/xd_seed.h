@@ -10,9 +10,11 @@
 // bin on a tie; the seed is that bin's match with the smallest p, then q.
 //
 // One workgroup per pair.  B's k-mers go into an open-addressing hash table
-// in LDS that stores only their positions (4 bytes a slot); the packed bases
-// of B's segment sit in LDS beside it, so a probe verifies a candidate by
-// re-reading its k-mer there.  A is streamed through LDS in chunks, every
+// in LDS whose 4-byte slots hold a k-mer's position and 19 further bits of
+// its hash (a tag); the packed bases of B's segment sit in LDS beside it, so
+// a probe compares tags first and verifies only a candidate whose tag agrees
+// by re-reading its k-mer there.  Each thread walks a contiguous run of A's
+// k-mers and rolls the k-mer code along it.  A is streamed through LDS in chunks, every
 // k-mer of A probes the table, and each exact match adds to its diagonal
 // bin's count and lowers the bin's smallest (p, q) with LDS atomics.  Reads
 // longer than one table fill run segment by segment (A is scanned once per
@@ -37,7 +39,9 @@ constexpr int kSeedBins = 2048;               // diagonal bins per window
 // before it, kSeedSeg k-mers of up to 31 bases, and the two words the last
 // k-mer's three-word read may touch
 constexpr int kSeedWords = (15 + kSeedSeg + 30 + 15) / 16 + 2;
-constexpr uint32_t kSeedEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kSeedEmpty = 0u;          // slot = (tag << 13) | (position + 1)
+constexpr int kSeedTagBits = 19;
+static_assert(kSeedSeg <= (1 << 13) - 1, "positions + 1 fit the slot's 13 low bits");
 constexpr int kSeedMaxK = 31;
 
 struct SeedArgs {
@@ -61,9 +65,16 @@ __device__ __forceinline__ uint64_t seed_kmer(const uint32_t *w, uint32_t t, uin
   return v & mask;
 }
 
-// Fibonacci (multiplicative) hashing of a k-mer code onto the table.
-__device__ __forceinline__ uint32_t seed_hash(uint64_t code) {
-  return (uint32_t)((code * 0x9E3779B97F4A7C15ull) >> (64 - kSeedTabBits));
+// Fibonacci (multiplicative) hashing of a k-mer code: the top bits index the
+// table, the next kSeedTagBits bits are the tag kept in the slot.
+__device__ __forceinline__ uint64_t seed_mix(uint64_t code) {
+  return code * 0x9E3779B97F4A7C15ull;
+}
+__device__ __forceinline__ uint32_t seed_index(uint64_t mix) {
+  return (uint32_t)(mix >> (64 - kSeedTabBits));
+}
+__device__ __forceinline__ uint32_t seed_tag(uint64_t mix) {
+  return (uint32_t)(mix >> (64 - kSeedTabBits - kSeedTagBits)) & ((1u << kSeedTagBits) - 1u);
 }
 
 // Packed words [g0 / 16, g0 / 16 + nw) of an arena into LDS (zero past its end).
@@ -133,8 +144,10 @@ __global__ __launch_bounds__(kSeedThreads) void k_find_seeds(SeedArgs S) {
           seed_load(bw, S.B, S.b_words, gb, (int)((sb + seg_n + k - 1 + 15) / 16) + 2);
           __syncthreads();
           for (int v = tid; v < seg_n; v += kSeedThreads) {
-            uint32_t h = seed_hash(seed_kmer(bw, sb + v, kmask));
-            while (atomicCAS(&tab[h], kSeedEmpty, (uint32_t)v) != kSeedEmpty)
+            const uint64_t mix = seed_mix(seed_kmer(bw, sb + v, kmask));
+            const uint32_t entry = (seed_tag(mix) << 13) | (uint32_t)(v + 1);
+            uint32_t h = seed_index(mix);
+            while (atomicCAS(&tab[h], kSeedEmpty, entry) != kSeedEmpty)
               h = (h + 1) & (kSeedTab - 1);
           }
           for (int64_t ach = 0; ach < nA; ach += kSeedChunk) {
@@ -144,13 +157,24 @@ __global__ __launch_bounds__(kSeedThreads) void k_find_seeds(SeedArgs S) {
             const uint32_t sa = (uint32_t)(ga & 15);
             seed_load(aw, S.A, S.a_words, ga, (int)((sa + a_n + k - 1 + 15) / 16) + 2);
             __syncthreads();
-            for (int u = tid; u < a_n; u += kSeedThreads) {
-              const uint64_t code = seed_kmer(aw, sa + u, kmask);
-              uint32_t h = seed_hash(code);
+            // a contiguous run of A's k-mers per thread, the code rolled along it
+            const int run = (a_n + kSeedThreads - 1) / kSeedThreads;
+            const int u0 = tid * run, u1 = u0 + run < a_n ? u0 + run : a_n;
+            uint64_t code = u0 < u1 ? seed_kmer(aw, sa + u0, kmask) : 0;
+            for (int u = u0; u < u1; ++u) {
+              if (u > u0) {   // base u + k - 1 enters at the top, base u - 1 leaves
+                const uint32_t t = sa + (uint32_t)(u + k - 1);
+                code = (code >> 2) | ((uint64_t)((aw[t >> 4] >> ((t & 15u) * 2u)) & 3u)
+                                      << (2 * (k - 1)));
+              }
+              const uint64_t mix = seed_mix(code);
+              const uint32_t tag = seed_tag(mix);
+              uint32_t h = seed_index(mix);
               for (;;) {
-                const uint32_t v = tab[h];
-                if (v == kSeedEmpty) break;
-                if (seed_kmer(bw, sb + v, kmask) == code) {
+                const uint32_t e = tab[h];
+                if (e == kSeedEmpty) break;
+                const uint32_t v = (e & 0x1FFFu) - 1u;
+                if ((e >> 13) == tag && seed_kmer(bw, sb + v, kmask) == code) {
                   const uint64_t p = (uint64_t)(ach + u), q = (uint64_t)(seg + v);
                   const uint64_t bin = (q + off - p) / w;
                   if (win == 0) ++my_total;

@@ -49,7 +49,8 @@ struct Request {
   xd_scores scores{};
   std::vector<xd_result> out;
   int32_t cls = 0;          // cost class (xd_admit.h)
-  int state = 0;            // 0 queued, 1 on the device, 2 done, 3 failed, 4 canceled
+  int state = 0;            // 0 queued, 1 on the device, 2 done, 3 failed, 4 canceled,
+                            // 5 timed out (watchdog)
   uint64_t done_ns = 0;
 };
 
@@ -67,6 +68,8 @@ struct Slot {
   int32_t cap_pairs = 0;
   uint64_t device_bytes = 0;   // arenas, pair records, results and the context
   bool busy = false;
+  bool draining = false;       // the watchdog failed this batch; its kernels still run
+  uint64_t launched_ns = 0;
   int32_t n_pairs = 0;
   std::vector<std::shared_ptr<Request>> reqs;
   std::vector<int32_t> first;   // first pair of each request in the batch
@@ -214,21 +217,47 @@ void finish_batch(xd_server *srv, Slot &s, bool ok) {
   srv->cv_done.notify_all();
 }
 
+// The watchdog: the requests of a batch that has run too long fail now; the
+// slot keeps draining until its kernels are done.
+void expire_batch(xd_server *srv, Slot &s) {
+  const uint64_t now = steady_ns();
+  {
+    std::lock_guard<std::mutex> lock(srv->mu);
+    for (auto &r : s.reqs) {
+      r->state = 5;
+      r->done_ns = now;
+      srv->st.timed_out += 1;
+    }
+  }
+  s.reqs.clear();
+  s.draining = true;
+  srv->cv_done.notify_all();
+}
+
 void scheduler(xd_server *srv) {
   (void)hipSetDevice(srv->o.device);
   for (;;) {
     bool progress = false;
     int inflight = 0;
+    const uint64_t wd_ns = (uint64_t)srv->o.watchdog_ms * 1000000ull;
     for (Slot &s : srv->slots) {   // completions
       if (!s.busy) continue;
       const hipError_t e = hipEventQuery(s.done);
-      if (e == hipSuccess) {
+      if (e != hipErrorNotReady && s.draining) {   // a timed-out batch has drained
+        s.busy = false;
+        s.draining = false;
+        progress = true;
+      } else if (e == hipSuccess) {
         finish_batch(srv, s, true);
         progress = true;
       } else if (e != hipErrorNotReady) {
         finish_batch(srv, s, false);
         progress = true;
       } else {
+        if (wd_ns && !s.draining && steady_ns() - s.launched_ns > wd_ns) {
+          expire_batch(srv, s);
+          progress = true;
+        }
         ++inflight;
       }
     }
@@ -258,6 +287,7 @@ void scheduler(xd_server *srv) {
       }
       if (s.reqs.empty()) break;
       s.busy = true;
+      s.launched_ns = steady_ns();
       ++inflight;
       if (launch_batch(srv, s) != XD_OK) {
         (void)hipStreamSynchronize(s.stream);
@@ -293,8 +323,8 @@ xd_status xd_server_create(const xd_server_opts *opts, xd_server **out) {
   if (o.mem_budget == 0) o.mem_budget = 1ull << 30;
   if (o.slots < 1 || o.slots > 16 || o.max_batch_pairs < 1 || o.max_batch_pairs > (1 << 24))
     return fail(XD_EINVAL, "xd_server_create: slots or max_batch_pairs out of range");
-  if (o.group_by_class < 0 || o.group_by_class > 1 || o.reserved != 0)
-    return fail(XD_EINVAL, "xd_server_create: group_by_class not 0/1 or reserved field set");
+  if (o.group_by_class < 0 || o.group_by_class > 1 || o.watchdog_ms < 0)
+    return fail(XD_EINVAL, "xd_server_create: group_by_class not 0/1 or negative watchdog");
   int ndev = 0;
   XD_HIP(hipGetDeviceCount(&ndev));
   if (o.device < 0 || o.device >= ndev) return fail(XD_EINVAL, "xd_server_create: no such device");
@@ -373,6 +403,8 @@ xd_status xd_server_poll(xd_server *srv, uint64_t ticket, xd_result *out, int32_
   srv->table.erase(r->ticket);
   if (done_ns) *done_ns = r->done_ns;
   if (r->state == 4) return fail(XD_ECANCELED, "xd_server_poll: the request was canceled");
+  if (r->state == 5)
+    return fail(XD_ETIMEDOUT, "xd_server_poll: the request's batch outran the watchdog");
   if (r->state == 3) return fail(XD_EDEVICE, "xd_server_poll: the request's batch failed");
   std::memcpy(out, r->out.data(), sizeof(xd_result) * r->out.size());
   return XD_OK;

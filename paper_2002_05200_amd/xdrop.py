@@ -17,7 +17,8 @@ import torch  # noqa: F401  (loads the HIP runtime libxdrop binds to)
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libxdrop.so")
 
-XD_OK, XD_EINVAL, XD_ENOMEM, XD_EDEVICE, XD_EBUSY, XD_EOVERFLOW, XD_ECANCELED, XD_ENOTREADY = range(8)
+(XD_OK, XD_EINVAL, XD_ENOMEM, XD_EDEVICE, XD_EBUSY, XD_EOVERFLOW, XD_ECANCELED, XD_ENOTREADY,
+ XD_ETIMEDOUT) = range(9)
 SCHED_AUTO, SCHED_PLAIN, SCHED_PERSISTENT = 0, 1, 2
 TIER_CELLS = (1, 2, 4, 8, 16, 32)
 
@@ -62,7 +63,7 @@ class ServerOpts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("slots", ctypes.c_int32),
                 ("max_batch_pairs", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("mem_budget", ctypes.c_uint64), ("extend_opts", Opts),
-                ("group_by_class", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("group_by_class", ctypes.c_int32), ("watchdog_ms", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -77,7 +78,8 @@ class ServerStats(ctypes.Structure):
                 ("batches", ctypes.c_uint64), ("cells", ctypes.c_uint64),
                 ("queued", ctypes.c_uint64), ("max_inflight", ctypes.c_uint64),
                 ("canceled", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
-                ("arena_words", ctypes.c_uint64), ("waiting_polls", ctypes.c_uint64)]
+                ("arena_words", ctypes.c_uint64), ("waiting_polls", ctypes.c_uint64),
+                ("timed_out", ctypes.c_uint64)]
 
 
 class XdropError(RuntimeError):
@@ -366,12 +368,13 @@ class Server:
 
     def __init__(self, device: int = 0, slots: int = 4, max_batch_pairs: int = 2048,
                  graph: int = 0, mem_budget: int = 0, opts: Optional[Opts] = None,
-                 group_by_class: int = 1):
+                 group_by_class: int = 1, watchdog_ms: int = 0):
         torch.cuda.init()
         o = ServerOpts()
         o.device, o.slots, o.max_batch_pairs, o.graph = device, slots, max_batch_pairs, graph
         o.mem_budget = mem_budget
         o.group_by_class = group_by_class
+        o.watchdog_ms = watchdog_ms
         o.extend_opts = opts if opts is not None else make_opts()
         h = ctypes.c_void_p()
         _check(lib().xd_server_create(ctypes.byref(o), ctypes.byref(h)))

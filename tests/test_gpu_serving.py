@@ -152,6 +152,35 @@ def test_cancel_and_destroy(xd, requests):
     assert all(v == xd.XD_ECANCELED or (isinstance(v, tuple)) for v in results.values())
 
 
+def test_watchdog_fails_slow_batches_and_the_server_goes_on(xd, requests):
+    """A watchdog shorter than most batches: their requests fail with
+    XD_ETIMEDOUT as soon as it fires, while their kernels still run to the end
+    (nothing on the GPU is interrupted); requests that finish in time are
+    exact; the slots are reused and the server shuts down cleanly."""
+    srv = xd.Server(slots=2, max_batch_pairs=256, mem_budget=256 << 20, watchdog_ms=1)
+    try:
+        packed = [xd.PackedRequest(bt) for bt in requests[:10]]
+        outcome = []
+        for rnd in range(2):                      # a second round reuses the drained slots
+            tickets = [srv.submit(p) for p in packed]
+            for r, (t, p) in enumerate(zip(tickets, packed)):
+                try:
+                    got = srv.poll(t, p.n, wait_ms=60000)
+                    assert got is not None
+                    assert same(got[0], oracle_of(requests[r])), f"request {r}"
+                    outcome.append("ok")
+                except xd.XdropError as e:
+                    assert e.status == xd.XD_ETIMEDOUT, e
+                    outcome.append("timed out")
+        print(f"[serving] watchdog outcomes {outcome}", flush=True)
+        assert "timed out" in outcome
+        assert srv.stats()["timed_out"] == outcome.count("timed out")
+    finally:
+        srv.close()
+    with pytest.raises(xd.XdropError):
+        xd.Server(slots=1, watchdog_ms=-1)
+
+
 def test_oversized_request_is_rejected(xd, requests):
     srv = xd.Server(slots=1, max_batch_pairs=4, mem_budget=8 << 20)
     try:
