@@ -504,6 +504,8 @@ def main():
                     help="1 = batches take requests of one cost class only")
     ap.add_argument("--serving-batch", type=int, default=2048)
     ap.add_argument("--serving-graph", type=int, default=1)
+    ap.add_argument("--waves-per-cu", type=int, default=None,
+                    help="force the persistent grid size (default: tuned table or per tier)")
     ap.add_argument("--multi-wave", type=int, default=None,
                     help="force the multi_wave launch option (default: tuned table or 0)")
     ap.add_argument("--tuned", action="store_true",
@@ -545,6 +547,8 @@ def main():
               flush=True)
     if args.multi_wave is not None:
         tuned["multi_wave"] = args.multi_wave
+    if args.waves_per_cu is not None:
+        tuned["waves_per_cu"] = args.waves_per_cu
     t0 = time.time()
     db = xdrop.DeviceBatch(bt, "cuda:0")
     del bt.a, bt.b

@@ -164,10 +164,12 @@ __global__ __launch_bounds__(kPlanBlock) void k_scatter(const int32_t *__restric
 
 // One job per wavefront.  Plain: wave w of the grid takes work item w.
 // Persistent (head != nullptr): waves pop work items until none is left.
+// The 32-register tier is held to 256 VGPRs (two resident wavefronts per
+// SIMD instead of one), so a second job hides the first one's latencies.
 template <int C, bool NARROW>
-__global__ __launch_bounds__(kBlock) void k_extend(const Job *__restrict__ jobs, TierQueue q,
-                                                   int32_t *head, JobOut *__restrict__ outs,
-                                                   unsigned long long *stats, Params P) {
+__global__ __launch_bounds__(kBlock, C >= 32 && NARROW ? 2 : 1) void k_extend(
+    const Job *__restrict__ jobs, TierQueue q, int32_t *head, JobOut *__restrict__ outs,
+    unsigned long long *stats, Params P) {
   const int wave = uniform((int32_t)(threadIdx.x >> 6));
   const int32_t n_init = q.counters[kInit + q.tier];
   const int32_t n_esc = q.counters[kEsc + q.tier];
@@ -512,9 +514,9 @@ template <bool NARROW>
 hipError_t launch_tiers(xd_ctx *c, const Bufs &B, hipStream_t s, bool persistent, int waves_per_cu,
                         int64_t nj, const Params &P, bool prof, int mw) {
   // waves per CU: each tier's resident limit from its register footprint
-  // (4 SIMDs x waves per SIMD: 7, 5, 7, 5, 3, 1 for C = 1 .. 32), rounded up
+  // (4 SIMDs x waves per SIMD: 7, 5, 7, 5, 3, 2 for C = 1 .. 32), rounded up
   // for the narrow tiers, whose queues are long
-  const int wpc[kTiers] = {32, 32, 28, 20, 12, 4};
+  const int wpc[kTiers] = {32, 32, 28, 20, 12, 8};
   auto w = [&](int t) { return waves_per_cu > 0 ? waves_per_cu : wpc[t]; };
   hipError_t e;
   auto mark = [&](int i) { return prof ? hipEventRecord(c->ev[i], s) : hipSuccess; };
@@ -613,14 +615,17 @@ xd_status enqueue(xd_ctx *c, const Bufs &B, hipStream_t s, const Launch &L, bool
     q.esc = B.esc_sorted;
     int32_t *huge_list = B.esc + kLists * stride;
     // 8,192 slots: 8 wavefronts of 16 registers (measured faster than 16 of 8:
-    // fewer waves take part in each anti-diagonal's barrier and reduction)
+    // fewer waves take part in each anti-diagonal's barrier and reduction);
+    // one workgroup per CU (two per CU measured the same on uneven: the
+    // tier's time is its longest job's)
     constexpr int kHugeNW = 8, kHugeC = 16;
+    const unsigned huge_grid = (unsigned)c->num_cu;
     if (narrow)
-      hipLaunchKernelGGL((k_extend_mw<kHugeNW, kHugeC, true>), dim3((unsigned)c->num_cu),
+      hipLaunchKernelGGL((k_extend_mw<kHugeNW, kHugeC, true>), dim3(huge_grid),
                          dim3(64 * kHugeNW), 0, s, B.jobs, q, B.counters + kHead + kTiers,
                          B.outs, B.stats, P, huge_list, B.counters + kHugeCount);
     else
-      hipLaunchKernelGGL((k_extend_mw<kHugeNW, kHugeC, false>), dim3((unsigned)c->num_cu),
+      hipLaunchKernelGGL((k_extend_mw<kHugeNW, kHugeC, false>), dim3(huge_grid),
                          dim3(64 * kHugeNW), 0, s, B.jobs, q, B.counters + kHead + kTiers,
                          B.outs, B.stats, P, huge_list, B.counters + kHugeCount);
     XD_HIP(hipGetLastError());
