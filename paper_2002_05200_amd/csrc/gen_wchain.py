@@ -212,6 +212,285 @@ def first_function(C):
     return lines
 
 
+# ---------------------------------------------------------------------------
+# WLoop<C>::run: whole anti-diagonals of one score-word block in assembly
+# ---------------------------------------------------------------------------
+def _jump(label_fmt, idx, n):
+    """A table of n branches indexed by SGPR operand `idx` (entry k jumps to
+    label_fmt.format(k))."""
+    out = [
+        f'"s_lshl_b32 s42, %[{idx}], 2\\n\\t"',
+        '"s_getpc_b64 s[40:41]\\n"',
+        '"{t}b_%=:\\n\\t"',
+        '"s_add_u32 s40, s40, s42\\n\\t"',
+        '"s_addc_u32 s41, s41, 0\\n\\t"',
+        '"s_add_u32 s40, s40, {t}t_%=-{t}b_%=\\n\\t"',
+        '"s_addc_u32 s41, s41, 0\\n\\t"',
+        '"s_nop 0\\n\\t"',
+        '"s_setpc_b64 s[40:41]\\n"',
+        '"{t}t_%=:\\n\\t"',
+    ]
+    out += [f'"s_branch {label_fmt.format(k)}\\n\\t"' for k in range(n)]
+    return out
+
+
+def _loop_chain(C, par, P):
+    """The chain of one parity inside WLoop (labels prefixed with P): cur
+    registers are c{r} (even: E, odd: O), the previous anti-diagonal's are
+    p{r}, score words w{r}."""
+    cur = "e" if par == 0 else "o"
+    prv = "o" if par == 0 else "e"
+    sw = "se" if par == 0 else "so"
+    rot = "wave_ror:1" if par == 0 else "wave_rol:1"
+
+    def reg(k):
+        return k if par == 0 else C - 1 - k
+
+    def cell(k):
+        r = reg(k)
+        own, carry = ("tA", "tB") if k % 2 == 0 else ("tB", "tA")
+        return [
+            f'"v_mov_b32_dpp %[{own}], %[{prv}{r}] {rot} row_mask:0xf bank_mask:0xf\\n\\t"',
+            f'"v_bfe_u32 %[u], %[{sw}{r}], %[pos], 2\\n\\t"',
+            f'"v_cndmask_b32_e64 %[t2], %[{own}], %[{carry}], %[lm{par}]\\n\\t"',
+            f'"v_add3_u32 %[{cur}{r}], %[{cur}{r}], %[base], %[u]\\n\\t"',
+            f'"v_max3_i32 %[{cur}{r}], %[{cur}{r}], %[{prv}{r}], %[t2]\\n\\t"',
+            f'"v_cmp_le_i32 vcc, %[thr], %[{cur}{r}]\\n\\t"',
+        ]
+
+    def keep(k):
+        r = reg(k)
+        return [
+            f'"v_cndmask_b32_e32 %[{cur}{r}], -2.0, %[{cur}{r}], vcc\\n\\t"',
+            f'"v_max_i32 %[mx], %[mx], %[{cur}{r}]\\n\\t"',
+        ]
+
+    out = [
+        '"v_mov_b32 %[tA], -2.0\\n\\t"',     # the chain's outer neighbour: -inf
+        '"v_mov_b32 %[tB], -2.0\\n\\t"',
+        '"v_mov_b32 %[mx], -2.0\\n\\t"',
+    ]
+    # entry: chain position of the first register
+    if par == 0:
+        out += ['"s_mov_b32 %[ix], %[rlo]\\n\\t"']
+    else:
+        out += [f'"s_sub_u32 %[ix], {C - 1}, %[rhi]\\n\\t"']
+    out += [x.replace("{t}", f".L{P}j") for x in _jump(f".L{P}h{{}}_%=", "ix", C)]
+    stop = "rhi" if par == 0 else "rlo"
+    for k in range(C):
+        r = reg(k)
+        nxt = f".L{P}r{k + 1}_%=" if k + 1 < C else f".L{P}end_%="
+        out += [f'".L{P}h{k}_%=:\\n\\t"'] + cell(k) + [
+            '"s_and_b64 vcc, vcc, %[mf]\\n\\t"',
+            '"s_mov_b64 %[lf], vcc\\n\\t"',
+        ] + keep(k) + [
+            f'"s_cmp_eq_u32 %[{stop}], {r}\\n\\t"',
+            f'"s_cbranch_scc1 .L{P}end_%=\\n\\t"',
+            f'"s_branch {nxt}\\n\\t"',
+        ]
+    for k in range(1, C):
+        r = reg(k)
+        out += [f'".L{P}r{k}_%=:\\n\\t"'] + cell(k) + [
+            f'"s_cmp_eq_u32 %[{stop}], {r}\\n\\t"',
+            f'"s_cbranch_scc1 .L{P}l{k}_%=\\n\\t"',
+        ] + keep(k)
+    out.append(f'"s_branch .L{P}end_%=\\n\\t"')
+    for k in range(1, C):
+        out += [f'".L{P}l{k}_%=:\\n\\t"', '"s_and_b64 vcc, vcc, %[ml]\\n\\t"'] + keep(k) + [
+            f'"s_branch .L{P}end_%=\\n\\t"']
+    out += [f'".L{P}end_%=:\\n\\t"', '"s_mov_b64 %[ll], vcc\\n\\t"']
+    return out
+
+
+def _loop_half(C, par):
+    """One anti-diagonal of parity `par` in WLoop, from the block-end test to
+    the recentre test of the next range."""
+    P = "E" if par == 0 else "O"
+    cur = "e" if par == 0 else "o"
+    spl, sph = f"spl{par}", f"sph{par}"
+    out = [f'".L{P}top_%=:\\n\\t"']
+    if par == 0:   # a block ends before an even anti-diagonal
+        out += ['"s_cmp_ge_i32 %[d], %[dstop]\\n\\t"', '"s_cbranch_scc1 .Lx0_%=\\n\\t"']
+    out += [
+        '"s_ashr_i32 %[rlo], %[lo], 6\\n\\t"',
+        '"s_ashr_i32 %[rhi], %[hi], 6\\n\\t"',
+        # score words must cover the span
+        '"s_cmp_lt_i32 %[rlo], %[wlo]\\n\\t"',
+        '"s_cbranch_scc1 .Lx1_%=\\n\\t"',
+        '"s_cmp_gt_i32 %[rhi], %[whi]\\n\\t"',
+        '"s_cbranch_scc1 .Lx1_%=\\n\\t"',
+        # registers leaving this parity's span become -inf (out of line)
+        f'"s_cmp_lt_i32 %[{spl}], %[rlo]\\n\\t"',
+        f'"s_cbranch_scc1 .L{P}cl_%=\\n\\t"',
+        f'"s_cmp_gt_i32 %[{sph}], %[rhi]\\n\\t"',
+        f'"s_cbranch_scc1 .L{P}cl_%=\\n"',
+        f'".L{P}clret_%=:\\n\\t"',
+        # lane masks of the range in its edge registers
+        '"s_and_b32 %[t], %[lo], 63\\n\\t"',
+        '"s_lshl_b64 %[mlo], -1, %[t]\\n\\t"',
+        '"s_and_b32 %[t], %[hi], 63\\n\\t"',
+        '"s_sub_u32 %[t], 63, %[t]\\n\\t"',
+        '"s_lshr_b64 %[mhi], -1, %[t]\\n\\t"',
+        '"s_and_b64 %[mf], %[mlo], %[mhi]\\n\\t"',
+        '"s_cmp_eq_u32 %[rlo], %[rhi]\\n\\t"',
+    ]
+    if par == 0:   # the chain enters at rlo (mask lo) and leaves at rhi (mask hi)
+        out += ['"s_cselect_b64 %[mf], %[mf], %[mlo]\\n\\t"', '"s_mov_b64 %[ml], %[mhi]\\n\\t"',
+                '"s_sub_i32 %[pos], %[d], %[e0x2]\\n\\t"']
+    else:          # enters at rhi (mask hi), leaves at rlo (mask lo)
+        out += ['"s_cselect_b64 %[mf], %[mf], %[mhi]\\n\\t"', '"s_mov_b64 %[ml], %[mlo]\\n\\t"',
+                '"s_sub_i32 %[pos], %[d], %[e0x2]\\n\\t"', '"s_add_i32 %[pos], %[pos], -1\\n\\t"']
+    out += _loop_chain(C, par, P)
+    # survivors of the range's first and last register
+    lo_mask, hi_mask = ("lf", "ll") if par == 0 else ("ll", "lf")
+    out += [
+        f'"s_cmp_eq_u64 %[{lo_mask}], 0\\n\\t"',
+        '"s_cbranch_scc1 .Lx2_%=\\n\\t"',
+        f'"s_cmp_eq_u64 %[{hi_mask}], 0\\n\\t"',
+        '"s_cbranch_scc1 .Lx2_%=\\n\\t"',
+        f'"s_ff1_i32_b64 %[first], %[{lo_mask}]\\n\\t"',
+        '"s_lshl_b32 %[t], %[rlo], 6\\n\\t"',
+        '"s_add_i32 %[first], %[first], %[t]\\n\\t"',
+        f'"s_flbit_i32_b64 %[last], %[{hi_mask}]\\n\\t"',
+        '"s_lshl_b32 %[t], %[rhi], 6\\n\\t"',
+        '"s_add_i32 %[t], %[t], 63\\n\\t"',
+        '"s_sub_i32 %[last], %[t], %[last]\\n\\t"',
+        # did best improve?  (match = 1: by exactly one; out of line)
+        '"v_cmp_lt_i32_e32 vcc, %[bw], %[mx]\\n\\t"',
+        f'"s_cbranch_vccnz .L{P}imp_%=\\n"',
+        f'".L{P}impret_%=:\\n\\t"',
+        # cells of this range, the span of this parity
+        '"s_sub_i32 %[t], %[hi], %[lo]\\n\\t"',
+        '"s_add_i32 %[cells], %[cells], %[t]\\n\\t"',
+        '"s_add_i32 %[cells], %[cells], 1\\n\\t"',
+        f'"s_mov_b32 %[{spl}], %[rlo]\\n\\t"',
+        f'"s_mov_b32 %[{sph}], %[rhi]\\n\\t"',
+    ]
+    if par == 0:   # next (odd) range: [first - 1, last]
+        out += ['"s_add_i32 %[lo], %[first], -1\\n\\t"', '"s_mov_b32 %[hi], %[last]\\n\\t"']
+    else:          # next (even) range: [first, last + 1]
+        out += ['"s_mov_b32 %[lo], %[first]\\n\\t"', '"s_add_i32 %[hi], %[last], 1\\n\\t"']
+    out += [
+        '"s_add_i32 %[bw], %[bw], %[ng]\\n\\t"',
+        '"s_add_i32 %[thr], %[thr], %[ng]\\n\\t"',
+        '"s_add_i32 %[d], %[d], 1\\n\\t"',
+        '"s_cmp_lt_i32 %[lo], 1\\n\\t"',
+        '"s_cbranch_scc1 .Lx3_%=\\n\\t"',
+        '"s_cmp_gt_i32 %[hi], %[smax]\\n\\t"',
+        '"s_cbranch_scc1 .Lx3_%=\\n\\t"',
+    ]
+    return out
+
+
+def _loop_outofline(C, par):
+    """Span clearing and the improvement search of one parity."""
+    P = "E" if par == 0 else "O"
+    cur = "e" if par == 0 else "o"
+    spl, sph = f"spl{par}", f"sph{par}"
+    out = [
+        # clear registers of the old span [spl, sph] that are outside [rlo, rhi]
+        f'".L{P}cl_%=:\\n\\t"',
+        f'"s_mov_b32 %[ix], %[{spl}]\\n"',
+        f'".L{P}clloop_%=:\\n\\t"',
+        f'"s_cmp_gt_i32 %[ix], %[{sph}]\\n\\t"',
+        f'"s_cbranch_scc1 .L{P}clret_%=\\n\\t"',
+        '"s_cmp_lt_i32 %[ix], %[rlo]\\n\\t"',
+        f'"s_cbranch_scc1 .L{P}cldo_%=\\n\\t"',
+        '"s_cmp_gt_i32 %[ix], %[rhi]\\n\\t"',
+        f'"s_cbranch_scc1 .L{P}cldo_%=\\n"',
+        f'".L{P}clnext_%=:\\n\\t"',
+        '"s_add_i32 %[ix], %[ix], 1\\n\\t"',
+        f'"s_branch .L{P}clloop_%=\\n"',
+        f'".L{P}cldo_%=:\\n\\t"',
+    ]
+    out += [x.replace("{t}", f".L{P}z") for x in _jump(f".L{P}z{{}}_%=", "ix", C)]
+    for r in range(C):
+        out += [f'".L{P}z{r}_%=:\\n\\t"', f'"v_mov_b32 %[{cur}{r}], -2.0\\n\\t"',
+                f'"s_branch .L{P}clnext_%=\\n\\t"']
+    # improvement: the first slot above bw, scanning the span upwards
+    out += [f'".L{P}imp_%=:\\n\\t"']
+    out += [x.replace("{t}", f".L{P}q") for x in _jump(f".L{P}q{{}}_%=", "rlo", C)]
+    for r in range(C):
+        out += [
+            f'".L{P}q{r}_%=:\\n\\t"',
+            f'"v_cmp_lt_i32_e32 vcc, %[bw], %[{cur}{r}]\\n\\t"',
+            f'"s_cbranch_vccnz .L{P}f{r}_%=\\n\\t"',
+            f'"s_cmp_eq_u32 %[rhi], {r}\\n\\t"',
+            f'"s_cbranch_scc1 .L{P}impret_%=\\n\\t"',
+        ]
+    out.append(f'"s_branch .L{P}impret_%=\\n\\t"')
+    for r in range(C):
+        out += [
+            f'".L{P}f{r}_%=:\\n\\t"',
+            '"s_ff1_i32_b64 %[bs], vcc\\n\\t"',
+            f'"s_add_i32 %[bs], %[bs], {64 * r}\\n\\t"',
+            '"s_mov_b32 %[bpos], %[d]\\n\\t"',
+            '"s_add_i32 %[bw], %[bw], 1\\n\\t"',
+            '"s_add_i32 %[thr], %[thr], 1\\n\\t"',
+            f'"s_branch .L{P}impret_%=\\n\\t"',
+        ]
+    return out
+
+
+def loop_function(C):
+    """WLoop<C>::run: anti-diagonals of the current score-word block while the
+    window stays inside the matrix (checked by the caller), with match = 1
+    and narrow score fields.  Returns why it stopped: 0 the block ended, 1 the
+    span outgrew the registers with score words, 2 anti-diagonal s.d has been
+    computed but its survivors are not in the span's edge registers (the
+    caller finishes it), 3 the next range needs a recentre."""
+    lines = [
+        "template <>",
+        f"XD_MEMBER int32_t WLoop<{C}>::run(vint *E, vint *O, const vint *SE, const vint *SO,",
+        "                                   WLoopState &s) {",
+        "  int32_t d = s.d, lo = s.lo, hi = s.hi, bw = s.bw, thr = s.thr, cells = s.cells;",
+        "  int32_t bs = s.bs, bpos = s.bpos, spl0 = s.spl0, sph0 = s.sph0, spl1 = s.spl1, sph1 = s.sph1;",
+        "  int32_t rlo = 0, rhi = 0, code = 0, ix, t, pos, first, last;",
+        "  uint64_t mlo, mhi, mf, ml, lf = 0, ll = 0;",
+        "  const uint64_t lm0 = 1ull, lm1 = 1ull << 63;",
+        "  int32_t tA, tB, t2, u, mx = -(1 << 30);",
+        "  asm volatile(",
+        '      "s_bitcmp1_b32 %[d], 0\\n\\t"',
+        '      "s_cbranch_scc1 .LOtop_%=\\n\\t"',
+    ]
+    body = _loop_half(C, 0) + _loop_half(C, 1) + ['"s_branch .LEtop_%=\\n"']
+    body += [
+        '".Lx0_%=:\\n\\t"', '"s_mov_b32 %[code], 0\\n\\t"', '"s_branch .Lend_%=\\n"',
+        '".Lx1_%=:\\n\\t"', '"s_mov_b32 %[code], 1\\n\\t"', '"s_branch .Lend_%=\\n"',
+        '".Lx2_%=:\\n\\t"', '"s_mov_b32 %[code], 2\\n\\t"', '"s_branch .Lend_%=\\n"',
+        '".Lx3_%=:\\n\\t"', '"s_mov_b32 %[code], 3\\n\\t"', '"s_branch .Lend_%=\\n"',
+    ]
+    body += _loop_outofline(C, 0) + _loop_outofline(C, 1)
+    body += ['".Lend_%=:\\n"']
+    lines += ["      " + x for x in body]
+    outs = ", ".join([f'[e{r}] "+v"(E[{r}].x)' for r in range(C)] +
+                     [f'[o{r}] "+v"(O[{r}].x)' for r in range(C)])
+    ins = ", ".join([f'[se{r}] "v"(SE[{r}].x)' for r in range(C)] +
+                    [f'[so{r}] "v"(SO[{r}].x)' for r in range(C)])
+    lines += [
+        f"      : {outs},",
+        '        [tA] "=&v"(tA), [tB] "=&v"(tB), [t2] "=&v"(t2), [u] "=&v"(u), [mx] "+v"(mx),',
+        '        [d] "+s"(d), [lo] "+s"(lo), [hi] "+s"(hi), [bw] "+s"(bw), [thr] "+s"(thr),',
+        '        [cells] "+s"(cells), [bs] "+s"(bs), [bpos] "+s"(bpos), [spl0] "+s"(spl0),',
+        '        [sph0] "+s"(sph0), [spl1] "+s"(spl1), [sph1] "+s"(sph1), [rlo] "+s"(rlo),',
+        '        [rhi] "+s"(rhi), [code] "+s"(code), [ix] "=&s"(ix), [t] "=&s"(t),',
+        '        [pos] "=&s"(pos), [first] "=&s"(first), [last] "=&s"(last), [mlo] "=&s"(mlo),',
+        '        [mhi] "=&s"(mhi), [mf] "=&s"(mf), [ml] "=&s"(ml), [lf] "+s"(lf), [ll] "+s"(ll)',
+        f"      : {ins},",
+        '        [dstop] "s"(s.dstop), [e0x2] "s"(s.e0x2), [wlo] "s"(s.w_lo), [whi] "s"(s.w_hi),',
+        '        [base] "s"(s.base), [ng] "s"(s.ng), [smax] "s"(s.smax), [lm0] "s"(lm0),',
+        '        [lm1] "s"(lm1)',
+        '      : "vcc", "scc", "s40", "s41", "s42");',
+        "  s.d = d; s.lo = lo; s.hi = hi; s.bw = bw; s.thr = thr; s.cells = cells;",
+        "  s.bs = bs; s.bpos = bpos; s.spl0 = spl0; s.sph0 = sph0; s.spl1 = spl1; s.sph1 = sph1;",
+        "  s.rlo = rlo; s.rhi = rhi; s.lf = lf; s.ll = ll; s.mx = mx;",
+        "  return code;",
+        "}",
+        "",
+    ]
+    return lines
+
+
 def render() -> str:
     """The header's text."""
     out = [
@@ -230,6 +509,12 @@ def render() -> str:
         "//",
         "// WFirst<C>::run returns the first slot (64 r + lane) of registers",
         "// rlo..rhi whose cell exceeds bw, or -1 when none does.",
+        "//",
+        "// WLoop<C>::run runs whole anti-diagonals of one score-word block:",
+        "// span clearing, the chain, survivors, the improvement of best (match =",
+        "// 1), cells and the next range, leaving when the block ends, the span",
+        "// outgrows the score words, the survivors are not in the span's edge",
+        "// registers, or the next range needs a recentre.",
         "#pragma once",
         "",
         '#include "xd_wave.h"',
@@ -249,11 +534,32 @@ def render() -> str:
         "  XD_MEMBER static int32_t run(const vint *cur, int32_t bw, int32_t rlo, int32_t rhi);",
         "};",
         "",
+        "// Scalar state of WLoop: the anti-diagonal about to be computed, its range",
+        "// (slots), the W-form thresholds, cells of the block, the last improvement",
+        "// (slot and anti-diagonal, bpos = -1 for none) and both parities' spans;",
+        "// the block's limits; and, after a return of 2, the finished chain's span,",
+        "// edge survivors and running maximum.",
+        "struct WLoopState {",
+        "  int32_t d, lo, hi, bw, thr, cells, bs, bpos, spl0, sph0, spl1, sph1;",
+        "  int32_t dstop, e0x2, w_lo, w_hi, base, ng, smax;",
+        "  int32_t rlo, rhi;",
+        "  uint64_t lf, ll;",
+        "  int32_t mx;",
+        "};",
+        "",
+        "template <int C>",
+        "struct WLoop {",
+        "  XD_MEMBER static int32_t run(vint *E, vint *O, const vint *SE, const vint *SO,",
+        "                              WLoopState &s);",
+        "};",
+        "",
     ]
     for C in CS:
         for par in (0, 1):
             out += function(C, par)
         out += first_function(C)
+        if C >= 4:
+            out += loop_function(C)
     out += ["}  // namespace xd", ""]
     return "\n".join(out)
 
