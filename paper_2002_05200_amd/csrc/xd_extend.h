@@ -103,6 +103,7 @@ struct JobView {
   SeqView A, B;
   int64_t a_start, b_start;
   int32_t m, n, x, dir;
+  uint32_t *stage;   // the wavefront's LDS words for the wide tiers' score-word build
 };
 
 // Score words of the 16 steps e0 .. e0+15 for every slot (both parities),
@@ -323,6 +324,7 @@ XD_FN JobOut extend_job_w1(const Job &job, const Params &P, int32_t j) {
   jv.B = make_view(P.B, P.b_words, job.b_start);
   jv.a_start = job.a_start; jv.b_start = job.b_start;
   jv.m = job.m; jv.n = job.n; jv.x = job.x; jv.dir = job.dir;
+  jv.stage = nullptr;
 
   Band<1> bd;
   bd.O[0] = splat(kNeg);

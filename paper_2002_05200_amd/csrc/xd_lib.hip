@@ -171,6 +171,8 @@ __global__ __launch_bounds__(kBlock, C >= 32 && NARROW ? 2 : 1) void k_extend(
     const Job *__restrict__ jobs, TierQueue q, int32_t *head, JobOut *__restrict__ outs,
     unsigned long long *stats, Params P) {
   const int wave = uniform((int32_t)(threadIdx.x >> 6));
+  constexpr int kStage = C >= 2 ? 2 * kStageWords<C> : 1;
+  __shared__ uint32_t stage[kWavesPerBlock * kStage];
   const int32_t n_init = q.counters[kInit + q.tier];
   const int32_t n_esc = q.counters[kEsc + q.tier];
   const int32_t total = n_init + n_esc;
@@ -195,14 +197,14 @@ __global__ __launch_bounds__(kBlock, C >= 32 && NARROW ? 2 : 1) void k_extend(
       }
     } else if constexpr (C == 2) {
       if (P.impl == 0) {
-        o = extend_job_wide<2, NARROW, true>(job, P, j);
+        o = extend_job_wide<2, NARROW, true>(job, P, j, stage + wave * kStage);
       } else {
-        o = extend_job_wide<2, NARROW, false>(job, P, j);
+        o = extend_job_wide<2, NARROW, false>(job, P, j, stage + wave * kStage);
       }
     } else if (NARROW && P.impl == 0) {
-      o = extend_job_wide<C, NARROW, true>(job, P, j);
+      o = extend_job_wide<C, NARROW, true>(job, P, j, stage + wave * kStage);
     } else {
-      o = extend_job_wide<C, NARROW, false>(job, P, j);
+      o = extend_job_wide<C, NARROW, false>(job, P, j, stage + wave * kStage);
     }
     if (lane_id() == 0) {
       if (o.status == kJobWider) {

@@ -107,6 +107,7 @@ XD_FN JobOut extend_job_matrix(const Job &job, const Params &P, const int32_t *l
   jv.B = make_view(P.B, P.b_words, job.b_start);
   jv.a_start = job.a_start; jv.b_start = job.b_start;
   jv.m = job.m; jv.n = job.n; jv.x = job.x; jv.dir = job.dir;
+  jv.stage = nullptr;
 
   vint E = select(lane_index() == 32, splat(0), kNeg);   // anti-diagonal 0: the origin
   vint O = splat(kNeg);

@@ -450,6 +450,7 @@ XD_FN JobOut mw_extend(const Job &job, const Params &P, int32_t j, MwShared<NW, 
   jv.B = make_view(P.B, P.b_words, job.b_start);
   jv.a_start = job.a_start; jv.b_start = job.b_start;
   jv.m = job.m; jv.n = job.n; jv.x = job.x; jv.dir = job.dir;
+  jv.stage = nullptr;
 
   WBand<C> bd;
   MwScalars st;

@@ -43,43 +43,101 @@ struct WScalars {
   uint64_t cells;
 };
 
-// Score words of registers [r0, r1] for the 16 steps e0 .. e0 + 15 (slot s at
+// Per-wavefront staging of packed words in LDS for the score-word build: A's
+// words, then B's, kStageWords each (4 C + 6 consecutive words per sequence
+// cover the window; the word after them is a dump slot).
+template <int C>
+constexpr int kStageWords = 4 * C + 8;
+
+// One sequence's window positions over registers r and lanes l run as
+// g = c + 64 r + l (rising) or g = c - 64 r - l (falling).  With r' and l'
+// the register and lane counted in the rising sense (r' = C-1-r, l' = 63-l
+// for a falling run) and cc = c, resp. c - 64 C + 1, position g lies in word
+// (cc >> 4) + 4 r' + q(l') at bit 2 (((cc & 15) + l') & 15), where
+// q(l') = ((cc & 15) + l') >> 4 is at most 4.  stage_words copies words
+// (cc >> 4) + b, b = 0 .. 4 C + 5, of both sequences, clamped to the arena
+// like window16, into the stage: every load is issued before the first store.
+template <int C>
+XD_FN void stage_words(uint32_t *sa, const SeqView &A, int32_t wa, uint32_t *sb, const SeqView &B,
+                       int32_t wb) {
+  constexpr int N = 4 * C + 6;
+  constexpr int K = (N + kWave - 1) / kWave;
+  const int32_t l = lane_id();
+  uint32_t ga[K], gb[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    int32_t b = l + kWave * k;
+    b = b > N - 1 ? N - 1 : b;
+    int32_t w = wa + b;
+    w = w < A.lo_rel ? A.lo_rel : (w > A.hi_rel ? A.hi_rel : w);
+    ga[k] = A.base[w];
+    w = wb + b;
+    w = w < B.lo_rel ? B.lo_rel : (w > B.hi_rel ? B.hi_rel : w);
+    gb[k] = B.base[w];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    int32_t b = l + kWave * k;
+    b = b > N ? N : b;   // lanes past the words store into the dump slot
+    sa[b] = ga[k];
+    sb[b] = gb[k];
+  }
+}
+
+// Score words of every register for the 16 steps e0 .. e0 + 15 (slot s at
 // step e: even anti-diagonal 2e holds (s+h+e, e-s-h), odd 2e+1 holds
-// (s+h+e+1, e-s-h)).
-template <int C, bool NARROW>
-XD_FN void wbuild(WBand<C> &bd, WScalars &st, int32_t e0, int32_t r0, int32_t r1,
-                  const JobView &jv, const Params &P) {
-  if (r0 < 0) r0 = 0;
-  if (r1 > C - 1) r1 = C - 1;
-  const vint l = lane_index();
+// (s+h+e+1, e-s-h)).  The words of both sequences are staged in the
+// wavefront's LDS buffer first; each register then reads its two-word
+// windows at fixed offsets.  A's even- and odd-step windows are one base
+// apart and come from the same two words.
+template <int C, bool NARROW, int DIR>
+XD_FN void wbuild_dir(WBand<C> &bd, const WScalars &st, int32_t e0, const JobView &jv,
+                      const Params &P) {
+  uint32_t *sa = jv.stage;
+  uint32_t *sb = jv.stage + kStageWords<C>;
+  // A's lower window (even step for DIR > 0, odd for DIR < 0) and B's window:
+  //   DIR > 0: A at (h + e0 - 1) + s rising, B at (e0 - h - 1) - s falling
+  //   DIR < 0: A at (-15 - h - e0) - s falling, B at (-14 - e0 + h) + s rising
+  const int32_t ca = DIR > 0 ? st.h + e0 - 1 + jv.A.sub : -15 - st.h - e0 + jv.A.sub - 64 * C + 1;
+  const int32_t cb = DIR > 0 ? e0 - st.h - 1 + jv.B.sub - 64 * C + 1 : -14 - e0 + st.h + jv.B.sub;
+  stage_words<C>(sa, jv.A, ca >> 4, sb, jv.B, cb >> 4);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int32_t l = lane_id();
+  const int32_t la = DIR > 0 ? l : 63 - l, lb = DIR > 0 ? 63 - l : l;
+  const int32_t ta = (ca & 15) + la, tb = (cb & 15) + lb;
+  const uint32_t *pa = sa + (ta >> 4);
+  const uint32_t *pb = sb + (tb >> 4);
+  const uint32_t sha = (uint32_t)(ta & 15) << 1, shb = (uint32_t)(tb & 15) << 1;
 #pragma unroll
   for (int r = 0; r < C; ++r) {
-    if (r < r0 || r > r1) continue;
-    const vint s = l + 64 * r;
-    const vint i0 = s + (st.h + e0);
-    const vint j0 = splat(e0 - st.h) - s;
-    vint offAe, offAo, offB;
-    if (jv.dir > 0) {          // a_i = A[start + i - 1]
-      offAe = i0 - 1;
-      offAo = i0;
-      offB = j0 - 1;
-    } else {                   // a_i = A[start - i + 1]: window of the 16 bases below
-      offAe = splat(-14) - i0;
-      offAo = splat(-15) - i0;
-      offB = splat(-14) - j0;
-    }
-    const vint wb = window16(jv.B, offB);
-    vint xe = window16(jv.A, offAe) ^ wb;
-    vint xo = window16(jv.A, offAo) ^ wb;
-    if (jv.dir < 0) {
+    const int ra = DIR > 0 ? r : C - 1 - r, rb = DIR > 0 ? C - 1 - r : r;
+    const uint64_t xa = (uint64_t)pa[4 * ra] | ((uint64_t)pa[4 * ra + 1] << 32);
+    const uint32_t wb = __builtin_amdgcn_alignbit(pb[4 * rb + 1], pb[4 * rb], shb);
+    const uint32_t wlo = (uint32_t)(xa >> sha), whi = (uint32_t)(xa >> (sha + 2));
+    vint xe = {(int32_t)((DIR > 0 ? wlo : whi) ^ wb)};
+    vint xo = {(int32_t)((DIR > 0 ? whi : wlo) ^ wb)};
+    if (DIR < 0) {
       xe = bit_reverse(xe);
       xo = bit_reverse(xo);
     }
     bd.SE[r] = score_word<NARROW>(xe, P.pat);
     bd.SO[r] = score_word<NARROW>(xo, P.pat);
   }
-  st.w_lo = r0;
-  st.w_hi = r1;
+}
+
+// Builds every register's words (the requested range [r0, r1] is always
+// inside), so the next build is due at the block's end or a recentre.
+template <int C, bool NARROW>
+XD_FN void wbuild(WBand<C> &bd, WScalars &st, int32_t e0, int32_t r0, int32_t r1,
+                  const JobView &jv, const Params &P) {
+  (void)r0;
+  (void)r1;
+  if (jv.dir > 0) wbuild_dir<C, NARROW, 1>(bd, st, e0, jv, P);
+  else wbuild_dir<C, NARROW, -1>(bd, st, e0, jv, P);
+  st.w_lo = 0;
+  st.w_hi = C - 1;
 }
 
 // Cell update of register R of the span (no range clipping; see wstep),
@@ -721,7 +779,7 @@ XD_FN bool wide_fast(WBand<C> &bd, WScalars &st, const JobView &jv, const Params
 // loop for two registers, the generated chain with built-in edge clipping
 // for more (narrow score fields only; else FAST changes nothing).
 template <int C, bool NARROW, bool FAST = false>
-XD_FN JobOut extend_job_wide(const Job &job, const Params &P, int32_t j) {
+XD_FN JobOut extend_job_wide(const Job &job, const Params &P, int32_t j, uint32_t *stage) {
   constexpr int S = kWave * C;
   JobOut out;
   out.best = 0; out.bi = 0; out.bj = 0; out.status = kJobOk; out.cells = 0;
@@ -732,6 +790,7 @@ XD_FN JobOut extend_job_wide(const Job &job, const Params &P, int32_t j) {
   jv.B = make_view(P.B, P.b_words, job.b_start);
   jv.a_start = job.a_start; jv.b_start = job.b_start;
   jv.m = job.m; jv.n = job.n; jv.x = job.x; jv.dir = job.dir;
+  jv.stage = stage;
 
   WBand<C> bd;
   WScalars st;
@@ -768,7 +827,9 @@ XD_FN JobOut extend_job_wide(const Job &job, const Params &P, int32_t j) {
   bool ok = true;
   bool fast_loop = false;
   if constexpr (FAST && NARROW && C >= 4) fast_loop = P.unit_match != 0;
-  if (fast_loop) ok = wide_fast<C, NARROW>(bd, st, jv, P);
+  if constexpr (FAST && NARROW && C >= 4) {
+    if (fast_loop) ok = wide_fast<C, NARROW>(bd, st, jv, P);
+  }
   for (; !fast_loop;) {
     if constexpr (FAST && C == 2) {
       const int32_t d_before = st.d;
