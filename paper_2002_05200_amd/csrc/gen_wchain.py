@@ -237,7 +237,19 @@ def _jump(label_fmt, idx, n):
 def _loop_chain(C, par, P):
     """The chain of one parity inside WLoop (labels prefixed with P): cur
     registers are c{r} (even: E, odd: O), the previous anti-diagonal's are
-    p{r}, score words w{r}."""
+    p{r}, score words w{r}.
+
+    It enters at the span's first register (rlo going up, rhi going down)
+    and runs to the window's last register without a test per register.
+    The entry register's diagonal input is first cut to the range (mask mf),
+    so its lanes outside the range come out -inf, and its survivors go
+    straight to lf.  The registers past the span's far end hold -inf with
+    -inf neighbours (their slots lie beyond the previous anti-diagonal's
+    survivors) and stay -inf.  The far edge register may keep lanes past the
+    range that the diagonal term revived: a table of branches on its index
+    cuts them (mask ml) and takes its survivors into ll.  Those lanes may
+    have raised the running maximum: the improvement search after the chain
+    only looks at the range, so such a false alarm changes nothing."""
     cur = "e" if par == 0 else "o"
     prv = "o" if par == 0 else "e"
     sw = "se" if par == 0 else "so"
@@ -246,24 +258,25 @@ def _loop_chain(C, par, P):
     def reg(k):
         return k if par == 0 else C - 1 - k
 
-    def cell(k):
+    def cell(k, cond="vcc"):
         r = reg(k)
         own, carry = ("tA", "tB") if k % 2 == 0 else ("tB", "tA")
+        cmp = (f'"v_cmp_le_i32 vcc, %[thr], %[{cur}{r}]\\n\\t"' if cond == "vcc" else
+               f'"v_cmp_le_i32_e64 %[{cond}], %[thr], %[{cur}{r}]\\n\\t"')
         return [
             f'"v_mov_b32_dpp %[{own}], %[{prv}{r}] {rot} row_mask:0xf bank_mask:0xf\\n\\t"',
             f'"v_bfe_u32 %[u], %[{sw}{r}], %[pos], 2\\n\\t"',
             f'"v_cndmask_b32_e64 %[t2], %[{own}], %[{carry}], %[lm{par}]\\n\\t"',
             f'"v_add3_u32 %[{cur}{r}], %[{cur}{r}], %[base], %[u]\\n\\t"',
             f'"v_max3_i32 %[{cur}{r}], %[{cur}{r}], %[{prv}{r}], %[t2]\\n\\t"',
-            f'"v_cmp_le_i32 vcc, %[thr], %[{cur}{r}]\\n\\t"',
+            cmp,
         ]
 
-    def keep(k):
+    def keep(k, cond="vcc"):
         r = reg(k)
-        return [
-            f'"v_cndmask_b32_e32 %[{cur}{r}], -2.0, %[{cur}{r}], vcc\\n\\t"',
-            f'"v_max_i32 %[mx], %[mx], %[{cur}{r}]\\n\\t"',
-        ]
+        sel = (f'"v_cndmask_b32_e32 %[{cur}{r}], -2.0, %[{cur}{r}], vcc\\n\\t"' if cond == "vcc" else
+               f'"v_cndmask_b32_e64 %[{cur}{r}], -2.0, %[{cur}{r}], %[{cond}]\\n\\t"')
+        return [sel, f'"v_max_i32 %[mx], %[mx], %[{cur}{r}]\\n\\t"']
 
     out = [
         '"v_mov_b32 %[tA], -2.0\\n\\t"',     # the chain's outer neighbour: -inf
@@ -276,29 +289,26 @@ def _loop_chain(C, par, P):
     else:
         out += [f'"s_sub_u32 %[ix], {C - 1}, %[rhi]\\n\\t"']
     out += [x.replace("{t}", f".L{P}j") for x in _jump(f".L{P}h{{}}_%=", "ix", C)]
-    stop = "rhi" if par == 0 else "rlo"
     for k in range(C):
         r = reg(k)
-        nxt = f".L{P}r{k + 1}_%=" if k + 1 < C else f".L{P}end_%="
-        out += [f'".L{P}h{k}_%=:\\n\\t"'] + cell(k) + [
-            '"s_and_b64 vcc, vcc, %[mf]\\n\\t"',
-            '"s_mov_b64 %[lf], vcc\\n\\t"',
-        ] + keep(k) + [
-            f'"s_cmp_eq_u32 %[{stop}], {r}\\n\\t"',
-            f'"s_cbranch_scc1 .L{P}end_%=\\n\\t"',
-            f'"s_branch {nxt}\\n\\t"',
+        nxt = f".L{P}r{k + 1}_%=" if k + 1 < C else f".L{P}fx_%="
+        out += [f'".L{P}h{k}_%=:\\n\\t"',
+                f'"v_cndmask_b32_e64 %[{cur}{r}], -2.0, %[{cur}{r}], %[mf]\\n\\t"']
+        out += cell(k, "lf") + keep(k, "lf") + [f'"s_branch {nxt}\\n\\t"']
+    for k in range(1, C):
+        out += [f'".L{P}r{k}_%=:\\n\\t"'] + cell(k) + keep(k)
+    # the far edge register: rhi going up, rlo going down
+    far = "rhi" if par == 0 else "rlo"
+    out += [f'".L{P}fx_%=:\\n\\t"']
+    out += [x.replace("{t}", f".L{P}x") for x in _jump(f".L{P}F{{}}_%=", far, C)]
+    for r in range(C):
+        out += [
+            f'".L{P}F{r}_%=:\\n\\t"',
+            f'"v_cndmask_b32_e64 %[{cur}{r}], -2.0, %[{cur}{r}], %[ml]\\n\\t"',
+            f'"v_cmp_le_i32_e64 %[ll], %[thr], %[{cur}{r}]\\n\\t"',
+            f'"s_branch .L{P}end_%=\\n\\t"',
         ]
-    for k in range(1, C):
-        r = reg(k)
-        out += [f'".L{P}r{k}_%=:\\n\\t"'] + cell(k) + [
-            f'"s_cmp_eq_u32 %[{stop}], {r}\\n\\t"',
-            f'"s_cbranch_scc1 .L{P}l{k}_%=\\n\\t"',
-        ] + keep(k)
-    out.append(f'"s_branch .L{P}end_%=\\n\\t"')
-    for k in range(1, C):
-        out += [f'".L{P}l{k}_%=:\\n\\t"', '"s_and_b64 vcc, vcc, %[ml]\\n\\t"'] + keep(k) + [
-            f'"s_branch .L{P}end_%=\\n\\t"']
-    out += [f'".L{P}end_%=:\\n\\t"', '"s_mov_b64 %[ll], vcc\\n\\t"']
+    out += [f'".L{P}end_%=:\\n\\t"']
     return out
 
 
@@ -342,19 +352,25 @@ def _loop_half(C, par):
                 '"s_sub_i32 %[pos], %[d], %[e0x2]\\n\\t"', '"s_add_i32 %[pos], %[pos], -1\\n\\t"']
     out += _loop_chain(C, par, P)
     # survivors of the range's first and last register
+    # (lf, the entry register's, was written long before ll: test it first)
     lo_mask, hi_mask = ("lf", "ll") if par == 0 else ("ll", "lf")
-    out += [
+    first_part = [
         f'"s_cmp_eq_u64 %[{lo_mask}], 0\\n\\t"',
-        '"s_cbranch_scc1 .Lx2_%=\\n\\t"',
-        f'"s_cmp_eq_u64 %[{hi_mask}], 0\\n\\t"',
         '"s_cbranch_scc1 .Lx2_%=\\n\\t"',
         f'"s_ff1_i32_b64 %[first], %[{lo_mask}]\\n\\t"',
         '"s_lshl_b32 %[t], %[rlo], 6\\n\\t"',
         '"s_add_i32 %[first], %[first], %[t]\\n\\t"',
+    ]
+    last_part = [
+        f'"s_cmp_eq_u64 %[{hi_mask}], 0\\n\\t"',
+        '"s_cbranch_scc1 .Lx2_%=\\n\\t"',
         f'"s_flbit_i32_b64 %[last], %[{hi_mask}]\\n\\t"',
         '"s_lshl_b32 %[t], %[rhi], 6\\n\\t"',
         '"s_add_i32 %[t], %[t], 63\\n\\t"',
         '"s_sub_i32 %[last], %[t], %[last]\\n\\t"',
+    ]
+    out += (first_part + last_part) if par == 0 else (last_part + first_part)
+    out += [
         # did best improve?  (match = 1: by exactly one; out of line)
         '"v_cmp_lt_i32_e32 vcc, %[bw], %[mx]\\n\\t"',
         f'"s_cbranch_vccnz .L{P}imp_%=\\n"',
