@@ -241,15 +241,18 @@ def _loop_chain(C, par, P):
 
     It enters at the span's first register (rlo going up, rhi going down)
     and runs to the window's last register without a test per register.
-    The entry register's diagonal input is first cut to the range (mask mf),
-    so its lanes outside the range come out -inf, and its survivors go
-    straight to lf.  The registers past the span's far end hold -inf with
-    -inf neighbours (their slots lie beyond the previous anti-diagonal's
-    survivors) and stay -inf.  The far edge register may keep lanes past the
-    range that the diagonal term revived: a table of branches on its index
-    cuts them (mask ml) and takes its survivors into ll.  Those lanes may
-    have raised the running maximum: the improvement search after the chain
-    only looks at the range, so such a false alarm changes nothing."""
+    The entry register takes its outer neighbour from the rotation of the
+    register before it (a live cell when the range was clipped to the
+    matrix there, else -inf), is cut to the range (mask mf) before the
+    X-drop test, and its survivors go straight to lf.  Past the span's far
+    end every input is -inf except for at most two slots next to it (the
+    cells a clipped range left out of the matrix), so the registers there
+    stay -inf but for those slots; the far edge register and the one after
+    it are put right afterwards through a table of branches on its index:
+    the edge register is cut to the range (mask ml) and its survivors go to
+    ll, the next register becomes -inf (it lies outside the span).  Cut lanes
+    may have raised the running maximum: the improvement search after the
+    chain only looks at the range, so such a false alarm changes nothing."""
     cur = "e" if par == 0 else "o"
     prv = "o" if par == 0 else "e"
     sw = "se" if par == 0 else "so"
@@ -258,19 +261,20 @@ def _loop_chain(C, par, P):
     def reg(k):
         return k if par == 0 else C - 1 - k
 
-    def cell(k, cond="vcc"):
+    def cell(k, cond="vcc", mask=None):
         r = reg(k)
         own, carry = ("tA", "tB") if k % 2 == 0 else ("tB", "tA")
         cmp = (f'"v_cmp_le_i32 vcc, %[thr], %[{cur}{r}]\\n\\t"' if cond == "vcc" else
                f'"v_cmp_le_i32_e64 %[{cond}], %[thr], %[{cur}{r}]\\n\\t"')
+        cut = ([f'"v_cndmask_b32_e64 %[{cur}{r}], -2.0, %[{cur}{r}], %[{mask}]\\n\\t"']
+               if mask else [])
         return [
             f'"v_mov_b32_dpp %[{own}], %[{prv}{r}] {rot} row_mask:0xf bank_mask:0xf\\n\\t"',
             f'"v_bfe_u32 %[u], %[{sw}{r}], %[pos], 2\\n\\t"',
             f'"v_cndmask_b32_e64 %[t2], %[{own}], %[{carry}], %[lm{par}]\\n\\t"',
             f'"v_add3_u32 %[{cur}{r}], %[{cur}{r}], %[base], %[u]\\n\\t"',
             f'"v_max3_i32 %[{cur}{r}], %[{cur}{r}], %[{prv}{r}], %[t2]\\n\\t"',
-            cmp,
-        ]
+        ] + cut + [cmp]
 
     def keep(k, cond="vcc"):
         r = reg(k)
@@ -290,11 +294,12 @@ def _loop_chain(C, par, P):
         out += [f'"s_sub_u32 %[ix], {C - 1}, %[rhi]\\n\\t"']
     out += [x.replace("{t}", f".L{P}j") for x in _jump(f".L{P}h{{}}_%=", "ix", C)]
     for k in range(C):
-        r = reg(k)
         nxt = f".L{P}r{k + 1}_%=" if k + 1 < C else f".L{P}fx_%="
-        out += [f'".L{P}h{k}_%=:\\n\\t"',
-                f'"v_cndmask_b32_e64 %[{cur}{r}], -2.0, %[{cur}{r}], %[mf]\\n\\t"']
-        out += cell(k, "lf") + keep(k, "lf") + [f'"s_branch {nxt}\\n\\t"']
+        out += [f'".L{P}h{k}_%=:\\n\\t"']
+        if k >= 1:   # the outer neighbour: rotation of the register before
+            carry = "tB" if k % 2 == 0 else "tA"
+            out += [f'"v_mov_b32_dpp %[{carry}], %[{prv}{reg(k - 1)}] {rot} row_mask:0xf bank_mask:0xf\\n\\t"']
+        out += cell(k, "lf", "mf") + keep(k, "lf") + [f'"s_branch {nxt}\\n\\t"']
     for k in range(1, C):
         out += [f'".L{P}r{k}_%=:\\n\\t"'] + cell(k) + keep(k)
     # the far edge register: rhi going up, rlo going down
@@ -302,10 +307,12 @@ def _loop_chain(C, par, P):
     out += [f'".L{P}fx_%=:\\n\\t"']
     out += [x.replace("{t}", f".L{P}x") for x in _jump(f".L{P}F{{}}_%=", far, C)]
     for r in range(C):
+        rn = r + 1 if par == 0 else r - 1   # the register after it, outside the span
         out += [
             f'".L{P}F{r}_%=:\\n\\t"',
             f'"v_cndmask_b32_e64 %[{cur}{r}], -2.0, %[{cur}{r}], %[ml]\\n\\t"',
             f'"v_cmp_le_i32_e64 %[ll], %[thr], %[{cur}{r}]\\n\\t"',
+        ] + ([f'"v_mov_b32 %[{cur}{rn}], -2.0\\n\\t"'] if 0 <= rn < C else []) + [
             f'"s_branch .L{P}end_%=\\n\\t"',
         ]
     out += [f'".L{P}end_%=:\\n\\t"']
@@ -324,11 +331,6 @@ def _loop_half(C, par):
     out += [
         '"s_ashr_i32 %[rlo], %[lo], 6\\n\\t"',
         '"s_ashr_i32 %[rhi], %[hi], 6\\n\\t"',
-        # score words must cover the span
-        '"s_cmp_lt_i32 %[rlo], %[wlo]\\n\\t"',
-        '"s_cbranch_scc1 .Lx1_%=\\n\\t"',
-        '"s_cmp_gt_i32 %[rhi], %[whi]\\n\\t"',
-        '"s_cbranch_scc1 .Lx1_%=\\n\\t"',
         # registers leaving this parity's span become -inf (out of line)
         f'"s_cmp_lt_i32 %[{spl}], %[rlo]\\n\\t"',
         f'"s_cbranch_scc1 .L{P}cl_%=\\n\\t"',
@@ -390,6 +392,17 @@ def _loop_half(C, par):
         '"s_add_i32 %[bw], %[bw], %[ng]\\n\\t"',
         '"s_add_i32 %[thr], %[thr], %[ng]\\n\\t"',
         '"s_add_i32 %[d], %[d], 1\\n\\t"',
+        # clipped to the matrix: j <= n (slot >= floor(d/2) - n - h) and
+        # i <= m (slot <= m - h - ceil(d/2)); empty: the extension ends
+        '"s_lshr_b32 %[t], %[d], 1\\n\\t"',
+        '"s_sub_i32 %[t], %[t], %[nh]\\n\\t"',
+        '"s_max_i32 %[lo], %[lo], %[t]\\n\\t"',
+        '"s_add_i32 %[t], %[d], 1\\n\\t"',
+        '"s_lshr_b32 %[t], %[t], 1\\n\\t"',
+        '"s_sub_i32 %[t], %[mh], %[t]\\n\\t"',
+        '"s_min_i32 %[hi], %[hi], %[t]\\n\\t"',
+        '"s_cmp_gt_i32 %[lo], %[hi]\\n\\t"',
+        '"s_cbranch_scc1 .Lx4_%=\\n\\t"',
         '"s_cmp_lt_i32 %[lo], 1\\n\\t"',
         '"s_cbranch_scc1 .Lx3_%=\\n\\t"',
         '"s_cmp_gt_i32 %[hi], %[smax]\\n\\t"',
@@ -449,12 +462,13 @@ def _loop_outofline(C, par):
 
 
 def loop_function(C):
-    """WLoop<C>::run: anti-diagonals of the current score-word block while the
-    window stays inside the matrix (checked by the caller), with match = 1
-    and narrow score fields.  Returns why it stopped: 0 the block ended, 1 the
-    span outgrew the registers with score words, 2 anti-diagonal s.d has been
-    computed but its survivors are not in the span's edge registers (the
-    caller finishes it), 3 the next range needs a recentre."""
+    """WLoop<C>::run: anti-diagonals of the current score-word block (score
+    words built for every register), with match = 1 and narrow score fields,
+    each range clipped to the matrix.  Returns why it stopped: 0 the block
+    ended, 2 anti-diagonal s.d has been computed but its survivors are not
+    in the span's edge registers (the caller finishes it), 3 the next range
+    needs a recentre, 4 the next range lies outside the matrix (the
+    extension has ended)."""
     lines = [
         "template <>",
         f"XD_MEMBER int32_t WLoop<{C}>::run(vint *E, vint *O, const vint *SE, const vint *SO,",
@@ -472,9 +486,9 @@ def loop_function(C):
     body = _loop_half(C, 0) + _loop_half(C, 1) + ['"s_branch .LEtop_%=\\n"']
     body += [
         '".Lx0_%=:\\n\\t"', '"s_mov_b32 %[code], 0\\n\\t"', '"s_branch .Lend_%=\\n"',
-        '".Lx1_%=:\\n\\t"', '"s_mov_b32 %[code], 1\\n\\t"', '"s_branch .Lend_%=\\n"',
         '".Lx2_%=:\\n\\t"', '"s_mov_b32 %[code], 2\\n\\t"', '"s_branch .Lend_%=\\n"',
         '".Lx3_%=:\\n\\t"', '"s_mov_b32 %[code], 3\\n\\t"', '"s_branch .Lend_%=\\n"',
+        '".Lx4_%=:\\n\\t"', '"s_mov_b32 %[code], 4\\n\\t"', '"s_branch .Lend_%=\\n"',
     ]
     body += _loop_outofline(C, 0) + _loop_outofline(C, 1)
     body += ['".Lend_%=:\\n"']
@@ -493,7 +507,7 @@ def loop_function(C):
         '        [pos] "=&s"(pos), [first] "=&s"(first), [last] "=&s"(last), [mlo] "=&s"(mlo),',
         '        [mhi] "=&s"(mhi), [mf] "=&s"(mf), [ml] "=&s"(ml), [lf] "+s"(lf), [ll] "+s"(ll)',
         f"      : {ins},",
-        '        [dstop] "s"(s.dstop), [e0x2] "s"(s.e0x2), [wlo] "s"(s.w_lo), [whi] "s"(s.w_hi),',
+        '        [dstop] "s"(s.dstop), [e0x2] "s"(s.e0x2), [mh] "s"(s.mh), [nh] "s"(s.nh),',
         '        [base] "s"(s.base), [ng] "s"(s.ng), [smax] "s"(s.smax), [lm0] "s"(lm0),',
         '        [lm1] "s"(lm1)',
         '      : "vcc", "scc", "s40", "s41", "s42");',
@@ -557,7 +571,7 @@ def render() -> str:
         "// edge survivors and running maximum.",
         "struct WLoopState {",
         "  int32_t d, lo, hi, bw, thr, cells, bs, bpos, spl0, sph0, spl1, sph1;",
-        "  int32_t dstop, e0x2, w_lo, w_hi, base, ng, smax;",
+        "  int32_t dstop, e0x2, mh, nh, base, ng, smax;   // mh = m - h, nh = n + h",
         "  int32_t rlo, rhi;",
         "  uint64_t lf, ll;",
         "  int32_t mx;",

@@ -706,12 +706,11 @@ XD_FN int w2_fast(WBand<2> &bd, WScalars &st, const JobView &jv, const Params &P
 }
 
 // All anti-diagonals of an extension on C >= 4 registers with the
-// generated assembly (match = 1, narrow score fields), one anti-diagonal per
-// pass: block transitions, recentres and score words in C, then WLoop for as
-// many anti-diagonals of the block as it can run while the window stays
-// inside the matrix (it finishes an anti-diagonal here when its survivors
-// left the span's edge registers), else the C step.  Returns false when the
-// band outgrew the window.
+// generated assembly (match = 1, narrow score fields): block transitions,
+// recentres and score words in C, then WLoop for the rest of the block (its
+// ranges clipped to the matrix; an anti-diagonal whose survivors left the
+// span's edge registers is finished here).  Returns false when the band
+// outgrew the window.
 template <int C, bool NARROW>
 XD_FN bool wide_fast(WBand<C> &bd, WScalars &st, const JobView &jv, const Params &P) {
   constexpr int S = kWave * C;
@@ -731,46 +730,37 @@ XD_FN bool wide_fast(WBand<C> &bd, WScalars &st, const JobView &jv, const Params
     }
     if ((st.lo >> 6) < st.w_lo || (st.hi >> 6) > st.w_hi)
       wbuild<C, NARROW>(bd, st, e0, (st.lo >> 6) - 1, (st.hi >> 6) + 1, jv, P);
-    // every slot of the window stays inside the matrix (i <= m, j <= n) up
-    // to the block's last anti-diagonal: no range is clipped to the matrix,
-    // so the assembly needs no clipping
-    const int32_t dlast = 2 * e0 + 31;
-    if (S - 1 + ((dlast + 1) >> 1) + st.h <= jv.m && (dlast >> 1) - st.h <= jv.n) {
-      WLoopState ws;   // every field a wave-uniform scalar (SGPR operands)
-      ws.d = uniform(st.d); ws.lo = uniform(st.lo); ws.hi = uniform(st.hi);
-      ws.bw = uniform(st.bw); ws.thr = uniform(st.thr);
-      ws.cells = uniform((int32_t)st.cells_blk); ws.bs = 0; ws.bpos = -1;
-      ws.spl0 = uniform(st.span_lo[0]); ws.sph0 = uniform(st.span_hi[0]);
-      ws.spl1 = uniform(st.span_lo[1]); ws.sph1 = uniform(st.span_hi[1]);
-      ws.dstop = uniform(2 * (e0 + 16)); ws.e0x2 = uniform(2 * e0);
-      ws.w_lo = uniform(st.w_lo); ws.w_hi = uniform(st.w_hi);
-      ws.base = uniform(P.base); ws.ng = uniform(P.neg_gap); ws.smax = S - 2;
-      ws.rlo = 0; ws.rhi = 0; ws.lf = 0; ws.ll = 0; ws.mx = kNeg;
-      const int32_t rc = WLoop<C>::run(bd.E, bd.O, bd.SE, bd.SO, ws);
-      st.d = uniform(ws.d); st.lo = uniform(ws.lo); st.hi = uniform(ws.hi);
-      st.bw = uniform(ws.bw); st.thr = uniform(ws.thr);
-      st.cells_blk = (uint32_t)uniform(ws.cells);
-      st.span_lo[0] = uniform(ws.spl0); st.span_hi[0] = uniform(ws.sph0);
-      st.span_lo[1] = uniform(ws.spl1); st.span_hi[1] = uniform(ws.sph1);
-      if (ws.bpos >= 0) {   // the last improvement of best in this run
-        st.bi = uniform(ws.bs) + ((uniform(ws.bpos) + 1) >> 1) + st.h;
-        st.bj = uniform(ws.bpos) - st.bi;
-      }
-      st.best = st.bw - st.d * P.neg_gap;   // best = bw - d |gap| between anti-diagonals
-      if (rc == 2) {   // the chain of st.d is done; finish it here
-        vint vmx;
-        vmx.x = ws.mx;
-        const int rlo = uniform(ws.rlo), rhi = uniform(ws.rhi);
-        const bool go = (st.d & 1) == 0
-                            ? wtail<C, NARROW, 0, true>(bd, st, jv, P, rlo, rhi, ws.lf, ws.ll, vmx)
-                            : wtail<C, NARROW, 1, true>(bd, st, jv, P, rlo, rhi, ws.ll, ws.lf, vmx);
-        if (!go) return true;
-      }
-      continue;
+    WLoopState ws;   // every field a wave-uniform scalar (SGPR operands)
+    ws.d = uniform(st.d); ws.lo = uniform(st.lo); ws.hi = uniform(st.hi);
+    ws.bw = uniform(st.bw); ws.thr = uniform(st.thr);
+    ws.cells = uniform((int32_t)st.cells_blk); ws.bs = 0; ws.bpos = -1;
+    ws.spl0 = uniform(st.span_lo[0]); ws.sph0 = uniform(st.span_hi[0]);
+    ws.spl1 = uniform(st.span_lo[1]); ws.sph1 = uniform(st.span_hi[1]);
+    ws.dstop = uniform(2 * (e0 + 16)); ws.e0x2 = uniform(2 * e0);
+    ws.mh = uniform(jv.m - st.h); ws.nh = uniform(jv.n + st.h);
+    ws.base = uniform(P.base); ws.ng = uniform(P.neg_gap); ws.smax = S - 2;
+    ws.rlo = 0; ws.rhi = 0; ws.lf = 0; ws.ll = 0; ws.mx = kNeg;
+    const int32_t rc = WLoop<C>::run(bd.E, bd.O, bd.SE, bd.SO, ws);
+    st.d = uniform(ws.d); st.lo = uniform(ws.lo); st.hi = uniform(ws.hi);
+    st.bw = uniform(ws.bw); st.thr = uniform(ws.thr);
+    st.cells_blk = (uint32_t)uniform(ws.cells);
+    st.span_lo[0] = uniform(ws.spl0); st.span_hi[0] = uniform(ws.sph0);
+    st.span_lo[1] = uniform(ws.spl1); st.span_hi[1] = uniform(ws.sph1);
+    if (ws.bpos >= 0) {   // the last improvement of best in this run
+      st.bi = uniform(ws.bs) + ((uniform(ws.bpos) + 1) >> 1) + st.h;
+      st.bj = uniform(ws.bpos) - st.bi;
     }
-    const bool go = even ? wstep<C, NARROW, 0, true>(bd, st, e - e0, jv, P)
-                         : wstep<C, NARROW, 1, true>(bd, st, e - e0, jv, P);
-    if (!go) return true;
+    st.best = st.bw - st.d * P.neg_gap;   // best = bw - d |gap| between anti-diagonals
+    if (rc == 4) return true;             // the next range lies outside the matrix
+    if (rc == 2) {   // the chain of st.d is done; finish it here
+      vint vmx;
+      vmx.x = ws.mx;
+      const int rlo = uniform(ws.rlo), rhi = uniform(ws.rhi);
+      const bool go = (st.d & 1) == 0
+                          ? wtail<C, NARROW, 0, true>(bd, st, jv, P, rlo, rhi, ws.lf, ws.ll, vmx)
+                          : wtail<C, NARROW, 1, true>(bd, st, jv, P, rlo, rhi, ws.ll, ws.lf, vmx);
+      if (!go) return true;
+    }
   }
 }
 
