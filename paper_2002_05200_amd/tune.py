@@ -40,7 +40,7 @@ CANDIDATES: Dict[str, list] = {
     "sched": [0, 1],
     "long_tier_bias": [0, 1, 2, 3],
     "long_job": [2000, 10000, 40000],
-    "multi_wave+waves_per_cu": [(m, w) for m in (0, 1, 2) for w in (0, 8, 16, 24)],
+    "multi_wave+waves_per_cu": [(m, w) for m in (0, 1, 2) for w in (0, 8, 12, 16, 24)],
     "sort_jobs": [1, 0],
 }
 DEFAULTS = {"sched": 0, "waves_per_cu": 0, "sort_jobs": 1, "long_job": 0, "long_tier_bias": 0,
