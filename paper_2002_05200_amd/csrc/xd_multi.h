@@ -41,6 +41,7 @@ struct MwShared {
   int32_t red[2][NW][4];    // by parity: first, last, best value, its slot
   int32_t stage[64 * C * NW];   // window moves: one anti-diagonal by slot
   int32_t save_off;             // escalation save slot of the current job
+  uint32_t words[NW][2 * kStageWords<C>];   // each wave's packed words for its score words
 };
 
 // Block-wide scalar state (every wave keeps an identical copy).
@@ -53,41 +54,18 @@ struct MwScalars {
   uint64_t cells;
 };
 
-// Score words of this wave's registers [r0, r1] (chunk starting at slot base).
+// Score words of every register of this wave's chunk (starting at slot
+// base), staged through the wave's own LDS words as in wbuild; the
+// requested range [r0, r1] is always inside.
 template <int C, bool NARROW>
 XD_FN void mw_build(WBand<C> &bd, MwScalars &st, int32_t base, int32_t e0, int32_t r0,
-                    int32_t r1, const JobView &jv, const Params &P) {
-  if (r0 < 0) r0 = 0;
-  if (r1 > C - 1) r1 = C - 1;
-  const vint l = lane_index();
-#pragma unroll
-  for (int r = 0; r < C; ++r) {
-    if (r < r0 || r > r1) continue;
-    const vint s = l + (base + 64 * r);
-    const vint i0 = s + (st.h + e0);
-    const vint j0 = splat(e0 - st.h) - s;
-    vint offAe, offAo, offB;
-    if (jv.dir > 0) {
-      offAe = i0 - 1;
-      offAo = i0;
-      offB = j0 - 1;
-    } else {
-      offAe = splat(-14) - i0;
-      offAo = splat(-15) - i0;
-      offB = splat(-14) - j0;
-    }
-    const vint wb = window16(jv.B, offB);
-    vint xe = window16(jv.A, offAe) ^ wb;
-    vint xo = window16(jv.A, offAo) ^ wb;
-    if (jv.dir < 0) {
-      xe = bit_reverse(xe);
-      xo = bit_reverse(xo);
-    }
-    bd.SE[r] = score_word<NARROW>(xe, P.pat);
-    bd.SO[r] = score_word<NARROW>(xo, P.pat);
-  }
-  st.w_lo = r0;
-  st.w_hi = r1;
+                    int32_t r1, const JobView &jv, const Params &P, uint32_t *words) {
+  (void)r0;
+  (void)r1;
+  if (jv.dir > 0) wbuild_dir<C, NARROW, 1>(bd, st.h, e0, base, words, jv, P);
+  else wbuild_dir<C, NARROW, -1>(bd, st.h, e0, base, words, jv, P);
+  st.w_lo = 0;
+  st.w_hi = C - 1;
 }
 
 // Posts both parities' chunk-edge values (after the band was (re)loaded).
@@ -124,7 +102,7 @@ XD_FN bool mw_step(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w, int 
   int first = 0x7fffffff, last = -1, bestv = kNeg, bests = 0x7fffffff;
   if (active) {
     if (rlo < st.w_lo || rhi > st.w_hi)
-      mw_build<C, NARROW>(bd, st, base, (st.d >> 1) - q, rlo - 1, rhi + 1, jv, P);
+      mw_build<C, NARROW>(bd, st, base, (st.d >> 1) - q, rlo - 1, rhi + 1, jv, P, sh.words[w]);
     // neighbours in the adjacent chunks, posted on the previous anti-diagonal
     const int32_t nb_below = w > 0 ? sh.edge[1 - PAR][w - 1][1] : kNeg;
     const int32_t nb_above = w < NW - 1 ? sh.edge[1 - PAR][w + 1][0] : kNeg;

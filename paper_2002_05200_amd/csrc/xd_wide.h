@@ -91,15 +91,18 @@ XD_FN void stage_words(uint32_t *sa, const SeqView &A, int32_t wa, uint32_t *sb,
 // windows at fixed offsets.  A's even- and odd-step windows are one base
 // apart and come from the same two words.
 template <int C, bool NARROW, int DIR>
-XD_FN void wbuild_dir(WBand<C> &bd, const WScalars &st, int32_t e0, const JobView &jv,
-                      const Params &P) {
-  uint32_t *sa = jv.stage;
-  uint32_t *sb = jv.stage + kStageWords<C>;
-  // A's lower window (even step for DIR > 0, odd for DIR < 0) and B's window:
+XD_FN void wbuild_dir(WBand<C> &bd, int32_t h, int32_t e0, int32_t base, uint32_t *stage,
+                      const JobView &jv, const Params &P) {
+  uint32_t *sa = stage;
+  uint32_t *sb = stage + kStageWords<C>;
+  // A's lower window (even step for DIR > 0, odd for DIR < 0) and B's window,
+  // for slot s = base + 64 r + l:
   //   DIR > 0: A at (h + e0 - 1) + s rising, B at (e0 - h - 1) - s falling
   //   DIR < 0: A at (-15 - h - e0) - s falling, B at (-14 - e0 + h) + s rising
-  const int32_t ca = DIR > 0 ? st.h + e0 - 1 + jv.A.sub : -15 - st.h - e0 + jv.A.sub - 64 * C + 1;
-  const int32_t cb = DIR > 0 ? e0 - st.h - 1 + jv.B.sub - 64 * C + 1 : -14 - e0 + st.h + jv.B.sub;
+  const int32_t ca = DIR > 0 ? h + e0 - 1 + base + jv.A.sub
+                             : -15 - h - e0 - base + jv.A.sub - 64 * C + 1;
+  const int32_t cb = DIR > 0 ? e0 - h - 1 - base + jv.B.sub - 64 * C + 1
+                             : -14 - e0 + h + base + jv.B.sub;
   stage_words<C>(sa, jv.A, ca >> 4, sb, jv.B, cb >> 4);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -134,8 +137,8 @@ XD_FN void wbuild(WBand<C> &bd, WScalars &st, int32_t e0, int32_t r0, int32_t r1
                   const JobView &jv, const Params &P) {
   (void)r0;
   (void)r1;
-  if (jv.dir > 0) wbuild_dir<C, NARROW, 1>(bd, st, e0, jv, P);
-  else wbuild_dir<C, NARROW, -1>(bd, st, e0, jv, P);
+  if (jv.dir > 0) wbuild_dir<C, NARROW, 1>(bd, st.h, e0, 0, jv.stage, jv, P);
+  else wbuild_dir<C, NARROW, -1>(bd, st.h, e0, 0, jv.stage, jv, P);
   st.w_lo = 0;
   st.w_hi = C - 1;
 }
