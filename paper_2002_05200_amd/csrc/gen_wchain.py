@@ -157,6 +157,74 @@ def function(C, par):
     return lines
 
 
+def function_run(C, par):
+    """WChainRun<C, PAR>::run: WChain's chain run to the window's last
+    register (C - 1 going up, 0 going down) without a test per register; the
+    far register of the range (rhi going up, rlo going down) is then cut to
+    the lanes in ml through a table of branches, its survivors go to ll, and
+    the register past it becomes -inf.  Past the span's far end every input
+    is -inf except for at most two slots next to it when the range was
+    clipped there, so the registers beyond need nothing more; lanes cut from
+    the far register may have raised vmx, which callers only use to start a
+    search of the range itself."""
+    stop = "rhi" if par == 0 else "rlo"
+    lines = [
+        f"template <>",
+        f"XD_MEMBER void WChainRun<{C}, {par}>::run(vint *cur, const vint *prv, const vint *sw,",
+        f"                                      int32_t pos, int32_t thr, int32_t base, int32_t rlo,",
+        f"                                      int32_t rhi, vint carry, vint &vmx, uint64_t mf,",
+        f"                                      uint64_t ml, uint64_t &lf, uint64_t &ll) {{",
+        f"  int32_t tA = carry.x, tB = carry.x, t2, u, mx = vmx.x;",
+        f"  const int32_t first = {'rlo' if par == 0 else f'{C - 1} - rhi'};   // chain position of the entry",
+        f"  const int32_t stop = {stop};",
+        f"  const uint64_t lm = {'1ull' if par == 0 else '1ull << 63'};",
+        f"  uint64_t lfv, llv;",
+        f"  asm volatile(",
+    ]
+    body = [x.replace("{t}", ".Lj") for x in _jump(".Lh{}_%=", "first", C)]
+    for k in range(C):
+        r = _reg(C, par, k)
+        nxt = f".Lr{k + 1}_%=" if k + 1 < C else ".Lfx_%="
+        body += [f'".Lh{k}_%=:\\n\\t"'] + _cell(C, par, k) + [
+            '"s_and_b64 vcc, vcc, %[mf]\\n\\t"',
+            '"s_mov_b64 %[lf], vcc\\n\\t"',
+        ] + _keep(r) + [f'"s_branch {nxt}\\n\\t"']
+    for k in range(1, C):
+        body += [f'".Lr{k}_%=:\\n\\t"'] + _cell(C, par, k) + _keep(_reg(C, par, k))
+    body += ['".Lfx_%=:\\n\\t"']
+    body += [x.replace("{t}", ".Lx") for x in _jump(".LF{}_%=", "stop", C)]
+    for r in range(C):
+        rn = r + 1 if par == 0 else r - 1
+        body += [
+            f'".LF{r}_%=:\\n\\t"',
+            f'"v_cndmask_b32_e64 %[c{r}], -2.0, %[c{r}], %[ml]\\n\\t"',
+            f'"v_cmp_le_i32_e64 %[ll], %[thr], %[c{r}]\\n\\t"',
+        ] + ([f'"v_mov_b32 %[c{rn}], -2.0\\n\\t"'] if 0 <= rn < C else []) + [
+            '"s_branch .Lend_%=\\n\\t"',
+        ]
+    body += ['".Lend_%=:\\n"']
+    lines += ["      " + x for x in body]
+    outs = ", ".join(f'[c{r}] "+v"(cur[{r}].x)' for r in range(C))
+    ins = ", ".join(f'[p{r}] "v"(prv[{r}].x)' for r in range(C))
+    sws = ", ".join(f'[s{r}] "v"(sw[{r}].x)' for r in range(C))
+    lines += [
+        f"      : {outs},",
+        f'        [tA] "+v"(tA), [tB] "+v"(tB), [mx] "+v"(mx), [t2] "=&v"(t2), [u] "=&v"(u),',
+        f'        [lf] "=&s"(lfv), [ll] "=&s"(llv)',
+        f"      : {ins},",
+        f"        {sws},",
+        f'        [pos] "s"(pos), [thr] "s"(thr), [base] "s"(base), [first] "s"(first),',
+        f'        [stop] "s"(stop), [lm] "s"(lm), [mf] "s"(mf), [ml] "s"(ml)',
+        f'      : "vcc", "scc", "s40", "s41", "s42");',
+        f"  vmx.x = mx;",
+        f"  lf = lfv;",
+        f"  ll = llv;",
+        f"}}",
+        "",
+    ]
+    return lines
+
+
 def first_function(C):
     """WFirst<C>::run: slot (64 r + lane) of the first cell above `bw` in
     registers rlo .. rhi, or -1."""
@@ -540,11 +608,16 @@ def render() -> str:
         "// WFirst<C>::run returns the first slot (64 r + lane) of registers",
         "// rlo..rhi whose cell exceeds bw, or -1 when none does.",
         "//",
+        "// WChainRun<C, PAR>::run is the same chain run to the window's last",
+        "// register without a test per register, the far register cut to ml",
+        "// afterwards and the register past it set to -inf; its vmx may count",
+        "// lanes past the range (callers search the range itself).",
+        "//",
         "// WLoop<C>::run runs whole anti-diagonals of one score-word block:",
         "// span clearing, the chain, survivors, the improvement of best (match =",
-        "// 1), cells and the next range, leaving when the block ends, the span",
-        "// outgrows the score words, the survivors are not in the span's edge",
-        "// registers, or the next range needs a recentre.",
+        "// 1), cells and the next range clipped to the matrix, leaving when the",
+        "// block ends, the survivors are not in the span's edge registers, the",
+        "// next range needs a recentre, or the clipped range is empty.",
         "#pragma once",
         "",
         '#include "xd_wave.h"',
@@ -553,6 +626,14 @@ def render() -> str:
         "",
         "template <int C, int PAR>",
         "struct WChain {",
+        "  XD_MEMBER static void run(vint *cur, const vint *prv, const vint *sw, int32_t pos,",
+        "                            int32_t thr, int32_t base, int32_t rlo, int32_t rhi,",
+        "                            vint carry, vint &vmx, uint64_t mf, uint64_t ml,",
+        "                            uint64_t &lf, uint64_t &ll);",
+        "};",
+        "",
+        "template <int C, int PAR>",
+        "struct WChainRun {",
         "  XD_MEMBER static void run(vint *cur, const vint *prv, const vint *sw, int32_t pos,",
         "                            int32_t thr, int32_t base, int32_t rlo, int32_t rhi,",
         "                            vint carry, vint &vmx, uint64_t mf, uint64_t ml,",
@@ -587,6 +668,7 @@ def render() -> str:
     for C in CS:
         for par in (0, 1):
             out += function(C, par)
+            out += function_run(C, par)
         out += first_function(C)
         if C >= 4:
             out += loop_function(C)
