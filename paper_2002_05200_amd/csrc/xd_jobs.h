@@ -55,6 +55,9 @@ struct Params {
   // A against base q of B; has_lut = 0 for match/mismatch scoring.
   int32_t has_lut;
   int32_t lut[16];
+  // Persistent tiers: the first prio_jobs jobs a tier hands out (its longest)
+  // run at raised wavefront priority; 0 = none.
+  int32_t prio_jobs;
 };
 
 // Layout of one save: a header, then the W values of the latest even and odd

@@ -186,6 +186,10 @@ __global__ __launch_bounds__(kBlock, C >= 32 && NARROW ? 2 : 1) void k_extend(
     w = uniform(got);
   }
   while (w < total) {
+    // the queue hands out the longest jobs first: they set the tier's end, so
+    // they take the SIMD's issue slot ahead of the waves sharing it
+    if (w < P.prio_jobs) __builtin_amdgcn_s_setprio(3);
+    else __builtin_amdgcn_s_setprio(0);
     const int32_t j = tier_job(q, w, n_init, n_esc);
     const Job job = jobs[j];
     JobOut o;
@@ -580,6 +584,7 @@ xd_status enqueue(xd_ctx *c, const Bufs &B, hipStream_t s, const Launch &L, bool
   P.job_save = B.job_save;
   P.has_lut = 0;
   for (int t = 0; t < 16; ++t) P.lut[t] = 0;
+  P.prio_jobs = persistent ? 4 * c->num_cu : 0;
   const bool narrow = P.delta <= 3;
 
   if (prof) XD_HIP(hipEventRecord(c->ev[0], s));
