@@ -307,39 +307,59 @@ def _loop_chain(C, par, P):
     registers are c{r} (even: E, odd: O), the previous anti-diagonal's are
     p{r}, score words w{r}.
 
-    It enters at the span's first register (rlo going up, rhi going down)
-    and runs to the window's last register without a test per register.
-    The entry register takes its outer neighbour from the rotation of the
-    register before it (a live cell when the range was clipped to the
-    matrix there, else -inf), is cut to the range (mask mf) before the
-    X-drop test, and its survivors go straight to lf.  Past the span's far
-    end every input is -inf except for at most two slots next to it (the
-    cells a clipped range left out of the matrix), so the registers there
-    stay -inf but for those slots; the far edge register and the one after
-    it are put right afterwards through a table of branches on its index:
-    the edge register is cut to the range (mask ml) and its survivors go to
-    ll, the next register becomes -inf (it lies outside the span).  Cut lanes
-    may have raised the running maximum: the improvement search after the
-    chain only looks at the range, so such a false alarm changes nothing."""
+    Both parities walk the span downwards, from rhi to the window's register
+    0, without a test per register.  A cell's neighbour on the previous
+    anti-diagonal is the rotation of its own register with one lane taken
+    from the register beside it: on even anti-diagonals slot s - 1 (lane 0
+    from the register below, whose rotation each block computes for itself
+    and leaves to the next block as that block's own rotation), on odd ones
+    slot s + 1 (lane 63 from the register above, rotated by the block
+    before).  The entry register takes that neighbour from the real register
+    (a live cell when the range was clipped to the matrix there), is cut to
+    the range (mask mf) before the X-drop test, and its survivors go
+    straight to lf.  Below the span's low end every input is -inf except for
+    at most two slots next to it (cells a clipped range left out of the
+    matrix), so the registers there stay -inf but for those slots; the low
+    edge register rlo and the one below it are put right afterwards through
+    a table of branches on rlo: the edge register is cut to the range (mask
+    ml) and its survivors go to ll, the register below it becomes -inf (it
+    lies outside the span).  Cut lanes may have raised the running maximum:
+    the improvement search that follows only looks at the range, so such a
+    false alarm changes nothing.  Placing bands low in the window keeps the
+    registers below the span few."""
     cur = "e" if par == 0 else "o"
     prv = "o" if par == 0 else "e"
     sw = "se" if par == 0 else "so"
     rot = "wave_ror:1" if par == 0 else "wave_rol:1"
 
     def reg(k):
-        return k if par == 0 else C - 1 - k
+        return C - 1 - k
+
+    def regs(k):
+        """(rotation written by block k, the other one) for position k."""
+        return ("tA", "tB") if k % 2 == 0 else ("tB", "tA")
 
     def cell(k, cond="vcc", mask=None):
         r = reg(k)
-        own, carry = ("tA", "tB") if k % 2 == 0 else ("tB", "tA")
+        mine, other = regs(k)
         cmp = (f'"v_cmp_le_i32 vcc, %[thr], %[{cur}{r}]\\n\\t"' if cond == "vcc" else
                f'"v_cmp_le_i32_e64 %[{cond}], %[thr], %[{cur}{r}]\\n\\t"')
         cut = ([f'"v_cndmask_b32_e64 %[{cur}{r}], -2.0, %[{cur}{r}], %[{mask}]\\n\\t"']
                if mask else [])
-        return [
-            f'"v_mov_b32_dpp %[{own}], %[{prv}{r}] {rot} row_mask:0xf bank_mask:0xf\\n\\t"',
-            f'"v_bfe_u32 %[u], %[{sw}{r}], %[pos], 2\\n\\t"',
-            f'"v_cndmask_b32_e64 %[t2], %[{own}], %[{carry}], %[lm{par}]\\n\\t"',
+        if par == 0:
+            # even: this block rotates the register below (lane 0's neighbour here,
+            # the next block's own rotation); its own rotation is in `other`
+            below = (f'"v_mov_b32_dpp %[{mine}], %[{prv}{r - 1}] {rot} row_mask:0xf bank_mask:0xf\\n\\t"'
+                     if r >= 1 else f'"v_mov_b32 %[{mine}], -2.0\\n\\t"')
+            nbr = [below, f'"v_bfe_u32 %[u], %[{sw}{r}], %[pos], 2\\n\\t"',
+                   f'"v_cndmask_b32_e64 %[t2], %[{other}], %[{mine}], %[lm0]\\n\\t"']
+        else:
+            # odd: this block rotates its own register; lane 63's neighbour is the
+            # rotation of the register above, left by the block before in `other`
+            nbr = [f'"v_mov_b32_dpp %[{mine}], %[{prv}{r}] {rot} row_mask:0xf bank_mask:0xf\\n\\t"',
+                   f'"v_bfe_u32 %[u], %[{sw}{r}], %[pos], 2\\n\\t"',
+                   f'"v_cndmask_b32_e64 %[t2], %[{mine}], %[{other}], %[lm1]\\n\\t"']
+        return nbr + [
             f'"v_add3_u32 %[{cur}{r}], %[{cur}{r}], %[base], %[u]\\n\\t"',
             f'"v_max3_i32 %[{cur}{r}], %[{cur}{r}], %[{prv}{r}], %[t2]\\n\\t"',
         ] + cut + [cmp]
@@ -351,36 +371,33 @@ def _loop_chain(C, par, P):
         return [sel, f'"v_max_i32 %[mx], %[mx], %[{cur}{r}]\\n\\t"']
 
     out = [
-        '"v_mov_b32 %[tA], -2.0\\n\\t"',     # the chain's outer neighbour: -inf
+        '"v_mov_b32 %[tA], -2.0\\n\\t"',     # the neighbour above the window: -inf
         '"v_mov_b32 %[tB], -2.0\\n\\t"',
         '"v_mov_b32 %[mx], -2.0\\n\\t"',
+        f'"s_sub_u32 %[ix], {C - 1}, %[rhi]\\n\\t"',   # chain position of rhi
     ]
-    # entry: chain position of the first register
-    if par == 0:
-        out += ['"s_mov_b32 %[ix], %[rlo]\\n\\t"']
-    else:
-        out += [f'"s_sub_u32 %[ix], {C - 1}, %[rhi]\\n\\t"']
     out += [x.replace("{t}", f".L{P}j") for x in _jump(f".L{P}h{{}}_%=", "ix", C)]
     for k in range(C):
+        r = reg(k)
+        mine, other = regs(k)
         nxt = f".L{P}r{k + 1}_%=" if k + 1 < C else f".L{P}fx_%="
         out += [f'".L{P}h{k}_%=:\\n\\t"']
-        if k >= 1:   # the outer neighbour: rotation of the register before
-            carry = "tB" if k % 2 == 0 else "tA"
-            out += [f'"v_mov_b32_dpp %[{carry}], %[{prv}{reg(k - 1)}] {rot} row_mask:0xf bank_mask:0xf\\n\\t"']
+        if par == 0:   # the entry's own rotation (the block before would have left it)
+            out += [f'"v_mov_b32_dpp %[{other}], %[{prv}{r}] {rot} row_mask:0xf bank_mask:0xf\\n\\t"']
+        elif r + 1 < C:   # the rotation of the register above the entry
+            out += [f'"v_mov_b32_dpp %[{other}], %[{prv}{r + 1}] {rot} row_mask:0xf bank_mask:0xf\\n\\t"']
         out += cell(k, "lf", "mf") + keep(k, "lf") + [f'"s_branch {nxt}\\n\\t"']
     for k in range(1, C):
         out += [f'".L{P}r{k}_%=:\\n\\t"'] + cell(k) + keep(k)
-    # the far edge register: rhi going up, rlo going down
-    far = "rhi" if par == 0 else "rlo"
+    # the low edge register rlo and the one below it
     out += [f'".L{P}fx_%=:\\n\\t"']
-    out += [x.replace("{t}", f".L{P}x") for x in _jump(f".L{P}F{{}}_%=", far, C)]
+    out += [x.replace("{t}", f".L{P}x") for x in _jump(f".L{P}F{{}}_%=", "rlo", C)]
     for r in range(C):
-        rn = r + 1 if par == 0 else r - 1   # the register after it, outside the span
         out += [
             f'".L{P}F{r}_%=:\\n\\t"',
             f'"v_cndmask_b32_e64 %[{cur}{r}], -2.0, %[{cur}{r}], %[ml]\\n\\t"',
             f'"v_cmp_le_i32_e64 %[ll], %[thr], %[{cur}{r}]\\n\\t"',
-        ] + ([f'"v_mov_b32 %[{cur}{rn}], -2.0\\n\\t"'] if 0 <= rn < C else []) + [
+        ] + ([f'"v_mov_b32 %[{cur}{r - 1}], -2.0\\n\\t"'] if r >= 1 else []) + [
             f'"s_branch .L{P}end_%=\\n\\t"',
         ]
     out += [f'".L{P}end_%=:\\n\\t"']
@@ -414,16 +431,15 @@ def _loop_half(C, par):
         '"s_and_b64 %[mf], %[mlo], %[mhi]\\n\\t"',
         '"s_cmp_eq_u32 %[rlo], %[rhi]\\n\\t"',
     ]
-    if par == 0:   # the chain enters at rlo (mask lo) and leaves at rhi (mask hi)
-        out += ['"s_cselect_b64 %[mf], %[mf], %[mlo]\\n\\t"', '"s_mov_b64 %[ml], %[mhi]\\n\\t"',
-                '"s_sub_i32 %[pos], %[d], %[e0x2]\\n\\t"']
-    else:          # enters at rhi (mask hi), leaves at rlo (mask lo)
-        out += ['"s_cselect_b64 %[mf], %[mf], %[mhi]\\n\\t"', '"s_mov_b64 %[ml], %[mlo]\\n\\t"',
-                '"s_sub_i32 %[pos], %[d], %[e0x2]\\n\\t"', '"s_add_i32 %[pos], %[pos], -1\\n\\t"']
+    # the chain enters at rhi (mask hi) and leaves at rlo (mask lo)
+    out += ['"s_cselect_b64 %[mf], %[mf], %[mhi]\\n\\t"', '"s_mov_b64 %[ml], %[mlo]\\n\\t"',
+            '"s_sub_i32 %[pos], %[d], %[e0x2]\\n\\t"']
+    if par == 1:
+        out += ['"s_add_i32 %[pos], %[pos], -1\\n\\t"']
     out += _loop_chain(C, par, P)
     # survivors of the range's first and last register
     # (lf, the entry register's, was written long before ll: test it first)
-    lo_mask, hi_mask = ("lf", "ll") if par == 0 else ("ll", "lf")
+    lo_mask, hi_mask = "ll", "lf"
     first_part = [
         f'"s_cmp_eq_u64 %[{lo_mask}], 0\\n\\t"',
         '"s_cbranch_scc1 .Lx2_%=\\n\\t"',
@@ -439,7 +455,7 @@ def _loop_half(C, par):
         '"s_add_i32 %[t], %[t], 63\\n\\t"',
         '"s_sub_i32 %[last], %[t], %[last]\\n\\t"',
     ]
-    out += (first_part + last_part) if par == 0 else (last_part + first_part)
+    out += last_part + first_part
     out += [
         # did best improve?  (match = 1: by exactly one; out of line)
         '"v_cmp_lt_i32_e32 vcc, %[bw], %[mx]\\n\\t"',

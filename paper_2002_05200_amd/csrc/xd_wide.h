@@ -571,14 +571,27 @@ XD_FN void wshift(vint *a, int m) {
   }
 }
 
-// Moves the window so the pending range sits in its middle.  Returns false
+// Where a band of `width` slots starts after a window move: in the middle
+// for the two-register tier (its loop wants the band across both
+// registers), else low in the window, kLowMargin slots above its bottom
+// (WLoop's chains run from the span's top register down to register 0, so
+// registers below the span cost work on every anti-diagonal).
+constexpr int kLowMargin = 32;
+template <int C>
+XD_FN int wplace(int width) {
+  constexpr int S = kWave * C;
+  const int mid = (S - width) / 2;
+  return C >= 4 && mid > kLowMargin ? kLowMargin : mid;
+}
+
+// Moves the window so the pending range starts at wplace.  Returns false
 // when the range is too wide for this tier.
 template <int C>
 XD_FN bool wrecenter(WBand<C> &bd, WScalars &st) {
   constexpr int S = kWave * C;
   const int width = st.hi - st.lo + 1;
   if (width > S - 2) return false;
-  int dl = st.lo - (S - width) / 2;   // new slot = old slot - dl
+  int dl = st.lo - wplace<C>(width);   // new slot = old slot - dl
   while (dl != 0) {
     const int m = dl > 63 ? 63 : (dl < -63 ? -63 : dl);
     wshift<C>(bd.E, m);
@@ -624,10 +637,11 @@ XD_FN bool wrestore(WBand<C> &bd, WScalars &st, const Params &P, int32_t j) {
   constexpr int S = kWave * C;
   if (cs >= C) return false;
   const int32_t ss = kWave * cs;
-  const int32_t shift = (S - ss) / 2;
+  const int32_t lo0 = uniform(sv[kSvLo]), hi0 = uniform(sv[kSvHi]);
+  const int32_t shift = wplace<C>(hi0 - lo0 + 1) - lo0;   // saved slot + shift = new slot
   st.d = uniform(sv[kSvD]);
-  st.lo = uniform(sv[kSvLo]) + shift;
-  st.hi = uniform(sv[kSvHi]) + shift;
+  st.lo = lo0 + shift;
+  st.hi = hi0 + shift;
   st.h = uniform(sv[kSvH]) - shift;
   st.best = uniform(sv[kSvBest]); st.bi = uniform(sv[kSvBi]); st.bj = uniform(sv[kSvBj]);
   st.bw = uniform(sv[kSvBw]); st.thr = uniform(sv[kSvThr]);
@@ -721,14 +735,18 @@ XD_FN bool wide_fast(WBand<C> &bd, WScalars &st, const JobView &jv, const Params
   for (;;) {
     const int32_t e = st.d >> 1;
     const bool even = (st.d & 1) == 0;
+    bool move = st.lo < 1 || st.hi > S - 2;
     if (even && e - e0 == 16) {
       e0 = e;
       st.cells += st.cells_blk;
       st.cells_blk = 0;
       st.w_lo = 1;
       st.w_hi = 0;
+      // a band a register or more above its place moves down (the words are
+      // rebuilt for this block anyway)
+      if (st.lo - wplace<C>(st.hi - st.lo + 1) >= kWave) move = true;
     }
-    if (st.lo < 1 || st.hi > S - 2) {
+    if (move) {
       if (!wrecenter<C>(bd, st)) return false;
     }
     if ((st.lo >> 6) < st.w_lo || (st.hi >> 6) > st.w_hi)
@@ -759,8 +777,9 @@ XD_FN bool wide_fast(WBand<C> &bd, WScalars &st, const JobView &jv, const Params
       vint vmx;
       vmx.x = ws.mx;
       const int rlo = uniform(ws.rlo), rhi = uniform(ws.rhi);
+      // (both parities' chains enter at rhi: lf holds its survivors, ll rlo's)
       const bool go = (st.d & 1) == 0
-                          ? wtail<C, NARROW, 0, true>(bd, st, jv, P, rlo, rhi, ws.lf, ws.ll, vmx)
+                          ? wtail<C, NARROW, 0, true>(bd, st, jv, P, rlo, rhi, ws.ll, ws.lf, vmx)
                           : wtail<C, NARROW, 1, true>(bd, st, jv, P, rlo, rhi, ws.ll, ws.lf, vmx);
       if (!go) return true;
     }
