@@ -324,7 +324,7 @@ def host_buffers(ctx, db, args, tuned, cells_per_step, ref) -> dict:
 def kernel_name(tier: int, multi_wave: int):
     """Name and file tag of the kernel that runs a tier (stage) of the step."""
     if tier >= 6:   # the stage after the register tiers: a workgroup per job, then HBM
-        return ("k_extend_mw<8, 16> + k_spill (bands wider than 2,048 slots: 8 wavefronts "
+        return ("k_extend_mw<4, 16> + k_spill (bands wider than 2,048 slots: 4 wavefronts "
                 "per job, then a global-memory band)", "k_extend_huge")
     c = 1 << tier
     if tier >= 3 and multi_wave in (1, 2):

@@ -621,12 +621,14 @@ xd_status enqueue(xd_ctx *c, const Bufs &B, hipStream_t s, const Launch &L, bool
     XD_HIP(hipGetLastError());
     q.esc = B.esc_sorted;
     int32_t *huge_list = B.esc + kLists * stride;
-    // 8,192 slots: 8 wavefronts of 16 registers (measured faster than 16 of 8:
-    // fewer waves take part in each anti-diagonal's barrier and reduction);
-    // one workgroup per CU (two per CU measured the same on uneven: the
-    // tier's time is its longest job's)
-    constexpr int kHugeNW = 8, kHugeC = 16;
-    const unsigned huge_grid = (unsigned)c->num_cu;
+    // 4,096 slots: 4 wavefronts of 16 registers, two workgroups per CU (at
+    // 174 VGPRs two fit); measured faster than 8 wavefronts of 16 registers
+    // one per CU (uneven: 115 -> 100 ms): fewer waves take part in each
+    // anti-diagonal's barrier and reduction, and the jobs of the tier run
+    // at once instead of in two rounds.  Bands wider than 4,094 cells start
+    // over in the global-memory pass.
+    constexpr int kHugeNW = 4, kHugeC = 16;
+    const unsigned huge_grid = 2u * (unsigned)c->num_cu;
     if (narrow)
       hipLaunchKernelGGL((k_extend_mw<kHugeNW, kHugeC, true>), dim3(huge_grid),
                          dim3(64 * kHugeNW), 0, s, B.jobs, q, B.counters + kHead + kTiers,

@@ -346,8 +346,9 @@ def test_bands_wider_than_the_first_spill_pass(ctx, xd):
 
 
 def test_multi_wave_tier_from_the_start(ctx, xd):
-    """Every job straight to the workgroup-per-job tier (16 wavefronts, 8,192
-    slots): narrow and wide bands, recentring across wavefronts."""
+    """Every job straight to the workgroup-per-job tier (4 wavefronts of 16
+    registers, 4,096 slots): narrow and wide bands, recentring across
+    wavefronts."""
     from paper_2002_05200_amd import synth
     bt = synth.concat([synth.random_cases(seed=700, n=60, len_lo=17, len_hi=900,
                                           x_choices=(0, 1, 5, 20, 100)),
