@@ -378,6 +378,47 @@ def _ending_pairs(seed, n=48):
     return synth.from_pairs(a_l, b_l, pa_l, pa_l, x_l, name=f"ending[{seed}]")
 
 
+def _edge_riding_pairs(seed, n=24):
+    """Pairs of very unequal lengths: one read is a mutated stretch of the
+    other (or an unrelated read sharing only the seed) and ends long before
+    it, so once it runs out the band keeps going along the matrix edge (j = n
+    or i = m) with its range clipped there (X 100-400: bands of hundreds of
+    cells)."""
+    from paper_2002_05200_amd import synth
+    rng = np.random.default_rng(np.random.SeedSequence(1409, spawn_key=(seed,)))
+    a_l, b_l, pa_l, pb_l, x_l = [], [], [], [], []
+    for t in range(n):
+        la = int(rng.integers(3000, 8000))
+        lb = int(rng.integers(600, 2500))
+        a = rng.integers(0, 4, la).astype(np.uint8)
+        start = int(rng.integers(0, la - lb))
+        if t % 2 == 0:   # true stretch of A
+            b = synth.mutate(rng, a[start:start + lb], 0.04, 0.03, 0.03)
+        else:            # unrelated
+            b = rng.integers(0, 4, lb).astype(np.uint8)
+        pb = int(rng.integers(0, len(b) - 17))
+        pa = start + pb if t % 2 == 0 else int(rng.integers(0, la - 17))
+        pa = min(pa, la - 17)
+        b[pb:pb + 17] = a[pa:pa + 17]
+        if t % 4 >= 2:   # the short read as A: the range rides the edge i = m
+            a, b, pa, pb = b, a, pb, pa
+        a_l.append(a); b_l.append(b); pa_l.append(pa); pb_l.append(pb)
+        x_l.append(int(rng.choice([100, 200, 400])))
+    return synth.from_pairs(a_l, b_l, pa_l, pb_l, x_l, name=f"edge-riding[{seed}]")
+
+
+@pytest.mark.parametrize("min_tier", [0, 3, 4, 5])
+def test_bands_along_the_matrix_edge(ctx, xd, min_tier):
+    """The wide tiers' assembly loop with ranges clipped to the matrix for
+    long stretches (one read ends long before the other), from every
+    register count; both extension directions."""
+    bt = _edge_riding_pairs(min_tier)
+    got = run(ctx, xd, bt, min_tier=min_tier)
+    st = ctx.stats()
+    assert st["jobs"][3:6].sum() > 0, st
+    assert_same(got, oracle_of(bt), f"edge-riding from tier {min_tier}")
+
+
 @pytest.mark.parametrize("impl", [0, 1])
 def test_two_register_tier_cases(ctx, xd, impl):
     """The two-register tier's hand-scheduled loop and its C steps: bands of
