@@ -23,9 +23,10 @@
 
 namespace xd {
 
-// Shapes: NW wavefronts per job, C registers per wavefront.  The widest
-// (16 x 8, 8,192 slots) takes bands no single wavefront holds; narrower ones
-// (4 x 4, 4 x 8) shorten each anti-diagonal of very long jobs by spreading a
+// Shapes: NW wavefronts per job, C registers per wavefront.  4 x 16 (4,096
+// slots, two workgroups per CU) takes the bands no single wavefront holds;
+// the multi_wave option's shapes (2 or 4 wavefronts sharing a tier's
+// registers) shorten each anti-diagonal of very long jobs by spreading a
 // band one wavefront could hold over several.
 template <int NW, int C>
 struct MwShape {
