@@ -157,7 +157,7 @@ XD_FN Win make_win(const AsmView &v, vint off) {
   "v_cmp_lt_i32 vcc, %[bw], %[" CUR "]\n\t"                                       \
   "s_cbranch_vccnz .Li" TAG "_%=\n"                                                \
   ".Lr" TAG "_%=:\n\t"                                                             \
-  "s_add_i32 %[thr], %[thr], %[ng]\n\t"                                           \
+  "v_add_u32 %[thr], %[ng], %[thr]\n\t"                                           \
   "v_add_u32 %[bw], %[ng], %[bw]\n"                                               \
   ".Lq" TAG "_%=:\n\t"                                                             \
   "s_ff1_i32_b64 %[a], %[live]\n\t"                                               \
@@ -207,7 +207,7 @@ XD_FN Win make_win(const AsmView &v, vint off) {
   ".Li" TAG "_%=:\n\t"                                                             \
   "s_ff1_i32_b64 %[bs], vcc\n\t"                                                  \
   "s_add_i32 %[bpos], %[e0x2], " BP "\n\t"                                        \
-  "s_add_i32 %[thr], %[thr], %[ng1]\n\t"                                          \
+  "v_add_u32 %[thr], %[ng1], %[thr]\n\t"                                          \
   "v_add_u32 %[bw], %[ng1], %[bw]\n\t"                                            \
   "s_branch .Lq" TAG "_%=\n"
 #define XD_IMP_LOOP(TAG, CUR, BP)                                                 \
@@ -222,7 +222,7 @@ XD_FN Win make_win(const AsmView &v, vint off) {
   ".Lid" TAG "_%=:\n\t"                                                            \
   "v_cmp_eq_u32 vcc, %[tv], %[" CUR "]\n\t"                                       \
   "v_mov_b32 %[bw], %[tv]\n\t"                                                    \
-  "s_add_i32 %[thr], %[thr], %[inc]\n\t"                                          \
+  "v_add_u32 %[thr], %[inc], %[thr]\n\t"                                          \
   "s_ff1_i32_b64 %[bs], vcc\n\t"                                                  \
   "s_add_i32 %[bpos], %[e0x2], " BP "\n\t"                                        \
   "s_branch .Lr" TAG "_%=\n"
@@ -305,6 +305,7 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
   const uint32_t *base_a = av_a.base, *base_b = av_b.base;
   int32_t par = st.par;
   int32_t bw = st.bw;
+  int32_t thrv = st.thr;   // the prune threshold in a VGPR: its drift is a VOP2 add, off the scalar unit
   int32_t u, t, tv, x0, x1, x2, p0, p2;
   // score words of block e0 (the loop rebuilds them at each later block)
   {
@@ -367,7 +368,7 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
         [lo2] "+v"(w2.lo.x), [hi2] "+v"(w2.hi.x), [nx2] "+v"(w2.nx.x), [idx2] "+v"(w2.idx.x), \
         [u] "=&v"(u), [t] "=&v"(t), [tv] "=&v"(tv), [x0] "=&v"(x0), [x1] "=&v"(x1),   \
         [x2] "=&v"(x2), [p0] "=&v"(p0), [p2] "=&v"(p2),               \
-        [thr] "+s"(st.thr), [bs] "+s"(bs), [bpos] "+s"(bpos),                         \
+        [thr] "+v"(thrv), [bs] "+s"(bs), [bpos] "+s"(bpos),                         \
         [par] "+s"(par), [pos] "+s"(pos), [e0x2] "+s"(e0x2), [range] "+s"(st.range),  \
         [live] "+s"(live), [a] "+s"(a), [f] "+s"(f), [tmp] "+s"(tmp), [inc] "+s"(inc), \
         [status] "+s"(status)                                                         \
@@ -407,6 +408,7 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
   // thresholds satisfy bw = best + d |gap| there, which gives best
   const int32_t d_now = e0x2 + pos + par;
   st.bw = uniform(bw);
+  st.thr = uniform(thrv);
   st.best = st.bw - d_now * P.neg_gap;
   if (bpos >= 0) {   // best cell: i = s + ceil(d/2) + h, j = d - i, d = bpos
     st.bi = bs + ((bpos + 1) >> 1) + st.h;
