@@ -164,10 +164,14 @@ __global__ __launch_bounds__(kPlanBlock) void k_scatter(const int32_t *__restric
 
 // One job per wavefront.  Plain: wave w of the grid takes work item w.
 // Persistent (head != nullptr): waves pop work items until none is left.
-// The 32-register tier is held to 256 VGPRs (two resident wavefronts per
-// SIMD instead of one), so a second job hides the first one's latencies.
+// The one-register tier is held to eight resident wavefronts per SIMD (its
+// scalar registers were the limit at seven; the compiler keeps the excess in
+// VGPR lanes outside the assembly loop), which hides more of each
+// anti-diagonal's dependent chain.  The 32-register tier is held to 256 VGPRs
+// (two resident wavefronts per SIMD instead of one), so a second job hides
+// the first one's latencies.
 template <int C, bool NARROW>
-__global__ __launch_bounds__(kBlock, C >= 32 && NARROW ? 2 : 1) void k_extend(
+__global__ __launch_bounds__(kBlock, C == 1 ? 8 : (C >= 32 && NARROW ? 2 : 1)) void k_extend(
     const Job *__restrict__ jobs, TierQueue q, int32_t *head, JobOut *__restrict__ outs,
     unsigned long long *stats, Params P) {
   const int wave = uniform((int32_t)(threadIdx.x >> 6));

@@ -7,19 +7,26 @@
 // returns to C code when the extension ends, the band needs recentring, or
 // the window approaches the end of a read.
 //
-// Common path of one anti-diagonal (9 VALU, 8 SALU; the 32 anti-diagonals of
-// a score-word block are unrolled, so field offsets are immediates):
+// Common path of one anti-diagonal (10 VALU, 6-7 SALU; the 32 anti-diagonals
+// of a score-word block are unrolled, so field offsets are immediates):
 //   v_addc_co_u32  cnt, 0, cnt, carry=range          cells of this range, per lane
 //   v_mov_b32_dpp  t, prev  wave_shr:1 / wave_shl:1  neighbour diagonal (d-1)
 //   v_bfe_u32      u, score_word, 2q, 2              match field
 //   v_add3_u32     cur, cur, base, u                 diagonal term (d-2)
 //   v_max3_i32     cur, cur, prev, t                 the recurrence, gap-free form
 //   v_cmp_le_i32   vcc, thr, cur                     X-drop test ...
-//   s_and_b64      live, vcc, range                  ... within the computed range
-//   v_cndmask_b32  cur, -inf, cur, live              pruned cells to -inf
+//   s_and_b64      vcc, vcc, range                   ... within the computed range
+//   v_cndmask_b32  cur, -inf, cur, vcc               pruned cells to -inf (VOP2 form:
+//                                                    the survivor mask stays in VCC)
+//   s_ff1 / s_flbit                                  survivor ends, read before the
+//                                                    improvement test takes VCC
 //   v_cmp_lt_i32   vcc, bw, cur                      did best improve?
-//   s_add / v_add  thr, bw += -gap                   thresholds of d+1
-//   s_ff1 / s_flbit / s_bfm                          trim: next range mask
+//   v_add / v_add  thr, bw += -gap                   thresholds of d+1
+//   s_add / s_sub / s_bfm                            trim: next range mask
+// The issue slots per anti-diagonal matter less than its dependent chain:
+// with one job per wavefront a SIMD runs only a few wavefronts, so the
+// kernel is built for the eight resident wavefronts per SIMD that its
+// register use allows.
 // An improvement of best costs 3 SALU + 1 VALU out of line; best itself is
 // not tracked in the loop but recovered from bw afterwards.
 // Block transition (every 32 anti-diagonals): 2 window shifts, 2 clamped
@@ -145,28 +152,29 @@ XD_FN Win make_win(const AsmView &v, vint off) {
 // then its thresholds and survivor ends.  TAG names the step's exits:
 // .Ld (nothing survived), .Li (best improved; returns to .Lr, or past the drift
 // to .Lq).
-#define XD_CORE(TAG, DIAG, CUR, PRV, SW, SHIFT, P)                                \
+#define XD_CORE(TAG, DIAG, CUR, PRV, SW, SHIFT, P, EDGE)                          \
   "v_addc_co_u32_e64 %[cnt], vcc, 0, %[cnt], %[range]\n\t"                        \
   "v_mov_b32_dpp %[t], %[" PRV "] " SHIFT " row_mask:0xf bank_mask:0xf\n\t"        \
   DIAG(CUR, SW, P)                                                                \
   "v_max3_i32 %[" CUR "], %[" CUR "], %[" PRV "], %[t]\n\t"                        \
   "v_cmp_le_i32 vcc, %[thr], %[" CUR "]\n\t"                                      \
-  "s_and_b64 %[live], vcc, %[range]\n\t"                                          \
-  "v_cndmask_b32_e64 %[" CUR "], -2.0, %[" CUR "], %[live]\n\t"                   \
+  "s_and_b64 vcc, vcc, %[range]\n\t"                                             \
   "s_cbranch_scc0 .Ld" TAG "_%=\n\t"                                               \
+  "v_cndmask_b32_e32 %[" CUR "], -2.0, %[" CUR "], vcc\n\t"                         \
+  "s_ff1_i32_b64 %[a], vcc\n\t"                                                  \
+  "s_flbit_i32_b64 %[f], vcc\n\t"                                                \
+  EDGE                                                                            \
   "v_cmp_lt_i32 vcc, %[bw], %[" CUR "]\n\t"                                       \
   "s_cbranch_vccnz .Li" TAG "_%=\n"                                                \
   ".Lr" TAG "_%=:\n\t"                                                             \
   "v_add_u32 %[thr], %[ng], %[thr]\n\t"                                           \
   "v_add_u32 %[bw], %[ng], %[bw]\n"                                               \
-  ".Lq" TAG "_%=:\n\t"                                                             \
-  "s_ff1_i32_b64 %[a], %[live]\n\t"                                               \
-  "s_flbit_i32_b64 %[f], %[live]\n\t"
+  ".Lq" TAG "_%=:\n\t"
 
 // Even anti-diagonal 2(e0 + K): next (odd) range is lanes [a - 1, 63 - f].
 #define XD_EVEN(K, P, DIAG)                                                       \
   ".Le" K "_%=:\n\t"                                                               \
-  XD_CORE("e" K, DIAG, "E", "O", "SE", "wave_shr:1", P)                           \
+  XD_CORE("e" K, DIAG, "E", "O", "SE", "wave_shr:1", P, "")                       \
   "s_add_i32 %[tmp], %[a], %[f]\n\t"                                              \
   "s_sub_i32 %[tmp], 65, %[tmp]\n\t"                                              \
   "s_add_i32 %[a], %[a], -1\n\t"                                                  \
@@ -185,12 +193,12 @@ XD_FN Win make_win(const AsmView &v, vint off) {
   "s_bfm_b64 %[range], %[tmp], %[a]\n"
 #define XD_ODD(K, P, DIAG)                                                        \
   ".Lo" K "_%=:\n\t"                                                               \
-  XD_CORE("o" K, DIAG, "O", "E", "SO", "wave_shl:1", P)                           \
+  XD_CORE("o" K, DIAG, "O", "E", "SO", "wave_shl:1", P, "")                       \
   XD_ODD_RANGE
 #define XD_ODD_EDGE(K, P, DIAG)                                                   \
   ".Lo" K "_%=:\n\t"                                                               \
-  XD_CORE("o" K, DIAG, "O", "E", "SO", "wave_shl:1", P)                           \
-  "s_and_b64 vcc, %[live], %[edge]\n\t"                                           \
+  XD_CORE("o" K, DIAG, "O", "E", "SO", "wave_shl:1", P,                           \
+          "s_and_b64 %[live], vcc, %[edge]\n\t")                                   \
   "s_cbranch_scc1 .Lco" K "_%=\n\t"                                                \
   XD_ODD_RANGE
 #define XD_PAIR(K, P, DIAG) XD_EVEN(K, P, DIAG) XD_ODD(K, P, DIAG)
@@ -203,14 +211,15 @@ XD_FN Win make_win(const AsmView &v, vint off) {
 // them and the anti-diagonal are recorded; (i, j) and best itself are
 // derived after the loop.  The unit form applies the anti-diagonal's drift of
 // both thresholds together with the raise and rejoins the step after it.
-#define XD_IMP_UNIT(TAG, CUR, BP)                                                 \
+#define XD_IMP_UNIT(TAG, CUR, BP, TAIL)                                           \
   ".Li" TAG "_%=:\n\t"                                                             \
   "s_ff1_i32_b64 %[bs], vcc\n\t"                                                  \
   "s_add_i32 %[bpos], %[e0x2], " BP "\n\t"                                        \
   "v_add_u32 %[thr], %[ng1], %[thr]\n\t"                                          \
   "v_add_u32 %[bw], %[ng1], %[bw]\n\t"                                            \
+  TAIL                                                                            \
   "s_branch .Lq" TAG "_%=\n"
-#define XD_IMP_LOOP(TAG, CUR, BP)                                                 \
+#define XD_IMP_LOOP(TAG, CUR, BP, TAIL)                                           \
   ".Li" TAG "_%=:\n\t"                                                             \
   "s_mov_b32 %[inc], 1\n"                                                         \
   ".Lil" TAG "_%=:\n\t"                                                            \
@@ -225,13 +234,14 @@ XD_FN Win make_win(const AsmView &v, vint off) {
   "v_add_u32 %[thr], %[inc], %[thr]\n\t"                                          \
   "s_ff1_i32_b64 %[bs], vcc\n\t"                                                  \
   "s_add_i32 %[bpos], %[e0x2], " BP "\n\t"                                        \
+  TAIL                                                                            \
   "s_branch .Lr" TAG "_%=\n"
 
 // Out-of-line exits of the pair K: improvements, end of the extension, and
 // the recentre exit of the odd anti-diagonal (which resumes at pair K + 1).
 #define XD_STUBS(K, P, P1, PN, IMP)                                               \
-  IMP("e" K, "E", P)                                                              \
-  IMP("o" K, "O", P1)                                                             \
+  IMP("e" K, "E", P, "")                                                          \
+  IMP("o" K, "O", P1, "s_cmp_lg_u64 %[live], 0\n\t")                             \
   ".Lde" K "_%=:\n\t"                                                              \
   "s_mov_b32 %[pos], " P "\n\t"                                                   \
   "s_mov_b32 %[par], 0\n\t"                                                       \
