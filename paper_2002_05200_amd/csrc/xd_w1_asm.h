@@ -12,7 +12,9 @@
 //   v_addc_co_u32  cnt, 0, cnt, carry=range          cells of this range, per lane
 //   v_mov_b32_dpp  t, prev  wave_shr:1 / wave_shl:1  neighbour diagonal (d-1)
 //   v_bfe_u32      u, score_word, 2q, 2              match field
-//   v_add3_u32     cur, cur, base, u                 diagonal term (d-2)
+//   v_add3_u32     cur, cur, base, u                 diagonal term (d-2); a VOP2
+//                                                    add where base sits in the
+//                                                    field (+1/-1/-1)
 //   v_max3_i32     cur, cur, prev, t                 the recurrence, gap-free form
 //   v_cmp_le_i32   vcc, thr, cur                     X-drop test ...
 //   s_and_b64      vcc, vcc, range                   ... within the computed range
@@ -99,6 +101,12 @@ XD_FN Win make_win(const AsmView &v, vint off) {
   "v_mad_u32_u24 %[" CUR "], %[u], %[delta], %[" CUR "]\n\t" \
   "v_add_u32 %[" CUR "], %[base], %[" CUR "]\n\t"
 
+// base + delta * match held in the field itself (+1/-1/-1: 1 or 3), so the
+// diagonal term is one VOP2 add after the extract.
+#define XD_DIAG_FOLD(CUR, SW, P)                        \
+  "v_bfe_u32 %[u], %[" SW "], " P ", 2\n\t"             \
+  "v_add_u32 %[" CUR "], %[u], %[" CUR "]\n\t"
+
 // Score word from an XOR of two windows: match bits z = ~(x | x >> 1) & 0x5555..;
 // narrow form: delta in every matching 2-bit field; wide form: z itself.
 #define XD_SW_NARROW(S, X)                                          \
@@ -111,6 +119,11 @@ XD_FN Win make_win(const AsmView &v, vint off) {
 #define XD_SW_D2(S, X)                                              \
   "v_lshlrev_b32 %[u], 1, %[" X "]\n\t"                             \
   "v_bitop3_b32 %[" S "], %[u], %[pat], %[" X "] bitop3:4\n\t"
+// delta = 2 and base = 1: the high bit of each field as in XD_SW_D2, the low
+// bit set, ~(pat & (x | x << 1)), so a field holds base + delta * match.
+#define XD_SW_D2B(S, X)                                             \
+  "v_lshlrev_b32 %[u], 1, %[" X "]\n\t"                             \
+  "v_bitop3_b32 %[" S "], %[u], %[pat], %[" X "] bitop3:0x37\n\t"
 #define XD_SW_WIDE(S, X)                                            \
   "v_lshrrev_b32 %[u], 1, %[" X "]\n\t"                             \
   "v_bitop3_b32 %[" S "], %[u], %[k55], %[" X "] bitop3:4\n\t"
@@ -285,7 +298,7 @@ enum : int { kStepLeave = 3 };
 // them (its edge checks come every fourth anti-diagonal).
 constexpr uint64_t kAsmEntryLanes = ((1ull << 59) - 1ull) << 2;
 
-template <bool NARROW, bool UNIT, bool FWD, bool D2>
+template <bool NARROW, bool UNIT, bool FWD, bool D2, bool FOLD = false>
 XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &jv,
                      const AsmView &av_a, const AsmView &av_b, const Params &P,
                      int32_t &words_e0) {
@@ -327,6 +340,10 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
     if (!FWD) { xe = bit_reverse(xe); xo = bit_reverse(xo); }
     bd.SE[0] = score_word<NARROW>(xe, P.pat);
     bd.SO[0] = score_word<NARROW>(xo, P.pat);
+    if (FOLD) {   // base = 1 in every field (no carries: fields hold 0 or 2)
+      bd.SE[0] = bd.SE[0] | splat(0x55555555);
+      bd.SO[0] = bd.SO[0] | splat(0x55555555);
+    }
   }
   // The 32 anti-diagonals of a block are unrolled, so field offsets and
   // anti-diagonal numbers are immediates; entry jumps through a table of
@@ -391,7 +408,10 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
       : "vcc", "scc", "memory", "s40", "s41", "s42")
 #define XD_REV_NONE ""
 #define XD_REV_BOTH "v_bfrev_b32 %[x0], %[x0]\n\tv_bfrev_b32 %[x1], %[x1]\n\t"
-  if (D2) {   // match = 1 and match - mismatch = 2 (e.g. +1/-1/-1)
+  if (FOLD) {   // +1/-1/-1: base 1 folded into the fields
+    if (FWD) { XD_ASM_BODY(XD_DIAG_FOLD, XD_IMP_UNIT, XD_SW_D2B, XD_SHIFT_FWD, XD_REV_NONE, XD_WORDS_FWD); }
+    else { XD_ASM_BODY(XD_DIAG_FOLD, XD_IMP_UNIT, XD_SW_D2B, XD_SHIFT_BWD, XD_REV_BOTH, XD_WORDS_BWD); }
+  } else if (D2) {   // match = 1 and match - mismatch = 2
     if (FWD) { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_UNIT, XD_SW_D2, XD_SHIFT_FWD, XD_REV_NONE, XD_WORDS_FWD); }
     else { XD_ASM_BODY(XD_DIAG_NARROW, XD_IMP_UNIT, XD_SW_D2, XD_SHIFT_BWD, XD_REV_BOTH, XD_WORDS_BWD); }
   } else if (FWD) {
@@ -430,7 +450,7 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
   st.width = __builtin_popcountll(st.range);
   // the score words in SE/SO belong to block e0_now unless the loop left at a
   // block boundary before rebuilding them
-  words_e0 = (status == kStepLeave) ? -1 : e0_now;
+  words_e0 = (status == kStepLeave || FOLD) ? -1 : e0_now;   // folded words are the loop's own
   if (status == 2) {   // pending even range [a, 64 - f] needs the window moved
     st.lo = a;
     st.hi = 64 - f;
@@ -459,6 +479,11 @@ struct RunAsm {
       const AsmView av_b = make_asm_view(P.B, P.b_words, jv.b_start, reach);
       // the loop leaves score words of block words_e0 built for this window base
       words_h = st.h;
+      if (NARROW && P.unit_match && P.delta == 2 && P.base == 1) {
+        return jv.dir > 0
+                   ? run_w1_asm<NARROW, true, true, true, true>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0)
+                   : run_w1_asm<NARROW, true, false, true, true>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0);
+      }
       if (NARROW && P.unit_match && P.delta == 2) {
         return jv.dir > 0
                    ? run_w1_asm<NARROW, true, true, true>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0)
