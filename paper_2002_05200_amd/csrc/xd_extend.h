@@ -314,6 +314,13 @@ XD_FN uint32_t lane_sum(vint v) {
   return (uint32_t)readlane(v, 0);
 }
 
+// Maximum over the 64 lanes (the same exchange).
+XD_FN int32_t lane_max(vint v) {
+#pragma unroll
+  for (int sh = 1; sh < kWave; sh <<= 1) v = vmax(v, from_lane_offset(v, sh, INT32_MIN));
+  return readlane(v, 0);
+}
+
 template <bool NARROW, class Runner = RunC>
 XD_FN JobOut extend_job_w1(const Job &job, const Params &P, int32_t j) {
   JobOut out;

@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_scatter(const int32_t *__restric
 // (two resident wavefronts per SIMD instead of one), so a second job hides
 // the first one's latencies.
 template <int C, bool NARROW>
-__global__ __launch_bounds__(kBlock, C == 1 ? 8 : (C >= 32 && NARROW ? 2 : 1)) void k_extend(
+__global__ __launch_bounds__(kBlock, C == 1 ? 8 : C == 4 ? 8 : C == 8 ? 5 : (C >= 32 && NARROW ? 2 : 1)) void k_extend(
     const Job *__restrict__ jobs, TierQueue q, int32_t *head, JobOut *__restrict__ outs,
     unsigned long long *stats, Params P) {
   const int wave = uniform((int32_t)(threadIdx.x >> 6));
@@ -526,7 +526,7 @@ hipError_t launch_tiers(xd_ctx *c, const Bufs &B, hipStream_t s, bool persistent
   // waves per CU: each tier's resident limit from its register footprint
   // (4 SIMDs x waves per SIMD: 7, 5, 7, 5, 3, 2 for C = 1 .. 32), rounded up
   // for the narrow tiers, whose queues are long
-  const int wpc[kTiers] = {32, 32, 28, 20, 12, 8};
+  const int wpc[kTiers] = {32, 32, 32, 20, 12, 8};
   auto w = [&](int t) { return waves_per_cu > 0 ? waves_per_cu : wpc[t]; };
   hipError_t e;
   auto mark = [&](int i) { return prof ? hipEventRecord(c->ev[i], s) : hipSuccess; };

@@ -223,14 +223,16 @@ XD_FN Win make_win(const AsmView &v, vint off) {
 // lanes above bw are exactly the lanes holding the new best.  The first of
 // them and the anti-diagonal are recorded; (i, j) and best itself are
 // derived after the loop.  The unit form applies the anti-diagonal's drift of
-// both thresholds together with the raise and rejoins the step after it.
+// both thresholds together with the raise and rejoins the step after it; it
+// records the anti-diagonal in a per-lane register instead (bl: its offset in
+// the block for the lanes that raised best, turned into -2 - d at the block's
+// end), which leaves the scalar unit and SCC alone, and the lanes holding the
+// largest d give the first best cell after the loop.
 #define XD_IMP_UNIT(TAG, CUR, BP, TAIL)                                           \
   ".Li" TAG "_%=:\n\t"                                                             \
-  "s_ff1_i32_b64 %[bs], vcc\n\t"                                                  \
-  "s_add_i32 %[bpos], %[e0x2], " BP "\n\t"                                        \
+  "v_cndmask_b32_e64 %[bl], %[bl], " BP ", vcc\n\t"                                \
   "v_add_u32 %[thr], %[ng1], %[thr]\n\t"                                          \
   "v_add_u32 %[bw], %[ng1], %[bw]\n\t"                                            \
-  TAIL                                                                            \
   "s_branch .Lq" TAG "_%=\n"
 #define XD_IMP_LOOP(TAG, CUR, BP, TAIL)                                           \
   ".Li" TAG "_%=:\n\t"                                                             \
@@ -320,6 +322,7 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
   int32_t pos = 2 * (st.e - e0);
   int32_t a = 0, f = 0, tmp = 0, inc = 0;
   int32_t bs = 0, bpos = -1;   // lane and anti-diagonal of the last improvement
+  vint bl = splat(-1);          // the same, per lane, in the unit form (none: -1)
   uint64_t live = 0;
   const uint64_t edge = 0xE000000000000003ull;   // lanes 0, 1, 61, 62, 63
   const int32_t k55 = 0x55555555;
@@ -366,6 +369,10 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
       ".Ltab_%=:\n\t"                                                                  \
       XD_ALL_TABLE                                                                    \
       XD_ALL_PAIRS(DIAG)                                                              \
+      "v_cmp_le_i32 vcc, 0, %[bl]\n\t"                                                \
+      "s_sub_i32 %[tmp], -2, %[e0x2]\n\t"                                             \
+      "v_sub_u32_e32 %[tv], %[tmp], %[bl]\n\t"                                        \
+      "v_cndmask_b32_e32 %[bl], %[bl], %[tv], vcc\n\t"                                \
       "s_add_i32 %[e0x2], %[e0x2], 32\n\t"                                            \
       "s_cmp_gt_i32 %[e0x2], %[lim2]\n\t"                                             \
       "s_cbranch_scc1 .Lleave_%=\n\t"                                                  \
@@ -395,7 +402,7 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
         [lo2] "+v"(w2.lo.x), [hi2] "+v"(w2.hi.x), [nx2] "+v"(w2.nx.x), [idx2] "+v"(w2.idx.x), \
         [u] "=&v"(u), [t] "=&v"(t), [tv] "=&v"(tv), [x0] "=&v"(x0), [x1] "=&v"(x1),   \
         [x2] "=&v"(x2), [p0] "=&v"(p0), [p2] "=&v"(p2),               \
-        [thr] "+v"(thrv), [bs] "+s"(bs), [bpos] "+s"(bpos),                         \
+        [thr] "+v"(thrv), [bl] "+v"(bl.x), [bs] "+s"(bs), [bpos] "+s"(bpos),       \
         [par] "+s"(par), [pos] "+s"(pos), [e0x2] "+s"(e0x2), [range] "+s"(st.range),  \
         [live] "+s"(live), [a] "+s"(a), [f] "+s"(f), [tmp] "+s"(tmp), [inc] "+s"(inc), \
         [status] "+s"(status)                                                         \
@@ -440,6 +447,11 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
   st.bw = uniform(bw);
   st.thr = uniform(thrv);
   st.best = st.bw - d_now * P.neg_gap;
+  if (UNIT) {   // records: block offsets of block e0x2 (>= 0), or -2 - d
+    const vint dl = select(bl >= 0, bl + splat(e0x2), splat(-2) - bl);
+    bpos = lane_max(dl);
+    if (bpos >= 0) bs = __builtin_ctzll(ballot(dl == bpos));
+  }
   if (bpos >= 0) {   // best cell: i = s + ceil(d/2) + h, j = d - i, d = bpos
     st.bi = bs + ((bpos + 1) >> 1) + st.h;
     st.bj = bpos - st.bi;
