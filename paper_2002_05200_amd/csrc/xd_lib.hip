@@ -164,10 +164,11 @@ __global__ __launch_bounds__(kPlanBlock) void k_scatter(const int32_t *__restric
 
 // One job per wavefront.  Plain: wave w of the grid takes work item w.
 // Persistent (head != nullptr): waves pop work items until none is left.
-// The one-register tier is held to eight resident wavefronts per SIMD (its
-// scalar registers were the limit at seven; the compiler keeps the excess in
-// VGPR lanes outside the assembly loop), which hides more of each
-// anti-diagonal's dependent chain.  The 32-register tier is held to 256 VGPRs
+// The one- and four-register tiers are held to eight resident wavefronts per
+// SIMD and the eight-register tier to five (registers were the limit at
+// seven, seven and four; the compiler keeps the excess scalars in VGPR lanes
+// outside the assembly loops), which hides more of each anti-diagonal's
+// dependent chain.  The 32-register tier is held to 256 VGPRs
 // (two resident wavefronts per SIMD instead of one), so a second job hides
 // the first one's latencies.
 template <int C, bool NARROW>
