@@ -634,7 +634,6 @@ XD_FN bool wrestore(WBand<C> &bd, WScalars &st, const Params &P, int32_t j) {
   if (off < 0) return false;
   const int32_t *sv = P.save_pool + off;
   const int32_t cs = uniform(sv[kSvC]);
-  constexpr int S = kWave * C;
   if (cs >= C) return false;
   const int32_t ss = kWave * cs;
   const int32_t lo0 = uniform(sv[kSvLo]), hi0 = uniform(sv[kSvHi]);
