@@ -16,6 +16,7 @@
 //                                  each register, the lane crossing between
 //                                  the registers taken from the other one
 //   v_bfe, v_add3 x2               diagonal term (d-2) from the score field
+//                                  (v_add for +1/-1/-1: base 1 in the field)
 //   v_max3 x2                      the recurrence, gap-free form
 //   v_cmp, s_and, v_cndmask x2     X-drop test within the range, -inf
 //   s_cmp + branches               a register without survivors: leave
@@ -49,9 +50,16 @@ namespace xd {
   "v_mov_b32_dpp %[t0], %[E0] wave_rol:1 row_mask:0xf bank_mask:0xf\n\t"         \
   "v_cndmask_b32_e64 %[t0], %[t0], %[t1], %[l63]\n\t"
 
-#define W2_DIAG(CUR, SW, P)                                                       \
+// The diagonal term; W2_DIAG_SEL picks the form where the loop is expanded:
+// W2_DIAG_ADD3 adds base, W2_DIAG_FOLD takes words whose fields already hold
+// base + delta * match (+1/-1/-1).
+#define W2_DIAG_ADD3(CUR, SW, P)                                                  \
   "v_bfe_u32 %[u], %[" SW "], " P ", 2\n\t"                                        \
   "v_add3_u32 %[" CUR "], %[" CUR "], %[base], %[u]\n\t"
+#define W2_DIAG_FOLD(CUR, SW, P)                                                  \
+  "v_bfe_u32 %[u], %[" SW "], " P ", 2\n\t"                                        \
+  "v_add_u32 %[" CUR "], %[u], %[" CUR "]\n\t"
+#define W2_DIAG(CUR, SW, P) W2_DIAG_SEL(CUR, SW, P)
 
 // Cells, recurrence, pruning and the improvement test of anti-diagonal
 // 2(e0 + K) + PAR, registers C0 / C1 (d-2 in, d out) from P0 / P1 (d-1).
@@ -170,10 +178,10 @@ namespace xd {
   "v_xor_b32 %[x0], %[x0], %[x2]\n\t"                                             \
   "v_xor_b32 %[x1], %[x1], %[x2]\n\t"                                             \
   REV                                                                             \
-  XD_SW_D2(SE, "x0")                                                              \
-  XD_SW_D2(SO, "x1")
+  W2_SW_SEL(SE, "x0")                                                             \
+  W2_SW_SEL(SO, "x1")
 
-template <bool NARROW, bool FWD>
+template <bool NARROW, bool FWD, bool FOLD>
 XD_FN int w2_loop(WBand<2> &bd, WScalars &st, const JobView &jv, const Params &P, uint64_t &m0,
                   uint64_t &m1) {
   // scalar state in SGPRs (the compiler cannot always prove these uniform)
@@ -206,6 +214,12 @@ XD_FN int w2_loop(WBand<2> &bd, WScalars &st, const JobView &jv, const Params &P
     }
     bd.SE[0] = score_word<true>(xe0, P.pat); bd.SO[0] = score_word<true>(xo0, P.pat);
     bd.SE[1] = score_word<true>(xe1, P.pat); bd.SO[1] = score_word<true>(xo1, P.pat);
+    if (FOLD) {   // base = 1 in every field (fields hold 0 or 2: no carries)
+      for (int r = 0; r < 2; ++r) {
+        bd.SE[r] = bd.SE[r] | splat(0x55555555);
+        bd.SO[r] = bd.SO[r] | splat(0x55555555);
+      }
+    }
   }
   // the window stays inside the matrix for blocks ending at or before e_lim
   int32_t e_lim = m - (2 * kWave - 1) - h;
@@ -288,10 +302,26 @@ XD_FN int w2_loop(WBand<2> &bd, WScalars &st, const JobView &jv, const Params &P
         [pat] "s"(P.pat), [hi_a] "s"(hi_a), [hi_b] "s"(hi_b), [base_a] "s"(base_a),    \
         [base_b] "s"(base_b)                                                          \
       : "vcc", "scc", "memory", "s40", "s41", "s42")
-  if (FWD) {
-    W2_ASM_BODY(XD_SHIFT_FWD, "");
+  if (FOLD) {   // the loop's own words: the C steps rebuild theirs afterwards
+#define W2_DIAG_SEL W2_DIAG_FOLD
+#define W2_SW_SEL XD_SW_D2B
+    if (FWD) {
+      W2_ASM_BODY(XD_SHIFT_FWD, "");
+    } else {
+      W2_ASM_BODY(XD_SHIFT_BWD, "v_bfrev_b32 %[x0], %[x0]\n\tv_bfrev_b32 %[x1], %[x1]\n\t");
+    }
+#undef W2_DIAG_SEL
+#undef W2_SW_SEL
   } else {
-    W2_ASM_BODY(XD_SHIFT_BWD, "v_bfrev_b32 %[x0], %[x0]\n\tv_bfrev_b32 %[x1], %[x1]\n\t");
+#define W2_DIAG_SEL W2_DIAG_ADD3
+#define W2_SW_SEL XD_SW_D2
+    if (FWD) {
+      W2_ASM_BODY(XD_SHIFT_FWD, "");
+    } else {
+      W2_ASM_BODY(XD_SHIFT_BWD, "v_bfrev_b32 %[x0], %[x0]\n\tv_bfrev_b32 %[x1], %[x1]\n\t");
+    }
+#undef W2_DIAG_SEL
+#undef W2_SW_SEL
   }
 #undef W2_ASM_BODY
   // the anti-diagonal the loop stopped at; W-form thresholds give best there

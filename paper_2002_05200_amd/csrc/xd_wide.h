@@ -677,7 +677,7 @@ enum : int { kW2Step = 1, kW2Recenter = 2, kW2Leave = 3 };
 //                which reaches slots {0, 1} or {125, 126, 127};
 //   kW2Leave     st.d starts a block in which the window would leave the
 //                matrix; st.lo .. st.hi its range.
-template <bool NARROW, bool FWD>
+template <bool NARROW, bool FWD, bool FOLD>
 XD_FN int w2_loop(WBand<2> &bd, WScalars &st, const JobView &jv, const Params &P, uint64_t &m0,
                   uint64_t &m1);
 
@@ -697,8 +697,11 @@ XD_FN int w2_fast(WBand<2> &bd, WScalars &st, const JobView &jv, const Params &P
       continue;                          // the window moved: test it again
     }
     uint64_t m0 = 0, m1 = 0;
-    const int rc = jv.dir > 0 ? w2_loop<NARROW, true>(bd, st, jv, P, m0, m1)
-                              : w2_loop<NARROW, false>(bd, st, jv, P, m0, m1);
+    const bool fold = P.base == 1;   // +1/-1/-1: base in the score fields
+    const int rc = jv.dir > 0 ? (fold ? w2_loop<NARROW, true, true>(bd, st, jv, P, m0, m1)
+                                      : w2_loop<NARROW, true, false>(bd, st, jv, P, m0, m1))
+                              : (fold ? w2_loop<NARROW, false, true>(bd, st, jv, P, m0, m1)
+                                      : w2_loop<NARROW, false, false>(bd, st, jv, P, m0, m1));
     st.span_lo[0] = st.span_lo[1] = 0;
     st.span_hi[0] = st.span_hi[1] = 1;
     st.w_lo = 1;                         // score words to be rebuilt by the C steps
