@@ -37,6 +37,7 @@ compare and two branches.
 Run from the repository root: python paper_2002_05200_amd/csrc/gen_wchain.py
 """
 import os
+import re
 
 CS = (2, 4, 8, 16, 32)
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -545,17 +546,18 @@ def _loop_outofline(C, par):
     return out
 
 
-def loop_function(C):
-    """WLoop<C>::run: anti-diagonals of the current score-word block (score
-    words built for every register), with match = 1 and narrow score fields,
-    each range clipped to the matrix.  Returns why it stopped: 0 the block
-    ended, 2 anti-diagonal s.d has been computed but its survivors are not
-    in the span's edge registers (the caller finishes it), 3 the next range
-    needs a recentre, 4 the next range lies outside the matrix (the
-    extension has ended)."""
+def loop_function(C, fold=False):
+    """WLoop<C, FOLD>::run: anti-diagonals of the current score-word block
+    (score words built for every register), with match = 1 and narrow score
+    fields, each range clipped to the matrix.  Returns why it stopped: 0 the
+    block ended, 2 anti-diagonal s.d has been computed but its survivors are
+    not in the span's edge registers (the caller finishes it), 3 the next
+    range needs a recentre, 4 the next range lies outside the matrix (the
+    extension has ended).  FOLD: the score fields hold base + delta * match
+    themselves (+1/-1/-1), so the diagonal term is one VOP2 add."""
     lines = [
         "template <>",
-        f"XD_MEMBER int32_t WLoop<{C}>::run(vint *E, vint *O, const vint *SE, const vint *SO,",
+        f"XD_MEMBER int32_t WLoop<{C}, {'true' if fold else 'false'}>::run(vint *E, vint *O, const vint *SE, const vint *SO,",
         "                                   WLoopState &s) {",
         "  int32_t d = s.d, lo = s.lo, hi = s.hi, bw = s.bw, thr = s.thr, cells = s.cells;",
         "  int32_t bs = s.bs, bpos = s.bpos, spl0 = s.spl0, sph0 = s.sph0, spl1 = s.spl1, sph1 = s.sph1;",
@@ -576,6 +578,9 @@ def loop_function(C):
     ]
     body += _loop_outofline(C, 0) + _loop_outofline(C, 1)
     body += ['".Lend_%=:\\n"']
+    if fold:
+        body = [re.sub(r"v_add3_u32 %\[(\w+)\], %\[\1\], %\[base\], %\[u\]",
+                       r"v_add_u32 %[\1], %[u], %[\1]", x) for x in body]
     lines += ["      " + x for x in body]
     outs = ", ".join([f'[e{r}] "+v"(E[{r}].x)' for r in range(C)] +
                      [f'[o{r}] "+v"(O[{r}].x)' for r in range(C)])
@@ -629,7 +634,8 @@ def render() -> str:
         "// afterwards and the register past it set to -inf; its vmx may count",
         "// lanes past the range (callers search the range itself).",
         "//",
-        "// WLoop<C>::run runs whole anti-diagonals of one score-word block:",
+        "// WLoop<C, FOLD>::run runs whole anti-diagonals of one score-word block",
+        "// (FOLD: the fields hold base + delta * match, +1/-1/-1):",
         "// span clearing, the chain, survivors, the improvement of best (match =",
         "// 1), cells and the next range clipped to the matrix, leaving when the",
         "// block ends, the survivors are not in the span's edge registers, the",
@@ -674,7 +680,7 @@ def render() -> str:
         "  int32_t mx;",
         "};",
         "",
-        "template <int C>",
+        "template <int C, bool FOLD>",
         "struct WLoop {",
         "  XD_MEMBER static int32_t run(vint *E, vint *O, const vint *SE, const vint *SO,",
         "                              WLoopState &s);",
@@ -688,6 +694,7 @@ def render() -> str:
         out += first_function(C)
         if C >= 4:
             out += loop_function(C)
+            out += loop_function(C, True)
     out += ["}  // namespace xd", ""]
     return "\n".join(out)
 

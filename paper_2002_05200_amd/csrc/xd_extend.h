@@ -77,18 +77,18 @@ XD_FN vint window16(const SeqView &v, vint off) {
 // 2-bit field holds delta = match - mismatch where the bases agree, else 0.
 // Wide form (delta > 3): the field's low bit flags a match.
 template <bool NARROW>
-XD_FN vint score_word(vint x, int32_t pat) {
+XD_FN vint score_word(vint x, int32_t pat, int32_t fold) {
   vint nz = (x | shr_u(x, 1)) & 0x55555555;   // low bit of a field: mismatch
   vint z = nz ^ splat(0x55555555);            // low bit of a field: match
-  if (NARROW) return (z | (z << 1)) & pat;    // pat = delta in every field
+  if (NARROW) return ((z | (z << 1)) & pat) | splat(fold);   // pat = delta in every field
   return z;
 }
 
 // Diagonal term of one cell: W_{d-2} + s(a_i, b_j) + 2|gap|.
 template <bool NARROW>
 XD_FN vint diag_term(vint w2, vint sw, int pos, const Params &P) {
-  if (NARROW) return w2 + bfe_u(sw, pos, 2) + P.base;            // v_add3_u32
-  return mad24(bfe_u(sw, pos, 1), P.delta, w2) + P.base;
+  if (NARROW) return w2 + bfe_u(sw, pos, 2) + P.dbase;           // v_add3_u32
+  return mad24(bfe_u(sw, pos, 1), P.delta, w2) + P.dbase;
 }
 
 template <int C>
@@ -135,8 +135,8 @@ XD_FN void build_words(Band<C> &bd, int32_t e0, int32_t h, const JobView &jv, co
       xe = bit_reverse(xe);
       xo = bit_reverse(xo);
     }
-    bd.SE[r] = score_word<NARROW>(xe, P.pat);
-    bd.SO[r] = score_word<NARROW>(xo, P.pat);
+    bd.SE[r] = score_word<NARROW>(xe, P.pat, P.fold);
+    bd.SO[r] = score_word<NARROW>(xo, P.pat, P.fold);
   }
 }
 

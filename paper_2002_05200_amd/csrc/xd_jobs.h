@@ -43,6 +43,8 @@ struct Params {
   int32_t base;      // mismatch - 2 gap
   int32_t delta;     // match - mismatch (>= 0)
   int32_t pat;       // delta replicated into every 2-bit field (narrow form)
+  int32_t fold;      // +1/-1/-1: base (1) in every field as well (0x55555555), else 0
+  int32_t dbase;     // what the diagonal term adds to the field: base, or 0 when folded
   int32_t impl;      // 0: hand-scheduled loops where available, 1: C loops only
   int32_t unit_match;  // match == 1: best grows by exactly 1 when it grows
   // Escalation saves: a job whose band outgrows its window stores its state

@@ -211,7 +211,14 @@ __global__ __launch_bounds__(kBlock, C == 1 ? 8 : C == 4 ? 8 : C == 8 ? 5 : (C >
         o = extend_job_wide<2, NARROW, false>(job, P, j, stage + wave * kStage);
       }
     } else if (NARROW && P.impl == 0) {
-      o = extend_job_wide<C, NARROW, true>(job, P, j, stage + wave * kStage);
+      // +1/-1/-1 (base in the score fields) runs its own instance, whose
+      // chain adds no base (one VOP2 add per register); the plain instance is
+      // exact on folded words too (it adds dbase = 0), and the 32-register
+      // tier keeps to it: a second instance there costs more register spills
+      if (C <= 16 && P.fold)
+        o = extend_job_wide<C, NARROW, true, C <= 16>(job, P, j, stage + wave * kStage);
+      else
+        o = extend_job_wide<C, NARROW, true, false>(job, P, j, stage + wave * kStage);
     } else {
       o = extend_job_wide<C, NARROW, false>(job, P, j, stage + wave * kStage);
     }
@@ -579,6 +586,9 @@ xd_status enqueue(xd_ctx *c, const Bufs &B, hipStream_t s, const Launch &L, bool
   P.base = sc.mismatch - 2 * sc.gap;
   P.delta = sc.match - sc.mismatch;
   P.pat = (int32_t)((uint32_t)P.delta * 0x55555555u);
+  // +1/-1/-1: base + delta * match (1 or 3) fits the 2-bit field itself
+  P.fold = (sc.match == 1 && P.delta == 2 && P.base == 1) ? 0x55555555 : 0;
+  P.dbase = P.fold ? 0 : P.base;
   P.impl = o.impl;
   P.unit_match = sc.match == 1;
   P.save_pool = B.save_pool;

@@ -150,7 +150,7 @@ XD_FN bool mw_step(WBand<C> &bd, MwScalars &st, MwShared<NW, C> &sh, int w, int 
           urlo == urhi ? (lo_mask & hi_mask) : (PAR == 0 ? lo_mask : hi_mask);
       const uint64_t ml = PAR == 0 ? hi_mask : lo_mask;
       uint64_t lf, ll;
-      WChainRun<C, PAR>::run(cur, prv, sw, uniform(pos), uniform(thr), uniform(P.base), urlo,
+      WChainRun<C, PAR>::run(cur, prv, sw, uniform(pos), uniform(thr), uniform(P.dbase), urlo,
                              urhi, carry, vmx, mf, ml, lf, ll);
       live_lo = PAR == 0 ? lf : ll;
       live_hi = PAR == 0 ? ll : lf;

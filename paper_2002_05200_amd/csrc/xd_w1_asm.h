@@ -341,12 +341,9 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
     vint xe = (FWD ? xk : xd) ^ xb;
     vint xo = (FWD ? xd : xk) ^ xb;
     if (!FWD) { xe = bit_reverse(xe); xo = bit_reverse(xo); }
-    bd.SE[0] = score_word<NARROW>(xe, P.pat);
-    bd.SO[0] = score_word<NARROW>(xo, P.pat);
-    if (FOLD) {   // base = 1 in every field (no carries: fields hold 0 or 2)
-      bd.SE[0] = bd.SE[0] | splat(0x55555555);
-      bd.SO[0] = bd.SO[0] | splat(0x55555555);
-    }
+    const int32_t fold = FOLD ? 0x55555555 : 0;   // P.fold, known here
+    bd.SE[0] = score_word<NARROW>(xe, P.pat, fold);
+    bd.SO[0] = score_word<NARROW>(xo, P.pat, fold);
   }
   // The 32 anti-diagonals of a block are unrolled, so field offsets and
   // anti-diagonal numbers are immediates; entry jumps through a table of
@@ -407,7 +404,7 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
         [live] "+s"(live), [a] "+s"(a), [f] "+s"(f), [tmp] "+s"(tmp), [inc] "+s"(inc), \
         [status] "+s"(status)                                                         \
       : [sh0] "v"(w0.sh.x), [shd] "v"(shd.x), [m30] "s"(m30), [sh2] "v"(w2.sh.x),     \
-        [base] "s"(P.base),                                                           \
+        [base] "s"(P.dbase),                                                           \
         [delta] "s"(P.delta), [ng] "s"(P.neg_gap), [ng1] "s"(ng1), [lim2] "s"(lim2),   \
         [edge] "s"(edge),                                                             \
         [k55] "s"(k55), [pat] "s"(P.pat), [hi_a] "s"(hi_a), [hi_b] "s"(hi_b),          \
@@ -462,7 +459,7 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
   st.width = __builtin_popcountll(st.range);
   // the score words in SE/SO belong to block e0_now unless the loop left at a
   // block boundary before rebuilding them
-  words_e0 = (status == kStepLeave || FOLD) ? -1 : e0_now;   // folded words are the loop's own
+  words_e0 = (status == kStepLeave) ? -1 : e0_now;
   if (status == 2) {   // pending even range [a, 64 - f] needs the window moved
     st.lo = a;
     st.hi = 64 - f;
@@ -491,7 +488,7 @@ struct RunAsm {
       const AsmView av_b = make_asm_view(P.B, P.b_words, jv.b_start, reach);
       // the loop leaves score words of block words_e0 built for this window base
       words_h = st.h;
-      if (NARROW && P.unit_match && P.delta == 2 && P.base == 1) {
+      if (NARROW && P.fold) {   // +1/-1/-1
         return jv.dir > 0
                    ? run_w1_asm<NARROW, true, true, true, true>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0)
                    : run_w1_asm<NARROW, true, false, true, true>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0);

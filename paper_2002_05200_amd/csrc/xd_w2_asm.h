@@ -212,14 +212,9 @@ XD_FN int w2_loop(WBand<2> &bd, WScalars &st, const JobView &jv, const Params &P
       xe0 = bit_reverse(xe0); xo0 = bit_reverse(xo0);
       xe1 = bit_reverse(xe1); xo1 = bit_reverse(xo1);
     }
-    bd.SE[0] = score_word<true>(xe0, P.pat); bd.SO[0] = score_word<true>(xo0, P.pat);
-    bd.SE[1] = score_word<true>(xe1, P.pat); bd.SO[1] = score_word<true>(xo1, P.pat);
-    if (FOLD) {   // base = 1 in every field (fields hold 0 or 2: no carries)
-      for (int r = 0; r < 2; ++r) {
-        bd.SE[r] = bd.SE[r] | splat(0x55555555);
-        bd.SO[r] = bd.SO[r] | splat(0x55555555);
-      }
-    }
+    const int32_t fold = FOLD ? 0x55555555 : 0;   // P.fold, known here
+    bd.SE[0] = score_word<true>(xe0, P.pat, fold); bd.SO[0] = score_word<true>(xo0, P.pat, fold);
+    bd.SE[1] = score_word<true>(xe1, P.pat, fold); bd.SO[1] = score_word<true>(xo1, P.pat, fold);
   }
   // the window stays inside the matrix for blocks ending at or before e_lim
   int32_t e_lim = m - (2 * kWave - 1) - h;
@@ -297,12 +292,12 @@ XD_FN int w2_loop(WBand<2> &bd, WScalars &st, const JobView &jv, const Params &P
         [v0] "+s"(v0), [v1] "+s"(v1), [a] "+s"(a), [f] "+s"(f), [tq] "+s"(tq),         \
         [status] "+s"(status)                                                         \
       : [sh0] "v"(w0.sh.x), [sh1] "v"(w1.sh.x), [sh2] "v"(w2.sh.x), [sh3] "v"(w3.sh.x), \
-        [sh4] "v"(w4.sh.x), [sh5] "v"(w5.sh.x), [base] "s"(P.base), [ng] "s"(P.neg_gap), \
+        [sh4] "v"(w4.sh.x), [sh5] "v"(w5.sh.x), [base] "s"(P.dbase), [ng] "s"(P.neg_gap), \
         [ng1] "s"(ng1), [lim2] "s"(lim2), [e1] "s"(e1), [l0] "s"(l0), [l63] "s"(l63),  \
         [pat] "s"(P.pat), [hi_a] "s"(hi_a), [hi_b] "s"(hi_b), [base_a] "s"(base_a),    \
         [base_b] "s"(base_b)                                                          \
       : "vcc", "scc", "memory", "s40", "s41", "s42")
-  if (FOLD) {   // the loop's own words: the C steps rebuild theirs afterwards
+  if (FOLD) {   // +1/-1/-1: base in the score fields
 #define W2_DIAG_SEL W2_DIAG_FOLD
 #define W2_SW_SEL XD_SW_D2B
     if (FWD) {

@@ -125,8 +125,8 @@ XD_FN void wbuild_dir(WBand<C> &bd, int32_t h, int32_t e0, int32_t base, uint32_
       xe = bit_reverse(xe);
       xo = bit_reverse(xo);
     }
-    bd.SE[r] = score_word<NARROW>(xe, P.pat);
-    bd.SO[r] = score_word<NARROW>(xo, P.pat);
+    bd.SE[r] = score_word<NARROW>(xe, P.pat, P.fold);
+    bd.SO[r] = score_word<NARROW>(xo, P.pat, P.fold);
   }
 }
 
@@ -268,7 +268,7 @@ XD_FN bool wstep(WBand<C> &bd, WScalars &st, int q, const JobView &jv, const Par
     const uint64_t mf = rlo == rhi ? (lo_mask & hi_mask) : (PAR == 0 ? lo_mask : hi_mask);
     const uint64_t ml = PAR == 0 ? hi_mask : lo_mask;
     uint64_t lf, ll;
-    WChain<C, PAR>::run(cur, prv, sw, uniform(pos), uniform(thr), uniform(P.base),
+    WChain<C, PAR>::run(cur, prv, sw, uniform(pos), uniform(thr), uniform(P.dbase),
                         uniform(rlo), uniform(rhi), carry, vmx, mf, ml, lf, ll);
     live_lo = PAR == 0 ? lf : ll;
     live_hi = PAR == 0 ? ll : lf;
@@ -697,7 +697,7 @@ XD_FN int w2_fast(WBand<2> &bd, WScalars &st, const JobView &jv, const Params &P
       continue;                          // the window moved: test it again
     }
     uint64_t m0 = 0, m1 = 0;
-    const bool fold = P.base == 1;   // +1/-1/-1: base in the score fields
+    const bool fold = P.base == 1;   // = P.fold here (match 1, delta 2 checked above)
     const int rc = jv.dir > 0 ? (fold ? w2_loop<NARROW, true, true>(bd, st, jv, P, m0, m1)
                                       : w2_loop<NARROW, true, false>(bd, st, jv, P, m0, m1))
                               : (fold ? w2_loop<NARROW, false, true>(bd, st, jv, P, m0, m1)
@@ -730,7 +730,7 @@ XD_FN int w2_fast(WBand<2> &bd, WScalars &st, const JobView &jv, const Params &P
 // ranges clipped to the matrix; an anti-diagonal whose survivors left the
 // span's edge registers is finished here).  Returns false when the band
 // outgrew the window.
-template <int C, bool NARROW>
+template <int C, bool NARROW, bool FOLD>
 XD_FN bool wide_fast(WBand<C> &bd, WScalars &st, const JobView &jv, const Params &P) {
   constexpr int S = kWave * C;
   int32_t e0 = (st.d >> 1) & ~15;
@@ -761,9 +761,9 @@ XD_FN bool wide_fast(WBand<C> &bd, WScalars &st, const JobView &jv, const Params
     ws.spl1 = uniform(st.span_lo[1]); ws.sph1 = uniform(st.span_hi[1]);
     ws.dstop = uniform(2 * (e0 + 16)); ws.e0x2 = uniform(2 * e0);
     ws.mh = uniform(jv.m - st.h); ws.nh = uniform(jv.n + st.h);
-    ws.base = uniform(P.base); ws.ng = uniform(P.neg_gap); ws.smax = S - 2;
+    ws.base = uniform(P.dbase); ws.ng = uniform(P.neg_gap); ws.smax = S - 2;
     ws.rlo = 0; ws.rhi = 0; ws.lf = 0; ws.ll = 0; ws.mx = kNeg;
-    const int32_t rc = WLoop<C>::run(bd.E, bd.O, bd.SE, bd.SO, ws);
+    const int32_t rc = WLoop<C, FOLD>::run(bd.E, bd.O, bd.SE, bd.SO, ws);
     st.d = uniform(ws.d); st.lo = uniform(ws.lo); st.hi = uniform(ws.hi);
     st.bw = uniform(ws.bw); st.thr = uniform(ws.thr);
     st.cells_blk = (uint32_t)uniform(ws.cells);
@@ -792,7 +792,7 @@ XD_FN bool wide_fast(WBand<C> &bd, WScalars &st, const JobView &jv, const Params
 // save when there is one.  FAST selects the assembly: the hand-scheduled
 // loop for two registers, the generated chain with built-in edge clipping
 // for more (narrow score fields only; else FAST changes nothing).
-template <int C, bool NARROW, bool FAST = false>
+template <int C, bool NARROW, bool FAST = false, bool FOLD = false>
 XD_FN JobOut extend_job_wide(const Job &job, const Params &P, int32_t j, uint32_t *stage) {
   constexpr int S = kWave * C;
   JobOut out;
@@ -842,7 +842,7 @@ XD_FN JobOut extend_job_wide(const Job &job, const Params &P, int32_t j, uint32_
   bool fast_loop = false;
   if constexpr (FAST && NARROW && C >= 4) fast_loop = P.unit_match != 0;
   if constexpr (FAST && NARROW && C >= 4) {
-    if (fast_loop) ok = wide_fast<C, NARROW>(bd, st, jv, P);
+    if (fast_loop) ok = wide_fast<C, NARROW, FOLD>(bd, st, jv, P);
   }
   for (; !fast_loop;) {
     if constexpr (FAST && C == 2) {
