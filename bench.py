@@ -154,13 +154,12 @@ def cpu_all_cores(workload: str, n_total: int, n_sample: int, gpu_results=None) 
     pairs when the workload runs out); GCUPS = all cells / the slowest shard's
     time.  When the shards cover pairs of the timed GPU run, every integer
     result field of those pairs is compared with the GPU's."""
-    from multiprocessing import get_context
     procs = max(1, min(16, host_cpu()["usable_cpus"]))
     per = max(1, min(n_sample, n_total // procs))
     stride = max(1, n_total // (per * procs))
     jobs = [(workload, n_total, p, stride * procs, per) for p in range(procs)]
-    with get_context("fork").Pool(procs) as pool:
-        out = pool.map(_oracle_shard, jobs)
+    from paper_2002_05200_amd import synth
+    out = synth.pool_map(_oracle_shard, jobs, procs)
     cells = sum(o[0] for o in out)
     slowest = max(o[1] for o in out)
     rec = {"value": round(cells / slowest / 1e9, 4), "unit": "GCUPS", "cores": procs,
@@ -186,12 +185,10 @@ def serving_leg(n_distinct: int, n_requests: int, load: float, slots: int, max_b
     scheduler observed (same steady clock).  `sweep` repeats the open-loop run
     at other loads with sweep_requests requests each."""
     import threading
-    from multiprocessing import get_context
     from paper_2002_05200_amd import synth, xdrop
     t0 = time.time()
     if workers > 1:
-        with get_context("fork").Pool(workers) as pool:
-            reqs = pool.map(synth.make_request, range(n_distinct), chunksize=8)
+        reqs = synth.pool_map(synth.make_request, range(n_distinct), workers, chunksize=8)
     else:
         reqs = [synth.make_request(r) for r in range(n_distinct)]
     packed = [xdrop.PackedRequest(bt) for bt in reqs]

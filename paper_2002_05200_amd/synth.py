@@ -276,12 +276,27 @@ def make_batch(workload: str, n: Optional[int] = None, start: int = 0,
                           [p[3] for p in ps], [p[4] for p in ps], name=workload)
     if workers <= 1 or n < 256:
         return _chunk((workload, start, start + n))
-    import multiprocessing as mp
     step = max(64, (n + workers * 8 - 1) // (workers * 8))
     jobs = [(workload, s, min(s + step, start + n)) for s in range(start, start + n, step)]
-    with mp.get_context("fork").Pool(workers) as pool:
-        parts = pool.map(_chunk, jobs)
-    return concat(parts, name=workload)
+    return concat(pool_map(_chunk, jobs, workers), name=workload)
+
+
+def pool_map(fn, jobs, workers: int, chunksize: int = 1) -> list:
+    """``fn`` over ``jobs`` in a pool of ``workers`` forked processes.  The
+    pool is closed and joined, so the workers leave on their own: a pool
+    left by ``with`` terminates them with SIGTERM, which a profiler's signal
+    handler preloaded into every process (rocprofv3) may not return from."""
+    import multiprocessing as mp
+    pool = mp.get_context("fork").Pool(workers)
+    try:
+        out = pool.map(fn, jobs, chunksize=chunksize)
+        pool.close()
+    except BaseException:
+        pool.terminate()
+        raise
+    finally:
+        pool.join()
+    return out
 
 
 # ---------------------------------------------------------------------------

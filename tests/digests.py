@@ -76,9 +76,7 @@ def generate(workload: str, workers: int = 1):
     n = synth.WORKLOADS[workload].n_pairs
     args = [(workload, lo, hi) for lo, hi in chunks(n, CHUNK[workload])]
     if workers > 1:
-        from multiprocessing import get_context
-        with get_context("fork").Pool(workers) as pool:
-            got = pool.map(_generate_chunk, args, chunksize=1)
+        got = synth.pool_map(_generate_chunk, args, workers)
     else:
         got = [_generate_chunk(a) for a in args]
     got.sort(key=lambda g: g[0])
