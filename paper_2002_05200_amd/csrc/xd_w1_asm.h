@@ -9,7 +9,6 @@
 //
 // Common path of one anti-diagonal (10 VALU, 6-7 SALU; the 32 anti-diagonals
 // of a score-word block are unrolled, so field offsets are immediates):
-//   v_addc_co_u32  cnt, 0, cnt, carry=range          cells of this range, per lane
 //   v_mov_b32_dpp  t, prev  wave_shr:1 / wave_shl:1  neighbour diagonal (d-1)
 //   v_bfe_u32      u, score_word, 2q, 2              match field
 //   v_add3_u32     cur, cur, base, u                 diagonal term (d-2); a VOP2
@@ -25,6 +24,9 @@
 //   v_cmp_lt_i32   vcc, bw, cur                      did best improve?
 //   v_add / v_add  thr, bw += -gap                   thresholds of d+1
 //   s_add / s_sub / s_bfm                            trim: next range mask
+//   v_add_u32      cnt, width, cnt                   cells: the next range's width
+//                                                    (the s_bfm width, an SGPR)
+//                                                    into one VGPR, every lane alike
 // The issue slots per anti-diagonal matter less than its dependent chain:
 // with one job per wavefront a SIMD runs only a few wavefronts, so the
 // kernel is built for the eight resident wavefronts per SIMD that its
@@ -166,7 +168,6 @@ XD_FN Win make_win(const AsmView &v, vint off) {
 // .Ld (nothing survived), .Li (best improved; returns to .Lr, or past the drift
 // to .Lq).
 #define XD_CORE(TAG, DIAG, CUR, PRV, SW, SHIFT, P, EDGE)                          \
-  "v_addc_co_u32_e64 %[cnt], vcc, 0, %[cnt], %[range]\n\t"                        \
   "v_mov_b32_dpp %[t], %[" PRV "] " SHIFT " row_mask:0xf bank_mask:0xf\n\t"        \
   DIAG(CUR, SW, P)                                                                \
   "v_max3_i32 %[" CUR "], %[" CUR "], %[" PRV "], %[t]\n\t"                        \
@@ -191,7 +192,8 @@ XD_FN Win make_win(const AsmView &v, vint off) {
   "s_add_i32 %[tmp], %[a], %[f]\n\t"                                              \
   "s_sub_i32 %[tmp], 65, %[tmp]\n\t"                                              \
   "s_add_i32 %[a], %[a], -1\n\t"                                                  \
-  "s_bfm_b64 %[range], %[tmp], %[a]\n"
+  "s_bfm_b64 %[range], %[tmp], %[a]\n\t"                                           \
+  "v_add_u32 %[cnt], %[tmp], %[cnt]\n"
 // Odd anti-diagonal 2(e0 + K) + 1: the next (even) range is [a, 64 - f].  On
 // odd K the step first leaves for a recentre (.Lc) when a survivor sits in
 // lanes 0-1 or 61-63.  Survivors in lanes [2, 60] there keep the ranges of
@@ -203,7 +205,8 @@ XD_FN Win make_win(const AsmView &v, vint off) {
 #define XD_ODD_RANGE                                                              \
   "s_add_i32 %[tmp], %[a], %[f]\n\t"                                              \
   "s_sub_i32 %[tmp], 65, %[tmp]\n\t"                                              \
-  "s_bfm_b64 %[range], %[tmp], %[a]\n"
+  "s_bfm_b64 %[range], %[tmp], %[a]\n\t"                                           \
+  "v_add_u32 %[cnt], %[tmp], %[cnt]\n"
 #define XD_ODD(K, P, DIAG)                                                        \
   ".Lo" K "_%=:\n\t"                                                               \
   XD_CORE("o" K, DIAG, "O", "E", "SO", "wave_shl:1", P, "")                       \
@@ -317,12 +320,17 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
   // the window stays inside the matrix for blocks ending at or before e_lim
   int32_t e_lim = jv.m - (kWave - 1) - st.h;
   if (st.h + jv.n < e_lim) e_lim = st.h + jv.n;
-  const int32_t lim2 = 2 * (e_lim - 16);
+  // at most 2^24 anti-diagonals per call: the cell count stays below 2^32
+  if (e_lim > e0 + (1 << 23)) e_lim = e0 + (1 << 23);
+  const int32_t lim2 = uniform(2 * (e_lim - 16));
   int32_t status = 0;
   int32_t pos = 2 * (st.e - e0);
   int32_t a = 0, f = 0, tmp = 0, inc = 0;
   int32_t bs = 0, bpos = -1;   // lane and anti-diagonal of the last improvement
   vint bl = splat(-1);          // the same, per lane, in the unit form (none: -1)
+  // cells: each range's width (its s_bfm width) added when it is computed, the
+  // entry range's here; the same in every lane
+  int32_t cntv = __builtin_popcountll(st.range);
   uint64_t live = 0;
   const uint64_t edge = 0xE000000000000003ull;   // lanes 0, 1, 61, 62, 63
   const int32_t k55 = 0x55555555;
@@ -393,7 +401,7 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
       "s_mov_b32 %[status], 3\n"                                                      \
       ".Lexit_%=:\n\t"                                                                 \
       "s_waitcnt vmcnt(0)\n"                                                          \
-      : [E] "+v"(bd.E[0].x), [O] "+v"(bd.O[0].x), [cnt] "+v"(cnt.x), [bw] "+v"(bw),   \
+      : [E] "+v"(bd.E[0].x), [O] "+v"(bd.O[0].x), [cnt] "+v"(cntv), [bw] "+v"(bw),   \
         [SE] "+v"(bd.SE[0].x), [SO] "+v"(bd.SO[0].x),                                 \
         [lo0] "+v"(w0.lo.x), [hi0] "+v"(w0.hi.x), [nx0] "+v"(w0.nx.x), [idx0] "+v"(w0.idx.x), \
         [lo2] "+v"(w2.lo.x), [hi2] "+v"(w2.hi.x), [nx2] "+v"(w2.nx.x), [idx2] "+v"(w2.idx.x), \
@@ -441,6 +449,10 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
   // the anti-diagonal the loop stopped at: d = e0x2 + pos + par; W-form
   // thresholds satisfy bw = best + d |gap| there, which gives best
   const int32_t d_now = e0x2 + pos + par;
+  // a leave at a block boundary has computed, and counted, the range of an
+  // anti-diagonal the C steps will compute
+  st.cells += (uint32_t)uniform(cntv) -
+              (status == kStepLeave ? (uint64_t)__builtin_popcountll(st.range) : 0ull);
   st.bw = uniform(bw);
   st.thr = uniform(thrv);
   st.best = st.bw - d_now * P.neg_gap;
