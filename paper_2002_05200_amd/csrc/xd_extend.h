@@ -299,7 +299,7 @@ XD_FN void ensure_words_w1(Band<1> &bd, const W1 &st, int32_t e0, const JobView 
 // Runner of extend_job_w1 built from the C steps above.
 struct RunC {
   template <bool NARROW, bool CLIP>
-  XD_MEMBER static int run(Band<1> &bd, W1 &st, vint & /*cnt*/, int32_t e0, int32_t e_end,
+  XD_MEMBER static int run(Band<1> &bd, W1 &st, int32_t e0, int32_t e_end,
                            const JobView &jv, const Params &P, int32_t &words_e0,
                            int32_t &words_h) {
     ensure_words_w1<NARROW>(bd, st, e0, jv, P, words_e0, words_h);
@@ -352,16 +352,15 @@ XD_FN JobOut extend_job_w1(const Job &job, const Params &P, int32_t j) {
   st.cells_blk = 0;
   st.cells = 0;
 
-  vint cnt = splat(0);            // cells counted per lane by the assembly loop
   int32_t words_e0 = -1, words_h = 0;
   for (;;) {
     const int32_t e0 = st.e & ~15;
     const int32_t e_end = e0 + 16;
     // the window stays inside the matrix up to anti-diagonal 2 e_end
     const bool inside = (kWave - 1 + e_end + st.h <= jv.m) && (st.h >= e_end - jv.n);
-    const int rc = inside ? Runner::template run<NARROW, false>(bd, st, cnt, e0, e_end, jv, P,
+    const int rc = inside ? Runner::template run<NARROW, false>(bd, st, e0, e_end, jv, P,
                                                                 words_e0, words_h)
-                          : Runner::template run<NARROW, true>(bd, st, cnt, e0, e_end, jv, P,
+                          : Runner::template run<NARROW, true>(bd, st, e0, e_end, jv, P,
                                                                words_e0, words_h);
     st.cells += st.cells_blk;
     st.cells_blk = 0;
@@ -371,7 +370,7 @@ XD_FN JobOut extend_job_w1(const Job &job, const Params &P, int32_t j) {
       const int width = st.hi - st.lo + 1;
       if (width > kWave - 2) {   // the next tier resumes from here
         int32_t *sv = save_reserve(P, j, kWave);
-        const uint64_t cells = st.cells + lane_sum(cnt);
+        const uint64_t cells = st.cells;
         if (sv) {
           save_scalars(sv, 2 * st.e + st.par, st.lo, st.hi, st.h, st.best, st.bi, st.bj, st.bw,
                        st.thr, 1, cells);
@@ -395,7 +394,7 @@ XD_FN JobOut extend_job_w1(const Job &job, const Params &P, int32_t j) {
   out.best = st.best;
   out.bi = st.bi;
   out.bj = st.bj;
-  out.cells = st.cells + lane_sum(cnt);
+  out.cells = st.cells;
   return out;
 }
 

@@ -304,7 +304,7 @@ enum : int { kStepLeave = 3 };
 constexpr uint64_t kAsmEntryLanes = ((1ull << 59) - 1ull) << 2;
 
 template <bool NARROW, bool UNIT, bool FWD, bool D2, bool FOLD = false>
-XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &jv,
+XD_FN int run_w1_asm(Band<1> &bd, W1 &st, int32_t e0, const JobView &jv,
                      const AsmView &av_a, const AsmView &av_b, const Params &P,
                      int32_t &words_e0) {
   // windows of block e0: A (the parity whose bases start lower in memory:
@@ -484,7 +484,7 @@ XD_FN int run_w1_asm(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, const JobView &
 // (with matrix clipping) near the ends of the reads.
 struct RunAsm {
   template <bool NARROW, bool CLIP>
-  XD_MEMBER static int run(Band<1> &bd, W1 &st, vint &cnt, int32_t e0, int32_t e_end,
+  XD_MEMBER static int run(Band<1> &bd, W1 &st, int32_t e0, int32_t e_end,
                            const JobView &jv, const Params &P, int32_t &words_e0,
                            int32_t &words_h) {
     if constexpr (CLIP) {
@@ -502,22 +502,22 @@ struct RunAsm {
       words_h = st.h;
       if (NARROW && P.fold) {   // +1/-1/-1
         return jv.dir > 0
-                   ? run_w1_asm<NARROW, true, true, true, true>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0)
-                   : run_w1_asm<NARROW, true, false, true, true>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0);
+                   ? run_w1_asm<NARROW, true, true, true, true>(bd, st, e0, jv, av_a, av_b, P, words_e0)
+                   : run_w1_asm<NARROW, true, false, true, true>(bd, st, e0, jv, av_a, av_b, P, words_e0);
       }
       if (NARROW && P.unit_match && P.delta == 2) {
         return jv.dir > 0
-                   ? run_w1_asm<NARROW, true, true, true>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0)
-                   : run_w1_asm<NARROW, true, false, true>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0);
+                   ? run_w1_asm<NARROW, true, true, true>(bd, st, e0, jv, av_a, av_b, P, words_e0)
+                   : run_w1_asm<NARROW, true, false, true>(bd, st, e0, jv, av_a, av_b, P, words_e0);
       }
       if (jv.dir > 0) {
         return P.unit_match
-                   ? run_w1_asm<NARROW, true, true, false>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0)
-                   : run_w1_asm<NARROW, false, true, false>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0);
+                   ? run_w1_asm<NARROW, true, true, false>(bd, st, e0, jv, av_a, av_b, P, words_e0)
+                   : run_w1_asm<NARROW, false, true, false>(bd, st, e0, jv, av_a, av_b, P, words_e0);
       }
       return P.unit_match
-                 ? run_w1_asm<NARROW, true, false, false>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0)
-                 : run_w1_asm<NARROW, false, false, false>(bd, st, cnt, e0, jv, av_a, av_b, P, words_e0);
+                 ? run_w1_asm<NARROW, true, false, false>(bd, st, e0, jv, av_a, av_b, P, words_e0)
+                 : run_w1_asm<NARROW, false, false, false>(bd, st, e0, jv, av_a, av_b, P, words_e0);
     }
   }
 };
