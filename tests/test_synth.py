@@ -60,3 +60,24 @@ def test_serving_requests():
 def test_encode_decode_roundtrip():
     s = "ACGTTGCA"
     assert synth.decode(synth.encode(s)) == s.encode()
+
+
+def _worker_pid(_):
+    import os
+    return os.getpid()
+
+
+def test_pool_map_matches_a_serial_map_and_lets_workers_exit():
+    # the same results, in order, as a plain map
+    assert synth.pool_map(abs, [-3, 4, -5, 6, -7], 2) == [3, 4, 5, 6, 7]
+    # the workers are joined before it returns: none of them is still alive
+    import os
+    pids = set(synth.pool_map(_worker_pid, range(8), 2))
+    assert os.getpid() not in pids
+    for pid in pids:
+        try:
+            os.kill(pid, 0)
+            alive = True
+        except ProcessLookupError:
+            alive = False
+        assert not alive
